@@ -1,0 +1,208 @@
+/*
+ * fch.h -- C ABI of the MI355X (gfx950) engine for the functionalized
+ * Cahn-Hilliard (FCH) gradient flow with Fourier pseudo-spectral space
+ * discretization and variable-step BDF2 time stepping.
+ *
+ * Model (paper Sec. 2): energy eq. Functional with the regularized well W_q
+ * of eq. e:Wq-def; H^{-1} gradient flow u_t = Lap mu, mu = dE/du (eqs. sFCH,
+ * FCH) on the periodic square [0, L)^2, N x N collocation points.
+ *
+ * Conventions shared by every call
+ *  - Precision: IEEE FP64 throughout.
+ *  - Memory: every array argument is a DEVICE pointer (HIP global memory)
+ *    owned by the caller; scalars marked "host" are host memory.  The plan
+ *    owns its twiddle table and a small control block, nothing else.
+ *  - Physical field: double u[y*N + x], y = row index (coordinate y*h),
+ *    x = column index, h = L/N.
+ *  - Spectral field ("half spectrum", kx-major): fch_c128 uh[kx*N + ky],
+ *    kx = 0..N/2 (N/2+1 columns), ky = 0..N-1; wavenumbers 2*pi*kx/L and
+ *    2*pi*(ky <= N/2 ? ky : ky-N)/L.  This is the transpose of the
+ *    numpy.fft.rfft2 layout.  Forward transforms are unnormalized; the inverse
+ *    carries 1/N^2 and returns the real part of the inverse DFT of the
+ *    Hermitian extension (imaginary parts at kx = 0 and kx = N/2 are ignored).
+ *  - The state of every time stepper is the half spectrum; physical fields
+ *    appear only through fch_forward / fch_inverse.
+ *  - Streams: all work is enqueued on the plan's stream (fch_plan_set_stream)
+ *    and calls return without synchronizing, except where an output is a host
+ *    scalar (then the call waits for that value).
+ *  - Aliasing: outputs must not alias inputs, except uh_np1 == uh_nm1 where
+ *    stated (every column is read before it is written).
+ *  - Errors: status codes only; nothing aborts.  Invalid arguments leave all
+ *    outputs untouched.  A plan is bound to one device and is not
+ *    thread-safe; calls on one plan must not overlap.
+ */
+#ifndef FCH_H
+#define FCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fch_plan_s* fch_plan_t;
+typedef struct { double re, im; } fch_c128;
+
+typedef enum {
+    FCH_OK = 0,
+    FCH_E_INVALID = -1,     /* bad argument (size, null pointer, E1 + D0 <= 0, ...) */
+    FCH_E_UNSUPPORTED = -2, /* N outside the supported powers of two 16..2048       */
+    FCH_E_HIP = -3,         /* a HIP runtime call failed                            */
+    FCH_E_NOMEM = -4,       /* workspace missing or too small                        */
+    FCH_E_NOCONV = -5,      /* PSD reached max_iter; last iterate and stats written  */
+    FCH_E_NONFINITE = -6    /* a reduction saw a NaN or Inf                          */
+} fch_status;
+
+/* Model parameters (paper Table t:Benchmark notation). */
+typedef struct {
+    int32_t N;                 /* grid points per side: power of two, 16..2048      */
+    double  L;                 /* side of the periodic square, > 0                  */
+    double  eps;               /* interface width epsilon, > 0                      */
+    double  eta1, eta2;        /* functionalization parameters as given             */
+    int32_t p;                 /* effective eta_i = eps^p * eta_i (p = 1 gives the
+                                  paper's eta_1 = 1.45 eps, eta_2 = 3 eps form)     */
+    double  q;                 /* well regularization q >= 0 (eq. e:Wq-def)         */
+    double  gamma_w;           /* well asymmetry gamma (0.3)                        */
+    double  b_minus, b_plus;   /* well minima (-1, +1)                              */
+    double  beta1, beta2;      /* SAV stabilization of L_0 (eq. e:SAV-L0), (2, 1)   */
+    double  zeta, D0;          /* SAV splitting constant (eq. 4.1) and energy shift
+                                  D_0 > -min E_1 (Sec. 3.5); see fch_sav_constants */
+} fch_params;
+
+/* Default SAV constants: zeta = ceil(10 max(0, -min_u W_q''))/10 and
+ * D0 = |Omega| (max(0, -min_u [W_q'^2/2 - eta2 W_q]) + 1), minima over a fine
+ * sample of u in [-3, 3].  Host-only; writes *zeta and *D0. */
+fch_status fch_sav_constants(const fch_params* prm, double* zeta, double* D0);
+
+/* alpha_m = W_q''(b_-) (Sec. 3.3), host-only. */
+double fch_alpha_m(const fch_params* prm);
+
+/* ---- plan ---------------------------------------------------------------- */
+/* Creates a plan on the current HIP device.  Allocates the twiddle table and a
+ * control block (device) and a small pinned host block.  *out is set on
+ * success only. */
+fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out);
+fch_status fch_plan_destroy(fch_plan_t plan);
+/* stream: a hipStream_t (NULL = the null stream). */
+fch_status fch_plan_set_stream(fch_plan_t plan, void* stream);
+/* Device workspace the caller must provide before any compute call
+ * (intermediate half spectra, reduction partials).  No compute call allocates. */
+size_t     fch_plan_workspace_bytes(fch_plan_t plan);
+fch_status fch_plan_set_workspace(fch_plan_t plan, void* dptr, size_t bytes);
+/* Launch configuration: rows per row-pass workgroup (R), FFT elements per
+ * thread in the row pass (row_E) and the column pass (col_E).  variant < 0
+ * selects the built-in default for N.  Returns FCH_E_UNSUPPORTED for a
+ * configuration that was not compiled. */
+typedef struct { int32_t row_R, row_E, col_E; } fch_launch_cfg;
+fch_status fch_plan_set_config(fch_plan_t plan, const fch_launch_cfg* cfg);
+fch_status fch_plan_get_config(fch_plan_t plan, fch_launch_cfg* cfg);
+/* Number of compiled configurations for a grid size, and the i-th of them. */
+int32_t    fch_config_count(int32_t N);
+fch_status fch_config_get(int32_t N, int32_t i, fch_launch_cfg* cfg);
+
+typedef struct {
+    int64_t fft_calls;     /* 2D real transforms (forward or inverse) of one N^2 field */
+    int64_t launches;      /* kernels enqueued                                        */
+    int64_t psd_iters;     /* PSD iterations performed                                */
+    int64_t steps, rejected;
+} fch_stats;
+fch_status fch_plan_stats(fch_plan_t plan, fch_stats* out);   /* host out */
+fch_status fch_plan_reset_stats(fch_plan_t plan);
+
+/* ---- transforms (pseudo-spectral discretization, Sec. 2.3 / Sec. 3) ------ */
+/* uh = DFT(u), unnormalized.  u: N*N doubles; uh: (N/2+1)*N complex. */
+fch_status fch_forward(fch_plan_t plan, const double* u, fch_c128* uh);
+/* u = real part of IDFT(Hermitian extension of uh) / N^2. */
+fch_status fch_inverse(fch_plan_t plan, const fch_c128* uh, double* u);
+
+/* ---- chemical potential (eq. FCH) ---------------------------------------- */
+/* muh = half spectrum of mu(u) = (eps^2 Lap - W''(u)) omega + eps^2 eta1 Lap u
+ * - eta2 W'(u), omega = eps^2 Lap u - W'(u); Laplacians as -|k|^2, products at
+ * collocation points (no dealiasing).  energy (nullable, host out): the
+ * discrete energy of eq. Functional, h^2 sum [omega^2/2 - eta2 W]
+ * - (eps^2 eta1/2) ||grad u||^2 with the gradient term by Parseval. */
+fch_status fch_chem_potential(fch_plan_t plan, const fch_c128* uh, fch_c128* muh,
+                              double* energy);
+
+/* ---- BDF2 steps (eqs. BDF2Coef, BDF2-general) ---------------------------- */
+/* Every step solves a u^{n+1} + b u^n + c u^{n-1} = (scheme's Lap mu) with
+ * a, b, c from (k_np1, k_n).  k_n <= 0 selects the first-order startup step
+ * (a = 1/k, b = -1/k, c = 0, u* = u^n); uh_nm1 is then not read and may be
+ * NULL.  uh_np1 may alias uh_nm1. */
+
+/* BDF2-IMEX (eqs. e:IMEX-op, IMEX, Richardson, IMEX-eq):
+ * (a + |k|^2 L_IMEX) u^{n+1} = -b u^n - c u^{n-1} - |k|^2 (mu(u*) - L_IMEX u*),
+ * L_IMEX = (eps^2 |k|^2 + alpha_m)^2, u* = u^n + (k_np1/k_n)(u^n - u^{n-1}). */
+fch_status fch_step_imex(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                         double k_np1, double k_n, fch_c128* uh_np1);
+
+/* BDF2-SAV (eqs. 4.7, 4.8) with L_0, L_1 of eqs. e:SAV-L0, e:SAV-L1:
+ * u^{n+1} = p + r^{n+1} q, (a + |k|^2 L_0) p = -b u^n - c u^{n-1} - |k|^2 L_1 u*,
+ * (a + |k|^2 L_0) q = -|k|^2 X, X = V(u*)/sqrt(E_1(u*) + D_0), V = mu - L_SAV u,
+ * r^{n+1} = (-b r^n - c r^{n-1} + (X, a p + b u^n + c u^{n-1})/2) / (a - a (X, q)/2).
+ * r_n, r_nm1 host scalars; *r_np1 host out.  FCH_E_INVALID if E_1(u*) + D_0 <= 0. */
+fch_status fch_step_sav(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                        double r_n, double r_nm1, double k_np1, double k_n,
+                        fch_c128* uh_np1, double* r_np1);
+/* SAV scalar r = sqrt(E_1(u) + D_0) of a state (host out). */
+fch_status fch_sav_r(fch_plan_t plan, const fch_c128* uh, double* r);
+
+/* BDF2-PSD (eq. residual, Sec. 3.3): iterate d = -L_PSD^{-1} R(u_s),
+ * u_{s+1} = u_s + lambda d with R = Pi_0 mu(u) - Lap^{-1}(a u + b u^n + c u^{n-1}),
+ * L_PSD = eps^4 Lap^2 - 2 alpha eps^2 Lap + alpha^2 - a Lap^{-1}; stop once
+ * ||d_s|| / ||u_{s+1}|| < tol.  guess (nullable): initial iterate, projected to
+ * the mean of u^n; NULL selects the extrapolation of eq. recurrence.
+ * lambda <= 0 selects Table SearchSize (linear in k; q in {0, 0.2, 0.5}).
+ * fixed_iters > 0 runs exactly that many iterations (tol ignored).
+ * Returns FCH_E_NOCONV after max_iter iterations (uh_np1 holds the last
+ * iterate).  stats (nullable, host out). */
+typedef struct { double tol; int32_t max_iter; double lambda; int32_t fixed_iters; } fch_psd_opts;
+typedef struct { int32_t iters; int64_t fft_calls; double last_ratio; } fch_psd_stats;
+fch_status fch_step_psd(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                        double k_np1, double k_n, const fch_c128* guess,
+                        const fch_psd_opts* opts, fch_c128* uh_np1, fch_psd_stats* stats);
+
+/* ---- adaptive time step (Sec. 3.2, Steps 2-4) ---------------------------- */
+/* F_trial = F(u~) = Lap mu(u~) (device out, the next step's cache);
+ * u_p = u^n + (k~/6)[(3+2g)/(1+g) F(u~) + (3+g) F^n - g^2/(1+g) F^{n-1}], g = k~/k_n;
+ * e = ||u~ - u_p|| / ||u_p|| (Parseval); accept = (e <= sigma_tol or k~ <= k_min);
+ * k_next = max(k_min, min(rho_s (sigma_tol/e)^{1/3} k~, k_max, cap k~)), cap <= 0
+ * disables the zero-stability cap.  accept, k_next, err: host outs (nullable). */
+typedef struct { double sigma_tol, k_min, k_max, rho_s, cap; } fch_adapt_opts;
+fch_status fch_adapt_dt(fch_plan_t plan, const fch_c128* uh_trial, const fch_c128* uh_n,
+                        const fch_c128* F_n, const fch_c128* F_nm1, double k_trial, double k_n,
+                        const fch_adapt_opts* opts, fch_c128* F_trial,
+                        int32_t* accept, double* k_next, double* err);
+/* F(u) = Lap mu(u) as a half spectrum (device out). */
+fch_status fch_rhs(fch_plan_t plan, const fch_c128* uh, fch_c128* Fh);
+
+/* ---- trajectories -------------------------------------------------------- */
+/* Runs a scheme on the device state.  On entry uh_n holds u^n and uh_nm1
+ * u^{n-1} (ignored when opts->startup = 1: a first-order step of size
+ * k_first is taken from uh_n).  On return uh_n holds the last accepted state
+ * and uh_nm1 the one before it.  Fixed-step runs (adaptive = 0) take nsteps
+ * steps of size k (the startup step counts as one); adaptive runs follow
+ * Sec. 3.2 until t_end or nsteps accepted steps.  *rs (SAV only, host in/out):
+ * r^n, r^{n-1}.  info (nullable, host out). */
+typedef enum { FCH_IMEX = 0, FCH_SAV = 1, FCH_PSD = 2 } fch_scheme;
+typedef struct {
+    int32_t scheme, adaptive, startup;
+    int64_t nsteps;
+    double  k, k_prev, k_first, t_end;
+    fch_adapt_opts adapt;
+    fch_psd_opts psd;
+} fch_run_opts;
+typedef struct {
+    int64_t accepted, rejected, psd_iters, fft_calls;
+    double  t, k_last, k_next;
+} fch_run_info;
+fch_status fch_run(fch_plan_t plan, const fch_run_opts* opts, fch_c128* uh_n, fch_c128* uh_nm1,
+                   double* rs, fch_run_info* info);
+
+const char* fch_status_string(fch_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O3, OpenMP over independent lines)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+        cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared",
                "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)

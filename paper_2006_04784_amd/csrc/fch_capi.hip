@@ -1,0 +1,913 @@
+// fch_capi.hip -- host side of the C ABI declared in include/fch.h: plan and
+// workspace management, argument validation, and the launch sequences of
+// each call (which kernels run, in which order, on which buffers).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <utility>
+#include <cstring>
+#include <new>
+
+#include "fch.h"
+#include "fch_kernels.hpp"
+
+using fch::cd;
+using fch::ColArgs;
+using fch::FinArgs;
+using fch::RowArgs;
+using fch::StepCtl;
+
+struct fch_plan_s {
+  fch_params prm;
+  fch::Consts c;
+  int N, H;
+  const fch::VTable* vt;
+  hipStream_t stream;
+  int device;
+  cd* tw;
+  StepCtl* ctl;
+  StepCtl* hctl;  // pinned mirror for read-back
+  char* ws;
+  size_t ws_bytes;
+  cd *P0, *P1, *aux, *st, *Fc[3];
+  double *rpart, *cpart;
+  fch_stats stats;
+  int psd_hint;
+};
+
+namespace {
+
+#define HIPCHK(x)                                 \
+  do {                                            \
+    if ((x) != hipSuccess) return FCH_E_HIP;      \
+  } while (0)
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// host evaluation of W_q and its derivatives (eq. e:Wq-def), used for the
+// plan constants alpha_m and the default SAV constants
+void well_host(const fch_params& p, double u, double* W, double* W1, double* W2) {
+  const double dm = u - p.b_minus, dp = u - p.b_plus;
+  double A = 0.5 * dm * dm, A1 = dm, A2 = 1.0;
+  if (p.q != 0.0) {
+    const double z = dm / p.eps;
+    const double e = std::exp(-std::fabs(z));
+    const double den = 1.0 / (1.0 + e * e);
+    const double sech = 2.0 * e * den;
+    const double th = std::copysign((1.0 - e * e) * den, z);
+    A += p.q * p.eps * (1.0 - sech);
+    A1 += p.q * sech * th;
+    A2 += (p.q / p.eps) * sech * (sech * sech - th * th);
+  }
+  const double g3 = p.gamma_w / 3.0;
+  const double B = 0.5 * dp * dp + g3 * (u - 0.5 * (3.0 * p.b_plus - p.b_minus));
+  const double B1 = dp + g3;
+  if (W) *W = A * B;
+  if (W1) *W1 = A1 * B + A * B1;
+  if (W2) *W2 = A2 * B + 2.0 * A1 * B1 + A;
+}
+
+double eff_eta(const fch_params& p, double eta) { return eta * std::pow(p.eps, p.p); }
+
+fch_status validate_params(const fch_params* p) {
+  if (!p) return FCH_E_INVALID;
+  if (!finite_pos(p->L) || !finite_pos(p->eps)) return FCH_E_INVALID;
+  if (!std::isfinite(p->eta1) || !std::isfinite(p->eta2) || !std::isfinite(p->q) || p->q < 0.0)
+    return FCH_E_INVALID;
+  if (!std::isfinite(p->gamma_w) || !std::isfinite(p->b_minus) || !std::isfinite(p->b_plus))
+    return FCH_E_INVALID;
+  if (!std::isfinite(p->beta1) || !std::isfinite(p->beta2) || !std::isfinite(p->zeta) ||
+      !std::isfinite(p->D0))
+    return FCH_E_INVALID;
+  if (!is_pow2(p->N) || p->N < 16) return p->N > 0 && p->N < 16 ? FCH_E_UNSUPPORTED : FCH_E_INVALID;
+  if (fch::vtable_count(p->N) == 0) return FCH_E_UNSUPPORTED;
+  return FCH_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t spec_bytes(int N) { return (size_t)(N / 2 + 1) * (size_t)N * sizeof(cd); }
+
+size_t workspace_layout(int N, fch_plan_s* p) {
+  const size_t S = align256(spec_bytes(N));
+  const size_t R = align256(sizeof(double) * 2 * (size_t)N);
+  const size_t C = align256(sizeof(double) * 2 * (size_t)(N / 2 + 1));
+  if (p) {
+    char* b = p->ws;
+    p->P0 = (cd*)b; b += S;
+    p->P1 = (cd*)b; b += S;
+    p->aux = (cd*)b; b += S;
+    p->st = (cd*)b; b += S;
+    for (int i = 0; i < 3; ++i) { p->Fc[i] = (cd*)b; b += S; }
+    p->rpart = (double*)b; b += R;
+    p->cpart = (double*)b; b += C;
+  }
+  return 7 * S + R + C;
+}
+
+StepCtl ctl_zero() {
+  StepCtl v;
+  std::memset(&v, 0, sizeof(v));
+  return v;
+}
+
+// eq. BDF2Coef; k_n <= 0 selects the first-order startup step (u* = u^n)
+void set_bdf2(StepCtl& v, double k_np1, double k_n) {
+  v.k_np1 = k_np1;
+  v.k_n = k_n;
+  if (k_n <= 0.0) {
+    v.a = 1.0 / k_np1;
+    v.b = -1.0 / k_np1;
+    v.c = 0.0;
+    v.gamma = 0.0;
+  } else {
+    v.a = 1.0 / k_np1 + 1.0 / (k_np1 + k_n);
+    v.b = -1.0 / k_np1 - 1.0 / k_n;
+    v.c = 1.0 / k_n - 1.0 / (k_np1 + k_n);
+    v.gamma = k_np1 / k_n;
+  }
+}
+
+// eq. Predictor: AM3 weights of F(u~), F^n, F^{n-1}
+void set_am3(StepCtl& v, double k_np1, double k_n) {
+  const double g = k_np1 / k_n;
+  v.w1 = k_np1 / 6.0 * (3.0 + 2.0 * g) / (1.0 + g);
+  v.w2 = k_np1 / 6.0 * (3.0 + g);
+  v.w3 = -k_np1 / 6.0 * g * g / (1.0 + g);
+}
+
+// Table SearchSize: lambda(q, k) linear in k between the printed columns,
+// constant outside; q must be one of the tabulated rows
+double lambda_table(double q, double k) {
+  static const double ks[10] = {1e-6, 1e-5, 5e-5, 1e-4, 5e-4, 1e-3, 5e-3, 0.01, 0.02, 0.03};
+  static const double qs[3] = {0.0, 0.2, 0.5};
+  static const double lam[3][10] = {
+      {1.0, 1.07, 1.11, 1.14, 1.24, 1.34, 1.60, 1.738, 1.804, 1.855},
+      {1.0, 1.04, 1.15, 1.28, 1.50, 1.70, 1.87, 1.92, 1.95, 1.97},
+      {1.0, 1.20, 1.32, 1.45, 1.72, 1.83, 1.965, 1.97, 1.985, 1.99}};
+  int row = -1;
+  for (int i = 0; i < 3; ++i)
+    if (std::fabs(q - qs[i]) < 1e-12) row = i;
+  if (row < 0) return -1.0;
+  if (k <= ks[0]) return lam[row][0];
+  if (k >= ks[9]) return lam[row][9];
+  int j = 0;
+  while (k > ks[j + 1]) ++j;
+  const double t = (k - ks[j]) / (ks[j + 1] - ks[j]);
+  return lam[row][j] + t * (lam[row][j + 1] - lam[row][j]);
+}
+
+RowArgs row_args(fch_plan_s* p) {
+  RowArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.c = p->c;
+  a.P0 = p->P0;
+  a.P1 = p->P1;
+  a.ctl = p->ctl;
+  a.tw = p->tw;
+  return a;
+}
+
+ColArgs col_args(fch_plan_s* p) {
+  ColArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.c = p->c;
+  a.P0 = p->P0;
+  a.P1 = p->P1;
+  a.ctl = p->ctl;
+  a.tw = p->tw;
+  return a;
+}
+
+fch_status need_ws(fch_plan_s* p) { return p->ws ? FCH_OK : FCH_E_NOMEM; }
+
+fch_status ctl_set(fch_plan_s* p, const StepCtl& v) {
+  HIPCHK(fch::launch_ctl_set(p->ctl, v, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+
+fch_status readback(fch_plan_s* p) {
+  HIPCHK(hipMemcpyAsync(p->hctl, p->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return FCH_OK;
+}
+
+fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
+  HIPCHK(p->vt->col(epi, pro, a, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+
+fch_status row_mu(fch_plan_s* p, double* partial) {
+  RowArgs a = row_args(p);
+  a.partial = partial;
+  HIPCHK(p->vt->row(fch::ROW_MU, a, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+
+fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
+  FinArgs f;
+  std::memset(&f, 0, sizeof(f));
+  f.c = p->c;
+  f.rpart = rows ? p->rpart : nullptr;
+  f.nrow = p->N / p->vt->row_R;
+  f.cpart = cols ? p->cpart : nullptr;
+  f.ncol = p->H;
+  f.ctl = p->ctl;
+  f.mode = mode;
+  HIPCHK(fch::launch_finalize(f, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+
+#define CHK(x)                         \
+  do {                                 \
+    fch_status s_ = (x);               \
+    if (s_ != FCH_OK) return s_;       \
+  } while (0)
+
+fch_status set_config(fch_plan_s* p, const fch::VTable* vt) {
+  p->vt = vt;
+  return FCH_OK;
+}
+
+// one chemical-potential evaluation of the field already column-inverted in
+// the pair buffer, ending in the given epilogue
+fch_status imex_attempt(fch_plan_s* p, const cd* un, const cd* um, double k_np1, double k_n,
+                        cd* out) {
+  StepCtl v = ctl_zero();
+  set_bdf2(v, k_np1, k_n);
+  CHK(ctl_set(p, v));
+  ColArgs a = col_args(p);
+  a.s0 = un;
+  a.s1 = um ? um : un;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+  CHK(row_mu(p, nullptr));
+  a.out = out;
+  CHK(col(p, fch::EPI_IMEX, fch::PRO_NONE, a));
+  p->stats.fft_calls += 4;
+  p->stats.steps += 1;
+  return FCH_OK;
+}
+
+fch_status status_from_ctl(fch_plan_s* p) {
+  if (p->hctl->nonfinite) return FCH_E_NONFINITE;
+  if (p->hctl->invalid) return FCH_E_INVALID;
+  return FCH_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* fch_status_string(fch_status s) {
+  switch (s) {
+    case FCH_OK: return "ok";
+    case FCH_E_INVALID: return "invalid argument";
+    case FCH_E_UNSUPPORTED: return "unsupported grid size or configuration";
+    case FCH_E_HIP: return "HIP runtime error";
+    case FCH_E_NOMEM: return "workspace missing or too small";
+    case FCH_E_NOCONV: return "PSD did not converge within max_iter";
+    case FCH_E_NONFINITE: return "non-finite value in the state";
+  }
+  return "unknown status";
+}
+
+double fch_alpha_m(const fch_params* prm) {
+  if (!prm) return NAN;
+  double w2 = 0.0;
+  well_host(*prm, prm->b_minus, nullptr, nullptr, &w2);
+  return w2;
+}
+
+fch_status fch_sav_constants(const fch_params* prm, double* zeta, double* D0) {
+  if (!prm || !zeta || !D0 || !finite_pos(prm->L) || !finite_pos(prm->eps)) return FCH_E_INVALID;
+  const double eta2 = eff_eta(*prm, prm->eta2);
+  double min_w2 = INFINITY, min_g = INFINITY;
+  const int n = 60001;
+  for (int i = 0; i < n; ++i) {
+    const double u = -3.0 + 6.0 * i / (n - 1);
+    double W, W1, W2;
+    well_host(*prm, u, &W, &W1, &W2);
+    min_w2 = std::fmin(min_w2, W2);
+    min_g = std::fmin(min_g, 0.5 * W1 * W1 - eta2 * W);
+  }
+  *zeta = std::ceil(10.0 * std::fmax(0.0, -min_w2)) / 10.0;
+  *D0 = prm->L * prm->L * (std::fmax(0.0, -min_g) + 1.0);
+  return FCH_OK;
+}
+
+fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
+  if (!out) return FCH_E_INVALID;
+  CHK(validate_params(prm));
+  fch_plan_s* p = new (std::nothrow) fch_plan_s;
+  if (!p) return FCH_E_NOMEM;
+  std::memset(p, 0, sizeof(*p));
+  p->prm = *prm;
+  p->N = prm->N;
+  p->H = prm->N / 2 + 1;
+  p->vt = fch::vtable_get(prm->N, 0);
+  p->psd_hint = 4;
+  fch::Consts& c = p->c;
+  c.N = prm->N;
+  c.L = prm->L;
+  c.eps = prm->eps;
+  c.inv_eps = 1.0 / prm->eps;
+  c.eps2 = prm->eps * prm->eps;
+  c.eta1 = eff_eta(*prm, prm->eta1);
+  c.eta2 = eff_eta(*prm, prm->eta2);
+  c.q = prm->q;
+  c.gw3 = prm->gamma_w / 3.0;
+  c.bm = prm->b_minus;
+  c.bp = prm->b_plus;
+  c.bshift = 0.5 * (3.0 * prm->b_plus - prm->b_minus);
+  c.alpha = fch_alpha_m(prm);
+  c.beta1 = prm->beta1;
+  c.beta2 = prm->beta2;
+  c.zeta = prm->zeta;
+  c.D0 = prm->D0;
+  const double tk = 2.0 * M_PI / prm->L;
+  c.kscale = tk * tk;
+  c.invN2 = 1.0 / ((double)prm->N * (double)prm->N);
+  const double h = prm->L / prm->N;
+  c.h2 = h * h;
+  c.pars = prm->L * prm->L / ((double)prm->N * prm->N * (double)prm->N * prm->N);
+
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FCH_E_HIP; }
+  // twiddles exp(-2 pi i m / N), evaluated in extended precision
+  const int N = prm->N;
+  cd* htw = new (std::nothrow) cd[N];
+  if (!htw) { delete p; return FCH_E_NOMEM; }
+  for (int m = 0; m < N; ++m) {
+    const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / N;
+    htw[m].x = (double)cosl(ang);
+    htw[m].y = (double)-sinl(ang);
+  }
+  bool ok = hipMalloc((void**)&p->tw, sizeof(cd) * N) == hipSuccess &&
+            hipMalloc((void**)&p->ctl, sizeof(StepCtl)) == hipSuccess &&
+            hipHostMalloc((void**)&p->hctl, sizeof(StepCtl), hipHostMallocDefault) == hipSuccess &&
+            hipMemcpy(p->tw, htw, sizeof(cd) * N, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemset(p->ctl, 0, sizeof(StepCtl)) == hipSuccess;
+  delete[] htw;
+  if (!ok) {
+    fch_plan_destroy(p);
+    return FCH_E_HIP;
+  }
+  std::memset(p->hctl, 0, sizeof(StepCtl));
+  *out = p;
+  return FCH_OK;
+}
+
+fch_status fch_plan_destroy(fch_plan_t p) {
+  if (!p) return FCH_E_INVALID;
+  if (p->tw) (void)hipFree(p->tw);
+  if (p->ctl) (void)hipFree(p->ctl);
+  if (p->hctl) (void)hipHostFree(p->hctl);
+  delete p;
+  return FCH_OK;
+}
+
+fch_status fch_plan_set_stream(fch_plan_t p, void* stream) {
+  if (!p) return FCH_E_INVALID;
+  p->stream = (hipStream_t)stream;
+  return FCH_OK;
+}
+
+size_t fch_plan_workspace_bytes(fch_plan_t p) {
+  if (!p) return 0;
+  return workspace_layout(p->N, nullptr);
+}
+
+fch_status fch_plan_set_workspace(fch_plan_t p, void* dptr, size_t bytes) {
+  if (!p || !dptr) return FCH_E_INVALID;
+  if (((uintptr_t)dptr & 255) != 0) return FCH_E_INVALID;
+  if (bytes < workspace_layout(p->N, nullptr)) return FCH_E_NOMEM;
+  p->ws = (char*)dptr;
+  p->ws_bytes = bytes;
+  workspace_layout(p->N, p);
+  return FCH_OK;
+}
+
+int32_t fch_config_count(int32_t N) { return fch::vtable_count(N); }
+
+fch_status fch_config_get(int32_t N, int32_t i, fch_launch_cfg* cfg) {
+  const fch::VTable* vt = fch::vtable_get(N, i);
+  if (!vt || !cfg) return FCH_E_UNSUPPORTED;
+  cfg->row_R = vt->row_R;
+  cfg->row_E = vt->row_E;
+  cfg->col_E = vt->col_E;
+  return FCH_OK;
+}
+
+fch_status fch_plan_set_config(fch_plan_t p, const fch_launch_cfg* cfg) {
+  if (!p) return FCH_E_INVALID;
+  if (!cfg) return set_config(p, fch::vtable_get(p->N, 0));
+  for (int i = 0; i < fch::vtable_count(p->N); ++i) {
+    const fch::VTable* vt = fch::vtable_get(p->N, i);
+    if (vt->row_R == cfg->row_R && vt->row_E == cfg->row_E && vt->col_E == cfg->col_E)
+      return set_config(p, vt);
+  }
+  return FCH_E_UNSUPPORTED;
+}
+
+fch_status fch_plan_get_config(fch_plan_t p, fch_launch_cfg* cfg) {
+  if (!p || !cfg) return FCH_E_INVALID;
+  cfg->row_R = p->vt->row_R;
+  cfg->row_E = p->vt->row_E;
+  cfg->col_E = p->vt->col_E;
+  return FCH_OK;
+}
+
+fch_status fch_plan_stats(fch_plan_t p, fch_stats* out) {
+  if (!p || !out) return FCH_E_INVALID;
+  *out = p->stats;
+  return FCH_OK;
+}
+
+fch_status fch_plan_reset_stats(fch_plan_t p) {
+  if (!p) return FCH_E_INVALID;
+  std::memset(&p->stats, 0, sizeof(p->stats));
+  return FCH_OK;
+}
+
+// ---- transforms -----------------------------------------------------------
+fch_status fch_forward(fch_plan_t p, const double* u, fch_c128* uh) {
+  if (!p || !u || !uh) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  RowArgs r = row_args(p);
+  r.u_in = u;
+  r.X_out = p->P0;
+  HIPCHK(p->vt->row(fch::ROW_FWD, r, p->stream));
+  ColArgs a = col_args(p);
+  a.X_in = p->P0;
+  a.X_out = (cd*)uh;
+  HIPCHK(p->vt->col_fwd1(a, p->stream));
+  p->stats.launches += 2;
+  p->stats.fft_calls += 1;
+  return FCH_OK;
+}
+
+fch_status fch_inverse(fch_plan_t p, const fch_c128* uh, double* u) {
+  if (!p || !u || !uh) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  ColArgs a = col_args(p);
+  a.X_in = (const cd*)uh;
+  a.X_out = p->P0;
+  HIPCHK(p->vt->col_inv1(a, p->stream));
+  RowArgs r = row_args(p);
+  r.X_in = p->P0;
+  r.u_out = u;
+  HIPCHK(p->vt->row(fch::ROW_INV, r, p->stream));
+  p->stats.launches += 2;
+  p->stats.fft_calls += 1;
+  return FCH_OK;
+}
+
+// ---- chemical potential ---------------------------------------------------
+fch_status fch_chem_potential(fch_plan_t p, const fch_c128* uh, fch_c128* muh, double* energy) {
+  if (!p || !uh || !muh || (const void*)uh == (const void*)muh) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  CHK(ctl_set(p, ctl_zero()));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+  CHK(row_mu(p, p->rpart));
+  a.out = (cd*)muh;
+  a.partial = p->cpart;
+  CHK(col(p, fch::EPI_MU, fch::PRO_NONE, a));
+  p->stats.fft_calls += 4;
+  if (energy) {
+    CHK(finalize(p, fch::FIN_ENERGY, true, true));
+    CHK(readback(p));
+    *energy = p->hctl->energy;
+    CHK(status_from_ctl(p));
+  }
+  return FCH_OK;
+}
+
+fch_status fch_rhs(fch_plan_t p, const fch_c128* uh, fch_c128* Fh) {
+  if (!p || !uh || !Fh || (const void*)uh == (const void*)Fh) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  CHK(ctl_set(p, ctl_zero()));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+  CHK(row_mu(p, nullptr));
+  a.out = (cd*)Fh;
+  CHK(col(p, fch::EPI_F, fch::PRO_NONE, a));
+  p->stats.fft_calls += 4;
+  return FCH_OK;
+}
+
+// ---- steps ----------------------------------------------------------------
+static fch_status check_step(fch_plan_t p, const fch_c128* un, const fch_c128* um, double k_np1,
+                             double k_n, const fch_c128* out) {
+  if (!p || !un || !out) return FCH_E_INVALID;
+  if (!finite_pos(k_np1) || !std::isfinite(k_n)) return FCH_E_INVALID;
+  if (k_n > 0.0 && !um) return FCH_E_INVALID;
+  if ((const void*)out == (const void*)un) return FCH_E_INVALID;
+  return need_ws(p);
+}
+
+fch_status fch_step_imex(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                         double k_np1, double k_n, fch_c128* uh_np1) {
+  CHK(check_step(p, uh_n, uh_nm1, k_np1, k_n, uh_np1));
+  const cd* um = (k_n > 0.0) ? (const cd*)uh_nm1 : (const cd*)uh_n;
+  return imex_attempt(p, (const cd*)uh_n, um, k_np1, k_n, (cd*)uh_np1);
+}
+
+fch_status fch_sav_r(fch_plan_t p, const fch_c128* uh, double* r) {
+  if (!p || !uh || !r) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  CHK(ctl_set(p, ctl_zero()));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+  CHK(row_mu(p, p->rpart));
+  CHK(finalize(p, fch::FIN_SAV_S, true, false));
+  CHK(readback(p));
+  CHK(status_from_ctl(p));
+  *r = p->hctl->s_star;
+  return FCH_OK;
+}
+
+fch_status fch_step_sav(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1, double r_n,
+                        double r_nm1, double k_np1, double k_n, fch_c128* uh_np1, double* r_np1) {
+  CHK(check_step(p, uh_n, uh_nm1, k_np1, k_n, uh_np1));
+  if (!r_np1 || !std::isfinite(r_n) || !std::isfinite(r_nm1)) return FCH_E_INVALID;
+  const cd* un = (const cd*)uh_n;
+  const cd* um = (k_n > 0.0) ? (const cd*)uh_nm1 : un;
+  StepCtl v = ctl_zero();
+  set_bdf2(v, k_np1, k_n);
+  v.r_n = r_n;
+  v.r_nm1 = (k_n > 0.0) ? r_nm1 : 0.0;
+  CHK(ctl_set(p, v));
+  ColArgs a = col_args(p);
+  a.s0 = un;
+  a.s1 = um;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+  CHK(row_mu(p, p->rpart));
+  CHK(finalize(p, fch::FIN_SAV_S, true, false));
+  a.out = (cd*)uh_np1;
+  a.aux = p->aux;
+  a.partial = p->cpart;
+  CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, a));
+  CHK(finalize(p, fch::FIN_SAV_R, false, true));
+  HIPCHK(fch::launch_axpy_r((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->stream));
+  p->stats.launches += 1;
+  p->stats.fft_calls += 4;
+  p->stats.steps += 1;
+  CHK(readback(p));
+  CHK(status_from_ctl(p));
+  *r_np1 = p->hctl->r_np1;
+  return FCH_OK;
+}
+
+fch_status fch_step_psd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1, double k_np1,
+                        double k_n, const fch_c128* guess, const fch_psd_opts* opts,
+                        fch_c128* uh_np1, fch_psd_stats* stats) {
+  CHK(check_step(p, uh_n, uh_nm1, k_np1, k_n, uh_np1));
+  if (!opts || opts->max_iter < 1 || !(opts->tol > 0.0 || opts->fixed_iters > 0))
+    return FCH_E_INVALID;
+  if ((const void*)guess == (const void*)uh_np1 && guess) return FCH_E_INVALID;
+  const double lam = opts->lambda > 0.0 ? opts->lambda : lambda_table(p->prm.q, k_np1);
+  if (!(lam > 0.0)) return FCH_E_INVALID;
+  const cd* un = (const cd*)uh_n;
+  const cd* um = (k_n > 0.0) ? (const cd*)uh_nm1 : un;
+  StepCtl v = ctl_zero();
+  set_bdf2(v, k_np1, k_n);
+  v.lambda = lam;
+  v.tol = opts->tol;
+  v.max_iter = opts->max_iter;
+  v.fixed_iters = opts->fixed_iters;
+  CHK(ctl_set(p, v));
+  ColArgs a = col_args(p);
+  a.s0 = un;
+  a.s1 = um;
+  a.guess = (const cd*)guess;
+  a.out = (cd*)uh_np1;
+  a.aux = p->aux;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_PSD_INIT, a));
+  a.partial = p->cpart;
+  const int limit = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
+  int queued = 0;
+  int chunk = p->psd_hint > 0 ? p->psd_hint : 4;
+  for (;;) {
+    const int n = (chunk < limit - queued) ? chunk : (limit - queued);
+    for (int i = 0; i < n; ++i) {
+      CHK(row_mu(p, nullptr));
+      CHK(col(p, fch::EPI_PSD, fch::PRO_NEXT_FIELD, a));
+      CHK(finalize(p, fch::FIN_PSD, false, true));
+    }
+    queued += n;
+    CHK(readback(p));
+    if (p->hctl->done || queued >= limit) break;
+    chunk = 4;
+  }
+  const int iters = p->hctl->iters;
+  p->psd_hint = iters > 0 ? iters : 4;
+  p->stats.psd_iters += iters;
+  p->stats.fft_calls += 4LL * iters;
+  p->stats.steps += 1;
+  if (stats) {
+    stats->iters = iters;
+    stats->fft_calls = 4LL * iters;
+    stats->last_ratio = p->hctl->ratio;
+  }
+  if (p->hctl->nonfinite || p->hctl->done == 3) return FCH_E_NONFINITE;
+  if (p->hctl->done == 2) return FCH_E_NOCONV;
+  return FCH_OK;
+}
+
+// ---- adaptivity -----------------------------------------------------------
+static fch_status check_adapt(const fch_adapt_opts* o) {
+  if (!o || !finite_pos(o->sigma_tol) || !finite_pos(o->k_min) || !(o->k_max >= o->k_min) ||
+      !finite_pos(o->rho_s) || std::isnan(o->cap))
+    return FCH_E_INVALID;
+  return FCH_OK;
+}
+
+static void set_adapt(StepCtl& v, const fch_adapt_opts* o) {
+  v.sigma_tol = o->sigma_tol;
+  v.k_min = o->k_min;
+  v.k_max = o->k_max;
+  v.rho_s = o->rho_s;
+  v.cap = o->cap;
+}
+
+fch_status fch_adapt_dt(fch_plan_t p, const fch_c128* uh_trial, const fch_c128* uh_n,
+                        const fch_c128* F_n, const fch_c128* F_nm1, double k_trial, double k_n,
+                        const fch_adapt_opts* opts, fch_c128* F_trial, int32_t* accept,
+                        double* k_next, double* err) {
+  if (!p || !uh_trial || !uh_n || !F_n || !F_nm1 || !F_trial) return FCH_E_INVALID;
+  if (!finite_pos(k_trial) || !finite_pos(k_n)) return FCH_E_INVALID;
+  const void* outs = F_trial;
+  if (outs == uh_trial || outs == uh_n || outs == F_n || outs == F_nm1) return FCH_E_INVALID;
+  CHK(check_adapt(opts));
+  CHK(need_ws(p));
+  StepCtl v = ctl_zero();
+  set_bdf2(v, k_trial, k_n);
+  set_am3(v, k_trial, k_n);
+  set_adapt(v, opts);
+  CHK(ctl_set(p, v));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh_trial;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+  CHK(row_mu(p, nullptr));
+  a.s1 = (const cd*)uh_n;
+  a.f_n = (const cd*)F_n;
+  a.f_nm1 = (const cd*)F_nm1;
+  a.out = (cd*)F_trial;
+  a.partial = p->cpart;
+  CHK(col(p, fch::EPI_AM3, fch::PRO_NONE, a));
+  CHK(finalize(p, fch::FIN_AM3, false, true));
+  p->stats.fft_calls += 4;
+  CHK(readback(p));
+  if (accept) *accept = p->hctl->accept;
+  if (k_next) *k_next = p->hctl->k_next;
+  if (err) *err = p->hctl->err;
+  return status_from_ctl(p);
+}
+
+// ---- trajectories ---------------------------------------------------------
+static fch_status copy_spec(fch_plan_t p, cd* dst, const cd* src) {
+  if (dst == src) return FCH_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, spec_bytes(p->N), hipMemcpyDeviceToDevice, p->stream));
+  return FCH_OK;
+}
+
+// put (cur, prev) back into the caller's (uh_n, uh_nm1)
+static fch_status settle(fch_plan_t p, cd* B0, cd* B1, cd* cur, cd* prev) {
+  if (cur == B0 && prev == B1) return FCH_OK;
+  if (cur == B1 && prev == B0) {
+    CHK(copy_spec(p, p->st, B1));
+    CHK(copy_spec(p, B1, B0));
+    return copy_spec(p, B0, p->st);
+  }
+  // one of them lives in the spare buffer
+  if (cur == B0) return copy_spec(p, B1, prev);
+  if (prev == B1) return copy_spec(p, B0, cur);
+  if (cur == B1) {  // prev is the spare
+    CHK(copy_spec(p, B0, B1));
+    return copy_spec(p, B1, prev);
+  }
+  // cur is the spare, prev == B0
+  CHK(copy_spec(p, B1, B0));
+  return copy_spec(p, B0, cur);
+}
+
+static fch_status sav_or_psd_step(fch_plan_t p, const fch_run_opts* o, const cd* un, const cd* um,
+                                  double k1, double k0, cd* out, double* rs, double* r_new,
+                                  int64_t* iters) {
+  if (o->scheme == FCH_SAV) {
+    return fch_step_sav(p, (const fch_c128*)un, (const fch_c128*)um, rs[0], rs[1], k1, k0,
+                        (fch_c128*)out, r_new);
+  }
+  fch_psd_stats st;
+  fch_status s = fch_step_psd(p, (const fch_c128*)un, (const fch_c128*)um, k1, k0, nullptr,
+                              &o->psd, (fch_c128*)out, &st);
+  *iters += st.iters;
+  return s;
+}
+
+fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128* uh_nm1,
+                   double* rs, fch_run_info* info) {
+  if (!p || !o || !uh_n || !uh_nm1 || uh_n == uh_nm1) return FCH_E_INVALID;
+  if (o->scheme < FCH_IMEX || o->scheme > FCH_PSD) return FCH_E_INVALID;
+  if (o->scheme == FCH_SAV && !rs) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  cd* B0 = (cd*)uh_n;
+  cd* B1 = (cd*)uh_nm1;
+  cd *cur = B0, *prev = B1, *spare = p->st;
+  fch_run_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  double r0 = 0.0;
+  if (o->scheme == FCH_SAV && o->startup) {
+    CHK(fch_sav_r(p, uh_n, &r0));
+    rs[0] = r0;
+    rs[1] = r0;
+  }
+
+  if (!o->adaptive) {
+    if (!finite_pos(o->k) || o->nsteps < 0) return FCH_E_INVALID;
+    int64_t done = 0;
+    double k_n = o->k_prev;
+    if (o->startup && o->nsteps > 0) {
+      // first-order step from u^0
+      if (o->scheme == FCH_IMEX) {
+        CHK(imex_attempt(p, cur, cur, o->k, -1.0, prev));
+      } else {
+        double rn = 0;
+        int64_t it = 0;
+        CHK(sav_or_psd_step(p, o, cur, cur, o->k, -1.0, prev, rs, &rn, &it));
+        inf.psd_iters += it;
+        if (o->scheme == FCH_SAV) { rs[1] = rs[0]; rs[0] = rn; }
+      }
+      std::swap(cur, prev);
+      k_n = o->k;
+      done = 1;
+    }
+    if (done < o->nsteps && !finite_pos(k_n)) return FCH_E_INVALID;
+    if (o->scheme == FCH_IMEX && done < o->nsteps) {
+      if (k_n != o->k) {  // a step-ratio change: one unfused step first
+        CHK(imex_attempt(p, cur, prev, o->k, k_n, prev));
+        std::swap(cur, prev);
+        k_n = o->k;
+        ++done;
+      }
+      if (done < o->nsteps) {
+        // fused chain at gamma = 1: each column pass ends one step and
+        // starts the next; u^{n+1} overwrites u^{n-1}
+        StepCtl v = ctl_zero();
+        set_bdf2(v, o->k, o->k);
+        CHK(ctl_set(p, v));
+        ColArgs a = col_args(p);
+        a.s0 = cur;
+        a.s1 = prev;
+        CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+        while (done < o->nsteps) {
+          CHK(row_mu(p, nullptr));
+          const bool last = (done + 1 == o->nsteps);
+          a.s0 = cur;
+          a.s1 = prev;
+          a.out = prev;
+          CHK(col(p, fch::EPI_IMEX, last ? fch::PRO_NONE : fch::PRO_NEXT_EXTRAP, a));
+          std::swap(cur, prev);
+          ++done;
+          p->stats.fft_calls += 4;
+          p->stats.steps += 1;
+        }
+      }
+    } else {
+      while (done < o->nsteps) {
+        double rn = 0;
+        int64_t it = 0;
+        CHK(sav_or_psd_step(p, o, cur, prev, o->k, k_n, prev, rs, &rn, &it));
+        inf.psd_iters += it;
+        if (o->scheme == FCH_SAV) { rs[1] = rs[0]; rs[0] = rn; }
+        std::swap(cur, prev);
+        k_n = o->k;
+        ++done;
+      }
+    }
+    inf.accepted = done;
+    inf.t = done * o->k;
+    inf.k_last = o->k;
+    inf.k_next = o->k;
+    CHK(settle(p, B0, B1, cur, prev));
+    if (info) {
+      inf.fft_calls = p->stats.fft_calls;
+      *info = inf;
+    }
+    return FCH_OK;
+  }
+
+  // ---- adaptive (Sec. 3.2) ----
+  CHK(check_adapt(&o->adapt));
+  const fch_adapt_opts* ad = &o->adapt;
+  if (!(o->t_end > 0.0)) return FCH_E_INVALID;
+  cd* Fn = p->Fc[0];
+  cd* Fm = p->Fc[1];
+  cd* Ft = p->Fc[2];
+  double t = 0.0, k_n = o->k_prev, kt = o->k;
+  if (o->startup) {
+    const double k1 = o->k_first > 0.0 ? o->k_first : ad->k_min;
+    CHK(fch_rhs(p, (const fch_c128*)cur, (fch_c128*)Fm));
+    if (o->scheme == FCH_IMEX) {
+      CHK(imex_attempt(p, cur, cur, k1, -1.0, prev));
+    } else {
+      double rn = 0;
+      int64_t it = 0;
+      CHK(sav_or_psd_step(p, o, cur, cur, k1, -1.0, prev, rs, &rn, &it));
+      inf.psd_iters += it;
+      if (o->scheme == FCH_SAV) { rs[1] = rs[0]; rs[0] = rn; }
+    }
+    std::swap(cur, prev);
+    CHK(fch_rhs(p, (const fch_c128*)cur, (fch_c128*)Fn));
+    t = k1;
+    k_n = k1;
+    kt = k1;  // Step 0: the first trial step equals the last step
+    inf.accepted = 1;
+  } else {
+    if (!finite_pos(k_n) || !finite_pos(kt)) return FCH_E_INVALID;
+    CHK(fch_rhs(p, (const fch_c128*)cur, (fch_c128*)Fn));
+    CHK(fch_rhs(p, (const fch_c128*)prev, (fch_c128*)Fm));
+  }
+  const double t_end = o->t_end;
+  const int64_t max_acc = o->nsteps > 0 ? o->nsteps : INT64_MAX;
+  while (t < t_end * (1.0 - 1e-14) && inf.accepted < max_acc) {
+    if (kt > t_end - t) kt = t_end - t;
+    double r_new = 0.0;
+    int64_t it = 0;
+    StepCtl v = ctl_zero();
+    set_bdf2(v, kt, k_n);
+    set_am3(v, kt, k_n);
+    set_adapt(v, ad);
+    if (o->scheme == FCH_IMEX) {
+      // fused: the step's column pass also starts the F(u~) evaluation
+      CHK(ctl_set(p, v));
+      ColArgs a = col_args(p);
+      a.s0 = cur;
+      a.s1 = prev;
+      CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+      CHK(row_mu(p, nullptr));
+      a.out = spare;
+      CHK(col(p, fch::EPI_IMEX, fch::PRO_NEXT_FIELD, a));
+      CHK(row_mu(p, nullptr));
+      ColArgs b = col_args(p);
+      b.s0 = spare;
+      b.s1 = cur;
+      b.f_n = Fn;
+      b.f_nm1 = Fm;
+      b.out = Ft;
+      b.partial = p->cpart;
+      CHK(col(p, fch::EPI_AM3, fch::PRO_NONE, b));
+      CHK(finalize(p, fch::FIN_AM3, false, true));
+      CHK(readback(p));
+      CHK(status_from_ctl(p));
+      p->stats.fft_calls += 8;
+    } else {
+      CHK(sav_or_psd_step(p, o, cur, prev, kt, k_n, spare, rs, &r_new, &it));
+      inf.psd_iters += it;
+      int32_t acc = 0;
+      double kn = 0, e = 0;
+      CHK(fch_adapt_dt(p, (const fch_c128*)spare, (const fch_c128*)cur, (const fch_c128*)Fn,
+                       (const fch_c128*)Fm, kt, k_n, ad, (fch_c128*)Ft, &acc, &kn, &e));
+    }
+    const bool accept = p->hctl->accept != 0;
+    const double k_next = p->hctl->k_next;
+    if (accept) {
+      cd* old_prev = prev;
+      prev = cur;
+      cur = spare;
+      spare = old_prev;
+      cd* old_Fm = Fm;
+      Fm = Fn;
+      Fn = Ft;
+      Ft = old_Fm;
+      if (o->scheme == FCH_SAV) { rs[1] = rs[0]; rs[0] = r_new; }
+      t += kt;
+      k_n = kt;
+      inf.accepted += 1;
+      inf.k_last = kt;
+    } else {
+      inf.rejected += 1;
+      p->stats.rejected += 1;
+    }
+    kt = k_next;
+  }
+  inf.t = t;
+  inf.k_next = kt;
+  CHK(settle(p, B0, B1, cur, prev));
+  if (info) {
+    inf.fft_calls = p->stats.fft_calls;
+    *info = inf;
+  }
+  return FCH_OK;
+}
+
+}  // extern "C"

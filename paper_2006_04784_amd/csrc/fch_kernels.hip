@@ -1,0 +1,590 @@
+// fch_kernels.hip -- HIP kernels of the FCH pseudo-spectral BDF2 path for
+// gfx950, FP64.
+//
+// A 2D real transform is split into a row pass (length-N FFTs along x, one
+// workgroup per R rows) and a column pass (length-N FFTs along y, one
+// workgroup per column kx).  Spectra are stored kx-major, so the column pass
+// reads and writes contiguous columns and the row pass gathers R-row
+// segments per kx (R*16 bytes).  Everything between two HBM round trips is
+// fused:
+//   row pass   : gather -> inverse FFT -> pointwise well / chemical-potential
+//                pieces (omega, p, E_1 and energy densities) -> forward FFT ->
+//                untangle -> scatter.  Physical rows never leave the CU.
+//   column pass: forward FFT -> spectral epilogue (mu assembly and the IMEX /
+//                SAV / PSD / AM3 diagonal algebra, Parseval partial sums) ->
+//                spectral prologue of the next evaluation (u*, Lap u*) ->
+//                inverse FFT.
+// Two real rows are transformed as one complex sequence z = a + i b (the
+// row pass always handles pairs: (u, Lap u) in, (omega, p) out).
+#include <hip/hip_runtime.h>
+
+#include "fch_kernels.hpp"
+
+namespace fch {
+
+__device__ __forceinline__ double wavek2(const Consts& c, int kx, int ky) {
+  const int N = c.N;
+  const int kyi = (ky <= N / 2) ? ky : ky - N;
+  return c.kscale * (double)(kx * kx + kyi * kyi);
+}
+
+// deterministic tree reduction of K values over NT threads; thread 0 writes
+template <int NT, int K>
+__device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, double* out) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k * NT + tid] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[k * NT + tid] += red[k * NT + tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = red[k * NT];
+  }
+}
+
+// ===========================================================================
+// Row pass
+// ===========================================================================
+template <int N, int R, int E, int MODE>
+__global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
+  constexpr int T = N / E;
+  constexpr int NT = R * T;
+  constexpr int M = N / 2;
+  constexpr int H = M + 1;
+  __shared__ cd Z[R][N];
+  __shared__ cd tw[N];
+  __shared__ double red[2 * NT];
+  if (done && *done) return;
+
+  const int tid = threadIdx.x;
+  const int seq = tid / T;
+  const int t = tid - seq * T;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  // ROW_MU: rows y0 .. y0+R-1, one (u, Lap u) pair per row.
+  // ROW_FWD/ROW_INV: rows y0 .. y0+2R-1, sequence s pairs rows y0+s, y0+R+s.
+  const int y0 = (MODE == ROW_MU) ? tile * R : tile * 2 * R;
+
+  for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+
+  cd v[1][E];
+  cd* const base[1] = {Z[seq]};
+
+  if constexpr (MODE == ROW_MU || MODE == ROW_INV) {
+    // gather the column-inverted half spectra of R rows; build the full
+    // length-N spectrum of z = a + i b from the two Hermitian halves
+    for (int idx = tid; idx < R * H; idx += NT) {
+      const int kx = idx / R, rr = idx - kx * R;
+      cd xa, xb;
+      if constexpr (MODE == ROW_MU) {
+        const size_t g = (size_t)kx * N + y0 + rr;
+        xa = a.P0[g];
+        xb = a.P1[g];
+      } else {
+        const size_t g = (size_t)kx * N + y0 + rr;
+        xa = a.X_in[g];
+        xb = a.X_in[g + R];
+      }
+      if (kx == 0 || kx == M) {
+        Z[rr][kx] = cd{xa.x, xb.x};  // real parts only: C2R of the Hermitian extension
+      } else {
+        Z[rr][kx] = cd{xa.x - xb.y, xa.y + xb.x};
+        Z[rr][N - kx] = cd{xa.x + xb.y, xb.x - xa.y};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) v[0][s] = Z[seq][t + s * T];
+    fft<N, E, 1, +1>(v, base, tw, t);
+  }
+
+  if constexpr (MODE == ROW_INV) {
+    double* ua = a.u_out + (size_t)(y0 + seq) * N;
+    double* ub = a.u_out + (size_t)(y0 + R + seq) * N;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      ua[t + s * T] = v[0][s].x * a.c.invN2;
+      ub[t + s * T] = v[0][s].y * a.c.invN2;
+    }
+    return;
+  }
+
+  double acc[2] = {0.0, 0.0};
+  if constexpr (MODE == ROW_MU) {
+    const Consts& c = a.c;
+    bool bad = false;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const double u = v[0][s].x * c.invN2;
+      const double lap = v[0][s].y * c.invN2;
+      double W, W1, W2;
+      well(c, u, W, W1, W2);
+      const double om = c.eps2 * lap - W1;
+      const double p = -W2 * om - c.eta2 * W1;
+      acc[0] += -c.eps2 * lap * (W1 + c.zeta * u) + 0.5 * W1 * W1 - c.eta2 * W;  // G (eq. e:G-def)
+      acc[1] += 0.5 * om * om - c.eta2 * W;                                       // energy density
+      bad |= !(isfinite(u) && isfinite(lap));
+      v[0][s] = cd{om, p};
+    }
+    if (bad) a.ctl->nonfinite = 1;
+  } else {  // ROW_FWD: two physical rows as one complex sequence
+    const double* ua = a.u_in + (size_t)(y0 + seq) * N;
+    const double* ub = a.u_in + (size_t)(y0 + R + seq) * N;
+#pragma unroll
+    for (int s = 0; s < E; ++s) v[0][s] = cd{ua[t + s * T], ub[t + s * T]};
+  }
+
+  fft<N, E, 1, -1>(v, base, tw, t);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < E; ++s) Z[seq][t + s * T] = v[0][s];
+  __syncthreads();
+
+  // untangle: A[k] = (Z[k] + conj Z[N-k])/2, B[k] = (Z[k] - conj Z[N-k])/(2i)
+  for (int idx = tid; idx < R * H; idx += NT) {
+    const int kx = idx / R, rr = idx - kx * R;
+    const cd zk = Z[rr][kx];
+    const cd zn = Z[rr][(N - kx) & (N - 1)];
+    const cd xa = {0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
+    const cd xb = {0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)};
+    const size_t g = (size_t)kx * N + y0 + rr;
+    if constexpr (MODE == ROW_MU) {
+      a.P0[g] = xa;
+      a.P1[g] = xb;
+    } else {
+      a.X_out[g] = xa;
+      a.X_out[g + R] = xb;
+    }
+  }
+
+  if constexpr (MODE == ROW_MU) {
+    if (a.partial) block_reduce<NT, 2>(acc, red, a.partial + 2 * tile);
+  }
+}
+
+// ===========================================================================
+// Column pass
+// ===========================================================================
+template <int N, int E, int EPI, int PRO>
+__global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
+  constexpr int T = N / E;
+  constexpr int M = N / 2;
+  __shared__ cd buf[2][N];
+  __shared__ cd tw[N];
+  __shared__ double red[2 * T];
+  if (done && *done) return;
+
+  const Consts& c = a.c;
+  const int t = threadIdx.x;
+  const int kx = blockIdx.x;
+  const size_t col = (size_t)kx * N;
+  const double wgt = (kx == 0 || kx == M) ? 1.0 : 2.0;  // Parseval weight of the half spectrum
+
+  for (int i = t; i < N; i += T) tw[i] = a.tw[i];
+  __syncthreads();
+
+  cd v[2][E];
+  cd* const base[2] = {buf[0], buf[1]};
+  cd unext[E];  // field handed to the prologue by the epilogue
+  double acc[2] = {0.0, 0.0};
+  const StepCtl* ctl = a.ctl;
+
+  if constexpr (EPI != EPI_NONE) {
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      v[0][s] = a.P0[col + t + s * T];
+      v[1][s] = a.P1[col + t + s * T];
+    }
+    fft<N, E, 2, -1>(v, base, tw, t);
+
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int ky = t + s * T;
+      const size_t g = col + ky;
+      const double k2 = wavek2(c, kx, ky);
+      const cd om = v[0][s], pp = v[1][s];
+      const double e2k2 = c.eps2 * k2;
+      // field U whose (U, Lap U) fed this evaluation
+      cd U;
+      cd un = {0, 0}, um = {0, 0};
+      if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
+        un = a.s0[g];
+        um = a.s1[g];
+        U = cadd(un, cscale(csub(un, um), ctl->gamma));
+      } else if constexpr (EPI == EPI_PSD) {
+        U = a.out[g];
+      } else {
+        U = a.s0[g];
+      }
+      // mu = -eps^2 |k|^2 omega + p - eps^2 eta1 |k|^2 U
+      const cd mu = {-e2k2 * om.x + pp.x - e2k2 * c.eta1 * U.x,
+                     -e2k2 * om.y + pp.y - e2k2 * c.eta1 * U.y};
+      if constexpr (EPI == EPI_MU) {
+        a.out[g] = mu;
+        acc[0] += wgt * k2 * cnorm2(U);
+        unext[s] = U;
+      } else if constexpr (EPI == EPI_F) {
+        a.out[g] = cscale(mu, -k2);
+        unext[s] = U;
+      } else if constexpr (EPI == EPI_IMEX) {
+        const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
+        const cd Nh = csub(mu, cscale(U, Lk));
+        const double inv = 1.0 / (ctl->a + k2 * Lk);
+        const cd un1 = {(-ctl->b * un.x - ctl->c * um.x - k2 * Nh.x) * inv,
+                        (-ctl->b * un.y - ctl->c * um.y - k2 * Nh.y) * inv};
+        a.out[g] = un1;
+        if constexpr (PRO == PRO_NEXT_EXTRAP)
+          unext[s] = cadd(un1, cscale(csub(un1, un), ctl->gamma));
+        else
+          unext[s] = un1;
+      } else if constexpr (EPI == EPI_SAV) {
+        const double lsav = e2k2 * e2k2 - e2k2 * (c.eta1 + 2.0 * c.zeta);
+        const double inv_s = 1.0 / ctl->s_star;
+        const cd X = cscale(csub(mu, cscale(U, lsav)), inv_s);
+        const double L0 = e2k2 * e2k2 + c.beta1 * c.alpha * e2k2 + c.beta2 * c.alpha * c.alpha;
+        const double L1 = -e2k2 * (c.eta1 + 2.0 * c.zeta) - c.beta1 * c.alpha * e2k2 -
+                          c.beta2 * c.alpha * c.alpha;
+        const double inv = 1.0 / (ctl->a + k2 * L0);
+        const cd p = {(-ctl->b * un.x - ctl->c * um.x - k2 * L1 * U.x) * inv,
+                      (-ctl->b * un.y - ctl->c * um.y - k2 * L1 * U.y) * inv};
+        const cd qv = cscale(X, -k2 * inv);
+        a.out[g] = p;
+        a.aux[g] = qv;
+        const cd rp = {ctl->a * p.x + ctl->b * un.x + ctl->c * um.x,
+                       ctl->a * p.y + ctl->b * un.y + ctl->c * um.y};
+        acc[0] += wgt * cdotr(X, rp);
+        acc[1] += wgt * cdotr(X, qv);
+      } else if constexpr (EPI == EPI_PSD) {
+        const cd G = a.aux[g];
+        cd d = {0.0, 0.0};
+        if (k2 != 0.0) {
+          const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
+          const double inv = -1.0 / (k2 * Lk + ctl->a);
+          d = cd{(k2 * mu.x + ctl->a * U.x + G.x) * inv, (k2 * mu.y + ctl->a * U.y + G.y) * inv};
+        }
+        const cd u1 = cadd(U, cscale(d, ctl->lambda));
+        a.out[g] = u1;
+        acc[0] += wgt * cnorm2(d);
+        acc[1] += wgt * cnorm2(u1);
+        unext[s] = u1;
+      } else if constexpr (EPI == EPI_AM3) {
+        const cd F = cscale(mu, -k2);
+        a.out[g] = F;
+        const cd u_n = a.s1[g], fn = a.f_n[g], fm = a.f_nm1[g];
+        const cd up = {u_n.x + ctl->w1 * F.x + ctl->w2 * fn.x + ctl->w3 * fm.x,
+                       u_n.y + ctl->w1 * F.y + ctl->w2 * fn.y + ctl->w3 * fm.y};
+        acc[0] += wgt * cnorm2(csub(U, up));
+        acc[1] += wgt * cnorm2(up);
+      }
+    }
+  }
+
+  if constexpr (PRO != PRO_NONE) {
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int ky = t + s * T;
+      const size_t g = col + ky;
+      const double k2 = wavek2(c, kx, ky);
+      cd U;
+      if constexpr (PRO == PRO_FIELD) {
+        U = a.s0[g];
+      } else if constexpr (PRO == PRO_EXTRAP) {
+        const cd un = a.s0[g], um = a.s1[g];
+        U = cadd(un, cscale(csub(un, um), ctl->gamma));
+      } else if constexpr (PRO == PRO_PSD_INIT) {
+        const cd un = a.s0[g], um = a.s1[g];
+        a.aux[g] = cd{ctl->b * un.x + ctl->c * um.x, ctl->b * un.y + ctl->c * um.y};
+        if (a.guess) {
+          U = (kx == 0 && ky == 0) ? un : a.guess[g];  // keep the mass of u^n
+        } else {
+          U = cadd(un, cscale(csub(un, um), ctl->gamma));
+        }
+        a.out[g] = U;
+      } else {
+        U = unext[s];
+      }
+      v[0][s] = U;
+      v[1][s] = cscale(U, -k2);
+    }
+    fft<N, E, 2, +1>(v, base, tw, t);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      a.P0[col + t + s * T] = v[0][s];
+      a.P1[col + t + s * T] = v[1][s];
+    }
+  }
+
+  if constexpr (EPI == EPI_MU || EPI == EPI_SAV || EPI == EPI_PSD || EPI == EPI_AM3) {
+    if (a.partial) block_reduce<T, 2>(acc, red, a.partial + 2 * kx);
+  }
+}
+
+// single-field column transforms (boundary fch_forward / fch_inverse):
+// two columns per workgroup, one sequence each
+template <int N, int E, int DIR>
+__global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
+  constexpr int T = N / E;
+  constexpr int H = N / 2 + 1;
+  __shared__ cd buf[2][N];
+  __shared__ cd tw[N];
+  const int t = threadIdx.x;
+  const int kx0 = 2 * blockIdx.x;
+  for (int i = t; i < N; i += T) tw[i] = a.tw[i];
+  __syncthreads();
+  cd v[2][E];
+  cd* const base[2] = {buf[0], buf[1]};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int kx = kx0 + q;
+#pragma unroll
+    for (int s = 0; s < E; ++s)
+      v[q][s] = (kx < H) ? a.X_in[(size_t)kx * N + t + s * T] : cd{0.0, 0.0};
+  }
+  fft<N, E, 2, DIR>(v, base, tw, t);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int kx = kx0 + q;
+    if (kx < H) {
+#pragma unroll
+      for (int s = 0; s < E; ++s) a.X_out[(size_t)kx * N + t + s * T] = v[q][s];
+    }
+  }
+}
+
+// ===========================================================================
+// Small kernels: control block, reductions, SAV combine
+// ===========================================================================
+__global__ void k_ctl_set(StepCtl* ctl, StepCtl v) { *ctl = v; }
+
+__device__ __forceinline__ double sum_strided(const double* p, int n, int stride, int off,
+                                              double* red) {
+  constexpr int NT = 256;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += p[(size_t)i * stride + off];
+  double v[1] = {s};
+  __shared__ double tot;
+  block_reduce<NT, 1>(v, red, &tot);
+  __syncthreads();
+  return tot;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
+  __shared__ double red[256];
+  StepCtl* ctl = a.ctl;
+  const Consts& c = a.c;
+  if (a.mode == FIN_PSD && ctl->done) return;
+  double r0 = 0, r1 = 0, c0 = 0, c1 = 0;
+  if (a.rpart) {
+    r0 = sum_strided(a.rpart, a.nrow, 2, 0, red);
+    r1 = sum_strided(a.rpart, a.nrow, 2, 1, red);
+  }
+  if (a.cpart) {
+    c0 = sum_strided(a.cpart, a.ncol, 2, 0, red);
+    c1 = sum_strided(a.cpart, a.ncol, 2, 1, red);
+  }
+  if (threadIdx.x != 0) return;
+  switch (a.mode) {
+    case FIN_SAV_S: {
+      const double E1 = c.h2 * r0;
+      const double s2 = E1 + c.D0;
+      ctl->E1 = E1;
+      if (!isfinite(s2)) {
+        ctl->nonfinite = 1;
+        ctl->s_star = 1.0;
+      } else if (!(s2 > 0.0)) {
+        ctl->invalid = 1;
+        ctl->s_star = 1.0;
+      } else {
+        ctl->s_star = sqrt(s2);
+      }
+      break;
+    }
+    case FIN_SAV_R: {
+      const double gp = c.pars * c0, gq = c.pars * c1;
+      const double r = (-ctl->b * ctl->r_n - ctl->c * ctl->r_nm1 + 0.5 * gp) /
+                       (ctl->a - 0.5 * ctl->a * gq);
+      ctl->r_np1 = r;
+      if (!isfinite(r)) ctl->nonfinite = 1;
+      break;
+    }
+    case FIN_PSD: {
+      const double ratio = sqrt(c0 / c1);
+      ctl->ratio = ratio;
+      ctl->iters += 1;
+      if (!isfinite(ratio)) {
+        ctl->nonfinite = 1;
+        ctl->done = 3;
+      } else if (ctl->fixed_iters > 0) {
+        if (ctl->iters >= ctl->fixed_iters) ctl->done = 1;
+      } else if (ratio < ctl->tol) {
+        ctl->done = 1;
+      } else if (ctl->iters >= ctl->max_iter) {
+        ctl->done = 2;
+      }
+      break;
+    }
+    case FIN_AM3: {
+      const double e = sqrt(c0 / c1);
+      const double ee = e > 1e-300 ? e : 1e-300;
+      double kn = ctl->rho_s * cbrt(ctl->sigma_tol / ee) * ctl->k_np1;
+      if (ctl->cap > 0.0 && kn > ctl->cap * ctl->k_np1) kn = ctl->cap * ctl->k_np1;
+      if (kn > ctl->k_max) kn = ctl->k_max;
+      if (kn < ctl->k_min) kn = ctl->k_min;
+      ctl->err = e;
+      ctl->k_next = kn;
+      ctl->accept = (e <= ctl->sigma_tol) || (ctl->k_np1 <= ctl->k_min);
+      if (!isfinite(e)) ctl->nonfinite = 1;
+      break;
+    }
+    case FIN_ENERGY: {
+      ctl->energy = c.h2 * r1 - 0.5 * c.eps2 * c.eta1 * c.pars * c0;
+      if (!isfinite(ctl->energy)) ctl->nonfinite = 1;
+      break;
+    }
+  }
+}
+
+__global__ void k_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n) {
+  const double r = ctl->r_np1;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const cd o = out[i], qq = q[i];
+    out[i] = cd{fma(r, qq.x, o.x), fma(r, qq.y, o.y)};
+  }
+}
+
+hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(1), 0, s, ctl, v);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_axpy_r, dim3((unsigned)blocks), dim3(256), 0, s, out, q, ctl, n);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Launch tables
+// ===========================================================================
+template <int N, int R, int RE, int CE>
+struct Impl {
+  static constexpr int RT = R * (N / RE);
+  static constexpr int CT = N / CE;
+  static constexpr int H = N / 2 + 1;
+
+  static hipError_t row(int mode, const RowArgs& a, hipStream_t s) {
+    const int* done = (mode == ROW_MU) ? &a.ctl->done : nullptr;
+    switch (mode) {
+      case ROW_MU:
+        hipLaunchKernelGGL((k_row<N, R, RE, ROW_MU>), dim3(N / R), dim3(RT), 0, s, a, done);
+        break;
+      case ROW_FWD:
+        hipLaunchKernelGGL((k_row<N, R, RE, ROW_FWD>), dim3(N / (2 * R)), dim3(RT), 0, s, a,
+                           nullptr);
+        break;
+      case ROW_INV:
+        hipLaunchKernelGGL((k_row<N, R, RE, ROW_INV>), dim3(N / (2 * R)), dim3(RT), 0, s, a,
+                           nullptr);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+
+  template <int EPI, int PRO>
+  static void lc(const ColArgs& a, hipStream_t s, const int* done) {
+    hipLaunchKernelGGL((k_col<N, CE, EPI, PRO>), dim3(H), dim3(CT), 0, s, a, done);
+  }
+
+  static hipError_t col(int epi, int pro, const ColArgs& a, hipStream_t s) {
+    const int* done = &a.ctl->done;
+#define FCH_COL(E_, P_)                \
+  if (epi == E_ && pro == P_) {        \
+    lc<E_, P_>(a, s, done);            \
+    return hipGetLastError();          \
+  }
+    FCH_COL(EPI_NONE, PRO_FIELD)
+    FCH_COL(EPI_NONE, PRO_EXTRAP)
+    FCH_COL(EPI_NONE, PRO_PSD_INIT)
+    FCH_COL(EPI_MU, PRO_NONE)
+    FCH_COL(EPI_F, PRO_NONE)
+    FCH_COL(EPI_IMEX, PRO_NONE)
+    FCH_COL(EPI_IMEX, PRO_NEXT_EXTRAP)
+    FCH_COL(EPI_IMEX, PRO_NEXT_FIELD)
+    FCH_COL(EPI_SAV, PRO_NONE)
+    FCH_COL(EPI_PSD, PRO_NEXT_FIELD)
+    FCH_COL(EPI_AM3, PRO_NONE)
+#undef FCH_COL
+    return hipErrorInvalidValue;
+  }
+
+  static hipError_t col_fwd1(const ColArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_col1<N, CE, -1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t col_inv1(const ColArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_col1<N, CE, +1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+    return hipGetLastError();
+  }
+
+  static const VTable* table() {
+    static const VTable vt = {N, R, RE, CE, RT, CT, &row, &col, &col_fwd1, &col_inv1};
+    return &vt;
+  }
+};
+
+// Compiled configurations per grid size (the first one is the default).
+#define FCH_CFG(N, R, RE, CE) Impl<N, R, RE, CE>::table()
+static const VTable* const* configs_for(int N, int* count) {
+  static const VTable* const c16[] = {FCH_CFG(16, 2, 4, 4)};
+  static const VTable* const c32[] = {FCH_CFG(32, 2, 4, 4)};
+  static const VTable* const c64[] = {FCH_CFG(64, 2, 8, 8)};
+  static const VTable* const c128[] = {FCH_CFG(128, 2, 8, 8)};
+  static const VTable* const c256[] = {FCH_CFG(256, 2, 16, 8)};
+  static const VTable* const c512[] = {FCH_CFG(512, 2, 8, 8)};
+  static const VTable* const c1024[] = {FCH_CFG(1024, 4, 16, 8)};
+  static const VTable* const c2048[] = {FCH_CFG(2048, 2, 16, 16)};
+#define FCH_RET(arr)                                 \
+  {                                                  \
+    *count = (int)(sizeof(arr) / sizeof(arr[0]));    \
+    return arr;                                      \
+  }
+  switch (N) {
+    case 16: FCH_RET(c16)
+    case 32: FCH_RET(c32)
+    case 64: FCH_RET(c64)
+    case 128: FCH_RET(c128)
+    case 256: FCH_RET(c256)
+    case 512: FCH_RET(c512)
+    case 1024: FCH_RET(c1024)
+    case 2048: FCH_RET(c2048)
+    default: *count = 0; return nullptr;
+  }
+#undef FCH_RET
+}
+
+int vtable_count(int N) {
+  int n = 0;
+  configs_for(N, &n);
+  return n;
+}
+const VTable* vtable_get(int N, int i) {
+  int n = 0;
+  const VTable* const* arr = configs_for(N, &n);
+  if (!arr || i < 0 || i >= n) return nullptr;
+  return arr[i];
+}
+
+}  // namespace fch

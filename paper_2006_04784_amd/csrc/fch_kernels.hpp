@@ -1,0 +1,93 @@
+// fch_kernels.hpp -- shared declarations between the HIP kernels and the
+// host orchestration: argument blocks, the device control block and the
+// per-grid-size launch table.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fch_device.hpp"
+
+namespace fch {
+
+// Per-call scalars live in device memory so that a captured launch sequence
+// can be replayed with new values (written by ctl_set or by a finalize kernel).
+struct StepCtl {
+  double k_np1, k_n, a, b, c, gamma;  // BDF2 coefficients (eq. BDF2Coef), u* ratio
+  double w1, w2, w3;                  // AM3 weights (eq. Predictor)
+  double lambda, tol;                 // PSD search step and stopping tolerance
+  double r_n, r_nm1, s_star, r_np1;   // SAV scalars
+  double sigma_tol, k_min, k_max, rho_s, cap;
+  double err, k_next, ratio, energy, E1;
+  int accept, iters, max_iter, fixed_iters;
+  int done;       // PSD: 0 running, 1 converged / fixed count reached, 2 max_iter, 3 non-finite
+  int nonfinite;  // set by any kernel that sees NaN/Inf
+  int invalid;    // SAV: E1 + D0 <= 0
+  int pad;
+};
+
+enum RowMode { ROW_MU = 0, ROW_FWD = 1, ROW_INV = 2 };
+enum Epi { EPI_NONE = 0, EPI_MU, EPI_F, EPI_IMEX, EPI_SAV, EPI_PSD, EPI_AM3 };
+enum Pro { PRO_NONE = 0, PRO_FIELD, PRO_EXTRAP, PRO_PSD_INIT, PRO_NEXT_EXTRAP, PRO_NEXT_FIELD };
+enum FinMode { FIN_SAV_S = 0, FIN_SAV_R, FIN_PSD, FIN_AM3, FIN_ENERGY };
+
+struct RowArgs {
+  Consts c;
+  cd* P0;              // pair buffer channel 0 (kx-major), in place (ROW_MU)
+  cd* P1;              // pair buffer channel 1
+  const double* u_in;  // ROW_FWD physical input
+  double* u_out;       // ROW_INV physical output
+  const cd* X_in;      // ROW_INV column-inverted input (kx-major)
+  cd* X_out;           // ROW_FWD row-transformed output (kx-major)
+  double* partial;     // ROW_MU: 2 per workgroup (E_1 density, energy density), nullable
+  StepCtl* ctl;
+  const cd* tw;        // exp(-2 pi i m / N), m < N
+};
+
+struct ColArgs {
+  Consts c;
+  cd* P0;
+  cd* P1;
+  const cd* s0;     // state / field input (u^n, u, u~)
+  const cd* s1;     // second input (u^{n-1}, or u^n for EPI_AM3)
+  cd* out;          // output (u^{n+1}, mu, F, PSD iterate); may alias s1
+  cd* aux;          // SAV q, PSD b u^n + c u^{n-1}
+  const cd* guess;  // PSD initial guess (nullable)
+  const cd* f_n;    // AM3 F^n
+  const cd* f_nm1;  // AM3 F^{n-1}
+  const cd* X_in;   // single-field column transform input
+  cd* X_out;        // single-field column transform output
+  double* partial;  // 2 per column
+  StepCtl* ctl;
+  const cd* tw;
+};
+
+struct FinArgs {
+  Consts c;
+  const double* rpart;  // row partials (2 per row workgroup)
+  int nrow;
+  const double* cpart;  // column partials (2 per column)
+  int ncol;
+  StepCtl* ctl;
+  int mode;
+};
+
+// Launch table of one compiled configuration for one grid size.
+struct VTable {
+  int N, row_R, row_E, col_E;
+  int row_threads, col_threads;
+  hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s);
+  hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s);
+  hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s);
+  hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s);
+};
+
+// registry (fch_kernels.hip)
+int vtable_count(int N);
+const VTable* vtable_get(int N, int i);
+
+hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s);
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s);
+
+}  // namespace fch

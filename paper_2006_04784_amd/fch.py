@@ -1,0 +1,336 @@
+"""ctypes binding of the HIP library ``libfch.so`` (C ABI in include/fch.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  Spectral
+tensors are complex128 of shape (N//2+1, N) (kx-major half spectrum);
+physical tensors are float64 of shape (N, N).  Nothing here falls back to a
+CPU implementation: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfch.so")
+_lib = None
+
+FCH_OK, FCH_E_INVALID, FCH_E_UNSUPPORTED, FCH_E_HIP, FCH_E_NOMEM, FCH_E_NOCONV, FCH_E_NONFINITE = \
+    0, -1, -2, -3, -4, -5, -6
+FCH_IMEX, FCH_SAV, FCH_PSD = 0, 1, 2
+
+
+class FchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (status %d)" % (msg, code))
+        self.code = code
+
+
+class fch_params(C.Structure):
+    _fields_ = [("N", C.c_int32), ("L", C.c_double), ("eps", C.c_double),
+                ("eta1", C.c_double), ("eta2", C.c_double), ("p", C.c_int32),
+                ("q", C.c_double), ("gamma_w", C.c_double), ("b_minus", C.c_double),
+                ("b_plus", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("zeta", C.c_double), ("D0", C.c_double)]
+
+
+class fch_launch_cfg(C.Structure):
+    _fields_ = [("row_R", C.c_int32), ("row_E", C.c_int32), ("col_E", C.c_int32)]
+
+
+class fch_stats(C.Structure):
+    _fields_ = [("fft_calls", C.c_int64), ("launches", C.c_int64), ("psd_iters", C.c_int64),
+                ("steps", C.c_int64), ("rejected", C.c_int64)]
+
+
+class fch_psd_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("lambda_", C.c_double),
+                ("fixed_iters", C.c_int32)]
+
+
+class fch_psd_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("fft_calls", C.c_int64), ("last_ratio", C.c_double)]
+
+
+class fch_adapt_opts(C.Structure):
+    _fields_ = [("sigma_tol", C.c_double), ("k_min", C.c_double), ("k_max", C.c_double),
+                ("rho_s", C.c_double), ("cap", C.c_double)]
+
+
+class fch_run_opts(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("adaptive", C.c_int32), ("startup", C.c_int32),
+                ("nsteps", C.c_int64), ("k", C.c_double), ("k_prev", C.c_double),
+                ("k_first", C.c_double), ("t_end", C.c_double), ("adapt", fch_adapt_opts),
+                ("psd", fch_psd_opts)]
+
+
+class fch_run_info(C.Structure):
+    _fields_ = [("accepted", C.c_int64), ("rejected", C.c_int64), ("psd_iters", C.c_int64),
+                ("fft_calls", C.c_int64), ("t", C.c_double), ("k_last", C.c_double),
+                ("k_next", C.c_double)]
+
+
+_V = C.c_void_p
+_D = C.c_double
+_I = C.c_int32
+_PD = C.POINTER(C.c_double)
+_PI = C.POINTER(C.c_int32)
+
+_SIGS = {
+    "fch_sav_constants": (_I, [C.POINTER(fch_params), _PD, _PD]),
+    "fch_alpha_m": (_D, [C.POINTER(fch_params)]),
+    "fch_plan_create": (_I, [C.POINTER(fch_params), C.POINTER(_V)]),
+    "fch_plan_destroy": (_I, [_V]),
+    "fch_plan_set_stream": (_I, [_V, _V]),
+    "fch_plan_workspace_bytes": (C.c_size_t, [_V]),
+    "fch_plan_set_workspace": (_I, [_V, _V, C.c_size_t]),
+    "fch_plan_set_config": (_I, [_V, C.POINTER(fch_launch_cfg)]),
+    "fch_plan_get_config": (_I, [_V, C.POINTER(fch_launch_cfg)]),
+    "fch_config_count": (_I, [_I]),
+    "fch_config_get": (_I, [_I, _I, C.POINTER(fch_launch_cfg)]),
+    "fch_plan_stats": (_I, [_V, C.POINTER(fch_stats)]),
+    "fch_plan_reset_stats": (_I, [_V]),
+    "fch_forward": (_I, [_V, _V, _V]),
+    "fch_inverse": (_I, [_V, _V, _V]),
+    "fch_chem_potential": (_I, [_V, _V, _V, _PD]),
+    "fch_step_imex": (_I, [_V, _V, _V, _D, _D, _V]),
+    "fch_step_sav": (_I, [_V, _V, _V, _D, _D, _D, _D, _V, _PD]),
+    "fch_sav_r": (_I, [_V, _V, _PD]),
+    "fch_step_psd": (_I, [_V, _V, _V, _D, _D, _V, C.POINTER(fch_psd_opts), _V,
+                          C.POINTER(fch_psd_stats)]),
+    "fch_adapt_dt": (_I, [_V, _V, _V, _V, _V, _D, _D, C.POINTER(fch_adapt_opts), _V, _PI,
+                          _PD, _PD]),
+    "fch_rhs": (_I, [_V, _V, _V]),
+    "fch_run": (_I, [_V, C.POINTER(fch_run_opts), _V, _V, _PD, C.POINTER(fch_run_info)]),
+    "fch_status_string": (C.c_char_p, [_I]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libfch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != FCH_OK:
+        raise FchError(code, lib().fch_status_string(code).decode())
+
+
+def _p(t):
+    return None if t is None else _V(t.data_ptr())
+
+
+def sav_constants(prm: fch_params):
+    z, d = C.c_double(), C.c_double()
+    _check(lib().fch_sav_constants(C.byref(prm), C.byref(z), C.byref(d)))
+    return z.value, d.value
+
+
+def config_list(N: int):
+    out = []
+    for i in range(lib().fch_config_count(N)):
+        c = fch_launch_cfg()
+        _check(lib().fch_config_get(N, i, C.byref(c)))
+        out.append((c.row_R, c.row_E, c.col_E))
+    return out
+
+
+@dataclass
+class AdaptOpts:
+    sigma_tol: float = 1e-5
+    k_min: float = 1e-9
+    k_max: float = float("inf")
+    rho_s: float = 0.9
+    cap: float = 1.0 + 2.0 ** 0.5
+
+    def c(self):
+        return fch_adapt_opts(self.sigma_tol, self.k_min, self.k_max, self.rho_s, self.cap)
+
+
+class Plan:
+    """A plan for one grid size and parameter set on one device."""
+
+    def __init__(self, N, L, eps, eta1, eta2, p=1, q=0.0, gamma_w=0.3, b_minus=-1.0,
+                 b_plus=1.0, beta1=2.0, beta2=1.0, zeta=None, D0=None, device="cuda:0"):
+        self.device = torch.device(device)
+        prm = fch_params(N, L, eps, eta1, eta2, p, q, gamma_w, b_minus, b_plus, beta1, beta2,
+                         0.0, 0.0)
+        if zeta is None or D0 is None:
+            z, d = sav_constants(prm)
+            zeta = z if zeta is None else zeta
+            D0 = d if D0 is None else D0
+        prm.zeta, prm.D0 = zeta, D0
+        self.prm = prm
+        self.N, self.H = N, N // 2 + 1
+        h = _V()
+        with torch.cuda.device(self.device):
+            _check(lib().fch_plan_create(C.byref(prm), C.byref(h)))
+        self.h = h
+        nbytes = lib().fch_plan_workspace_bytes(h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        _check(lib().fch_plan_set_workspace(h, _V(self.ws.data_ptr() + off), nbytes))
+
+    # -- plumbing -------------------------------------------------------
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().fch_plan_set_stream(self.h, _V(s)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fch_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spec(self):
+        return torch.empty((self.H, self.N), dtype=torch.complex128, device=self.device)
+
+    def phys(self):
+        return torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
+
+    def _chk_spec(self, *ts):
+        for t in ts:
+            if t is None:
+                continue
+            if t.dtype != torch.complex128 or tuple(t.shape) != (self.H, self.N) or \
+                    not t.is_contiguous() or t.device != self.device:
+                raise ValueError("expected contiguous complex128 (%d, %d) on %s" %
+                                 (self.H, self.N, self.device))
+
+    def alpha_m(self):
+        return lib().fch_alpha_m(C.byref(self.prm))
+
+    def set_config(self, cfg):
+        c = None if cfg is None else fch_launch_cfg(*cfg)
+        _check(lib().fch_plan_set_config(self.h, None if c is None else C.byref(c)))
+
+    def get_config(self):
+        c = fch_launch_cfg()
+        _check(lib().fch_plan_get_config(self.h, C.byref(c)))
+        return (c.row_R, c.row_E, c.col_E)
+
+    def stats(self):
+        s = fch_stats()
+        _check(lib().fch_plan_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in fch_stats._fields_}
+
+    def reset_stats(self):
+        _check(lib().fch_plan_reset_stats(self.h))
+
+    # -- calls (same names as the C ABI, minus the prefix) -----------------
+    def forward(self, u, out=None):
+        if u.dtype != torch.float64 or tuple(u.shape) != (self.N, self.N) or not u.is_contiguous():
+            raise ValueError("expected contiguous float64 (N, N)")
+        out = self.spec() if out is None else out
+        self._sync_stream()
+        _check(lib().fch_forward(self.h, _p(u), _p(out)))
+        return out
+
+    def inverse(self, uh, out=None):
+        self._chk_spec(uh)
+        out = self.phys() if out is None else out
+        self._sync_stream()
+        _check(lib().fch_inverse(self.h, _p(uh), _p(out)))
+        return out
+
+    def chem_potential(self, uh, out=None, energy=False):
+        self._chk_spec(uh)
+        out = self.spec() if out is None else out
+        e = C.c_double()
+        self._sync_stream()
+        _check(lib().fch_chem_potential(self.h, _p(uh), _p(out), C.byref(e) if energy else None))
+        return (out, e.value) if energy else out
+
+    def rhs(self, uh, out=None):
+        self._chk_spec(uh)
+        out = self.spec() if out is None else out
+        self._sync_stream()
+        _check(lib().fch_rhs(self.h, _p(uh), _p(out)))
+        return out
+
+    def step_imex(self, uh_n, uh_nm1, k_np1, k_n, out=None):
+        self._chk_spec(uh_n, uh_nm1)
+        out = self.spec() if out is None else out
+        self._sync_stream()
+        _check(lib().fch_step_imex(self.h, _p(uh_n), _p(uh_nm1), k_np1, k_n, _p(out)))
+        return out
+
+    def sav_r(self, uh):
+        self._chk_spec(uh)
+        r = C.c_double()
+        self._sync_stream()
+        _check(lib().fch_sav_r(self.h, _p(uh), C.byref(r)))
+        return r.value
+
+    def step_sav(self, uh_n, uh_nm1, r_n, r_nm1, k_np1, k_n, out=None):
+        self._chk_spec(uh_n, uh_nm1)
+        out = self.spec() if out is None else out
+        r = C.c_double()
+        self._sync_stream()
+        _check(lib().fch_step_sav(self.h, _p(uh_n), _p(uh_nm1), r_n, r_nm1, k_np1, k_n, _p(out),
+                                  C.byref(r)))
+        return out, r.value
+
+    def step_psd(self, uh_n, uh_nm1, k_np1, k_n, guess=None, tol=1e-10, max_iter=1000,
+                 lam=0.0, fixed_iters=0, out=None, raise_noconv=True):
+        self._chk_spec(uh_n, uh_nm1, guess)
+        out = self.spec() if out is None else out
+        o = fch_psd_opts(tol, max_iter, lam, fixed_iters)
+        st = fch_psd_stats()
+        self._sync_stream()
+        code = lib().fch_step_psd(self.h, _p(uh_n), _p(uh_nm1), k_np1, k_n, _p(guess),
+                                  C.byref(o), _p(out), C.byref(st))
+        if code != FCH_E_NOCONV or raise_noconv:
+            _check(code)
+        return out, {"iters": st.iters, "fft_calls": st.fft_calls,
+                     "last_ratio": st.last_ratio, "status": code}
+
+    def adapt_dt(self, uh_trial, uh_n, F_n, F_nm1, k_trial, k_n, opts: AdaptOpts = None,
+                 out=None):
+        self._chk_spec(uh_trial, uh_n, F_n, F_nm1)
+        out = self.spec() if out is None else out
+        o = (opts or AdaptOpts()).c()
+        acc, kn, err = C.c_int32(), C.c_double(), C.c_double()
+        self._sync_stream()
+        _check(lib().fch_adapt_dt(self.h, _p(uh_trial), _p(uh_n), _p(F_n), _p(F_nm1), k_trial,
+                                  k_n, C.byref(o), _p(out), C.byref(acc), C.byref(kn),
+                                  C.byref(err)))
+        return out, bool(acc.value), kn.value, err.value
+
+    def run(self, uh_n, uh_nm1, scheme="imex", adaptive=False, startup=True, nsteps=0, k=1e-3,
+            k_prev=0.0, k_first=0.0, t_end=0.0, adapt: AdaptOpts = None, psd_tol=1e-10,
+            psd_max_iter=1000, psd_lambda=0.0, rs=None):
+        self._chk_spec(uh_n, uh_nm1)
+        sch = {"imex": FCH_IMEX, "sav": FCH_SAV, "psd": FCH_PSD}[scheme]
+        o = fch_run_opts(sch, int(adaptive), int(startup), nsteps, k, k_prev, k_first, t_end,
+                         (adapt or AdaptOpts()).c(),
+                         fch_psd_opts(psd_tol, psd_max_iter, psd_lambda, 0))
+        r = (C.c_double * 2)(*(rs if rs is not None else (0.0, 0.0)))
+        info = fch_run_info()
+        self._sync_stream()
+        _check(lib().fch_run(self.h, C.byref(o), _p(uh_n), _p(uh_nm1),
+                             C.cast(r, _PD), C.byref(info)))
+        d = {k_: getattr(info, k_) for k_, _ in fch_run_info._fields_}
+        d["rs"] = (r[0], r[1])
+        return d

@@ -1,0 +1,82 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/fch.h declares, and its host-only entry points behave (argument
+validation, compiled launch configurations, alpha_m against Table
+t:Benchmark, the SAV constants of the documented reading)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fch.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fch_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def fch():
+    from paper_2006_04784_amd import fch as F
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("libfch.so not built")
+    return F
+
+
+def test_exports_every_declared_symbol(fch):
+    lib = fch.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in fch.EXPORTED, n
+
+
+def test_status_strings(fch):
+    for code in range(-6, 1):
+        assert fch.lib().fch_status_string(code)
+
+
+def _prm(fch, **kw):
+    base = dict(N=64, L=4 * np.pi, eps=0.1, eta1=1.45, eta2=2.0, p=1, q=0.0, gamma_w=0.3,
+                b_minus=-1.0, b_plus=1.0, beta1=2.0, beta2=1.0, zeta=1.1, D0=163.0)
+    base.update(kw)
+    return fch.fch_params(*[base[k] for k, _ in fch.fch_params._fields_])
+
+
+def test_alpha_m_table1(fch):
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "table1_alpha_m.txt"))
+    for q, eps, alpha in rows:
+        assert abs(fch.lib().fch_alpha_m(C.byref(_prm(fch, q=q, eps=eps))) - alpha) < 1e-13
+
+
+def test_sav_constants_reading(fch):
+    # q = 0: min W'' = -1.0075 at u = -0.05, so zeta = 1.1; the C1 box
+    # (L = 4 pi, eta2_eff = 0.2) has min (W'^2/2 - eta2 W) ~ -0.0322
+    z, d = fch.sav_constants(_prm(fch))
+    assert z == pytest.approx(1.1)
+    L = 4 * np.pi
+    assert d == pytest.approx(L * L * 1.0322, rel=2e-4)
+
+
+def test_plan_create_rejects_bad_params_before_touching_the_device(fch):
+    h = C.c_void_p()
+    for kw, code in [(dict(N=48), fch.FCH_E_INVALID), (dict(N=8), fch.FCH_E_UNSUPPORTED),
+                     (dict(N=4096), fch.FCH_E_UNSUPPORTED), (dict(L=-1.0), fch.FCH_E_INVALID),
+                     (dict(eps=0.0), fch.FCH_E_INVALID), (dict(q=-0.1), fch.FCH_E_INVALID),
+                     (dict(eta1=float("nan")), fch.FCH_E_INVALID)]:
+        assert fch.lib().fch_plan_create(C.byref(_prm(fch, **kw)), C.byref(h)) == code, kw
+    assert fch.lib().fch_plan_create(None, C.byref(h)) == fch.FCH_E_INVALID
+
+
+def test_compiled_configurations(fch):
+    for N in (16, 32, 64, 128, 256, 512, 1024, 2048):
+        cfgs = fch.config_list(N)
+        assert cfgs, N
+        for (R, rE, cE) in cfgs:
+            assert N % rE == 0 and N % cE == 0 and N % (2 * R) == 0
+    assert fch.lib().fch_config_count(4096) == 0
+    assert fch.lib().fch_config_count(100) == 0
