@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the FCH pseudo-spectral BDF2 hot path on one MI355X.
+
+Headline: fixed-step BDF2-IMEX steps/s on the 1024^2 FP64 workload (one
+circular bilayer on [0, 16 pi]^2, eps = 0.1, k = 1e-3), inputs resident in
+HBM.  A step is one chemical-potential evaluation (4 real 2D transforms with
+the pointwise well fused in) plus the IMEX diagonal solve, run as the fused
+launch chain (row pass, column pass) of the library.
+
+The same JSON line carries:
+  roofline     -- the dominant kernel's algorithmic bytes per launch over its
+                  average duration (HIP events on the plan's stream during a
+                  second, instrumented pass of the same steps), against 8 TB/s;
+                  traffic from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+                  summary when it was taken on the current kernel source;
+  cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
+  extra        -- SAV steps/s, adaptive IMEX accepted steps/s, PSD iterations/s
+                  and FFT calls per PSD step, 2D FFT GB/s on a 32-field batch.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def spec_bytes(N):
+    return 16 * N * (N // 2 + 1)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fch_kernels.hip", "fch_device.hpp", "fch_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2006_04784_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_class):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_m1_imex.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        m = re.match(r"\s*([a-z_0-9]+)\s*:\s*(\S+)", line)
+        if m:
+            kv[m.group(1)] = m.group(2)
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    key = "%s_bytes_per_launch" % kernel_class
+    return float(kv[key]) if key in kv else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip SAV/PSD/adaptive/FFT extras")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2006_04784_amd import fch, inputs
+
+    dev = torch.device("cuda:0")
+    kw, u0 = inputs.workload("m1")
+    N = kw["N"]
+    k = 1e-3
+    plan = fch.Plan(**kw, device=dev)
+    S = spec_bytes(N)
+
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    log("m1 1024^2: forward transform and startup step")
+    uh0 = plan.forward(torch.from_numpy(u0).to(dev))
+    a, b = uh0.clone(), torch.empty_like(uh0)
+    plan.run(a, b, scheme="imex", nsteps=1, k=k, startup=True)
+    log("warmup %d steps" % args.warmup)
+    plan.run(a, b, scheme="imex", nsteps=args.warmup, k=k, k_prev=k, startup=False)
+    torch.cuda.synchronize()
+
+    log("timed %d steps" % args.steps)
+    t0 = time.perf_counter()
+    plan.run(a, b, scheme="imex", nsteps=args.steps, k=k, k_prev=k, startup=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    steps_per_s = args.steps / dt
+    ms_per_step = 1e3 * dt / args.steps
+    if not torch.isfinite(a).all():
+        raise RuntimeError("non-finite state after the timed run")
+
+    # ---- roofline: per-kernel durations from HIP events -----------------
+    log("instrumented pass (HIP events per launch)")
+    nprof = min(args.steps, 4000)
+    plan.profile(True)
+    plan.run(a, b, scheme="imex", nsteps=nprof, k=k, k_prev=k, startup=False)
+    prof = plan.profile_read()
+    plan.profile(False)
+    row_n, row_ms = prof["row_mu"]
+    col_n, col_ms = prof["col_fused"]
+    row_avg = row_ms / max(row_n, 1) * 1e-3
+    col_avg = col_ms / max(col_n, 1) * 1e-3
+    kernels = {
+        # algorithmic bytes per launch (each half spectrum S = 16 N (N/2+1) B)
+        "row_mu": {"bytes": 4 * S, "avg_s": row_avg, "count": row_n},
+        "col_imex_fused": {"bytes": 7 * S, "avg_s": col_avg, "count": col_n},
+    }
+    dom = max(kernels, key=lambda kk: kernels[kk]["avg_s"] * max(kernels[kk]["count"], 1))
+    kd = kernels[dom]
+    achieved = kd["bytes"] / kd["avg_s"] / 1e9
+    traffic = read_traffic(dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": kd["bytes"], "avg_us": round(kd["avg_s"] * 1e6, 3),
+                "other_kernels": {kk: {"avg_us": round(v["avg_s"] * 1e6, 3),
+                                       "bytes_per_launch": v["bytes"],
+                                       "GBps": round(v["bytes"] / v["avg_s"] / 1e9, 1)}
+                                  for kk, v in kernels.items()},
+                "step_bytes": 11 * S,
+                "step_GBps": round(11 * S * steps_per_s / 1e9, 1)}
+
+    extra = {}
+    if not args.no_extra:
+        # SAV, fixed step
+        log("SAV fixed step")
+        rs = [plan.sav_r(a), 0.0]
+        rs[1] = rs[0]
+        a2, b2 = a.clone(), b.clone()
+        plan.run(a2, b2, scheme="sav", nsteps=20, k=k, k_prev=k, startup=False, rs=rs)
+        torch.cuda.synchronize()
+        ns = 200
+        t0 = time.perf_counter()
+        plan.run(a2, b2, scheme="sav", nsteps=ns, k=k, k_prev=k, startup=False, rs=rs)
+        torch.cuda.synchronize()
+        extra["sav_steps_per_s"] = round(ns / (time.perf_counter() - t0), 1)
+        # adaptive IMEX (AM3 error control, sigma_tol 1e-5)
+        log("adaptive IMEX")
+        a2, b2 = uh0.clone(), torch.empty_like(uh0)
+        opts = fch.AdaptOpts(sigma_tol=1e-5)
+        plan.run(a2, b2, scheme="imex", adaptive=True, startup=True, t_end=1.0, nsteps=50,
+                 adapt=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = plan.run(a2, b2, scheme="imex", adaptive=True, startup=True, t_end=10.0,
+                        nsteps=300, adapt=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        extra["adaptive_imex_accepted_steps_per_s"] = round(info["accepted"] / el, 1)
+        extra["adaptive_imex_attempts_per_s"] = round(
+            (info["accepted"] + info["rejected"]) / el, 1)
+        # PSD (i_tol 1e-10, lambda from Table SearchSize)
+        log("PSD")
+        a2, b2 = a.clone(), b.clone()
+        plan.reset_stats()
+        t0 = time.perf_counter()
+        npsd = 10
+        info = plan.run(a2, b2, scheme="psd", nsteps=npsd, k=k, k_prev=k, startup=False,
+                        psd_tol=1e-10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        extra["psd_iterations_per_s"] = round(info["psd_iters"] / el, 1)
+        extra["psd_fft_calls_per_step"] = round(4.0 * info["psd_iters"] / npsd, 2)
+        extra["psd_steps_per_s"] = round(npsd / el, 1)
+        # 2D FFT bandwidth on a 32-field batch (537 MB, larger than the MALL)
+        log("FFT batch of 32 x 1024^2")
+        B = 32
+        U = torch.randn((B, N, N), dtype=torch.float64, device=dev)
+        Uh = torch.empty((B, N // 2 + 1, N), dtype=torch.complex128, device=dev)
+        for i in range(B):
+            plan.forward(U[i], out=Uh[i])
+            plan.inverse(Uh[i], out=U[i])
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for i in range(B):
+                plan.forward(U[i], out=Uh[i])
+                plan.inverse(Uh[i], out=U[i])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        per_fft = el / (2 * B * reps)
+        fft_bytes = 8 * N * N + 3 * S
+        extra["fft2d_real_us"] = round(per_fft * 1e6, 2)
+        extra["fft2d_GBps"] = round(fft_bytes / per_fft / 1e9, 1)
+        extra["fft2d_bytes"] = fft_bytes
+        del U, Uh
+    if args.copy_probe:
+        # a plain elementwise copy of known size: 256 MiB read, 256 MiB written
+        x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (bounded sample)")
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = max(1, min(threads, os.cpu_count() or 1))
+        oracle.set_threads(threads)
+        m = oracle.Model(**kw, zeta=plan.prm.zeta, D0=plan.prm.D0)
+        un = oracle.r2c(u0)
+        um = un.copy()
+        n_done, t_cpu = 0, 0.0
+        while t_cpu < 15.0 and n_done < 200:
+            t0 = time.perf_counter()
+            nxt = oracle.imex_step(m, un, um, k, k if n_done else -1.0)
+            t_cpu += time.perf_counter() - t0
+            um, un = un, nxt
+            n_done += 1
+        cpu = {"value": round(n_done / t_cpu, 4), "unit": "steps/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "%d BDF2-IMEX steps of the 1024^2 workload (first is the startup "
+                         "step), C oracle with OpenMP over FFT lines" % n_done}
+
+    out = {
+        "metric": "BDF2 steps/s and FFT HBM GB/s (FP64, 1024²); PSD FFT calls/step "
+                  "learned vs plain",
+        "value": round(steps_per_s, 2),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "m1: FCH 1024^2 on [0,16pi]^2, eps 0.1, eta (1.45, 2.0) eps, "
+                               "q 0, fixed-step BDF2-IMEX k=1e-3, one circular bilayer r=0.3L",
+                   "N": N, "scheme": "imex", "k": k,
+                   "launch_config": list(plan.get_config())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -110,6 +110,17 @@ typedef struct {
 fch_status fch_plan_stats(fch_plan_t plan, fch_stats* out);   /* host out */
 fch_status fch_plan_reset_stats(fch_plan_t plan);
 
+/* Kernel timing.  While enabled, every row-pass and column-pass launch is
+ * bracketed by HIP events on the plan's stream (up to 16384 launches; later
+ * launches are not timed).  fch_plan_profile_read waits for the stream, sums
+ * the elapsed times per kernel class and clears the records.  Classes:
+ * 0 row pass (pointwise chemical potential), 1 column pass (forward FFT +
+ * epilogue + inverse FFT), 2 column pass (one direction only),
+ * 3 single-field transforms (fch_forward / fch_inverse passes). */
+typedef struct { int64_t count[4]; double ms[4]; } fch_profile;
+fch_status fch_plan_profile(fch_plan_t plan, int32_t enable);
+fch_status fch_plan_profile_read(fch_plan_t plan, fch_profile* out);
+
 /* ---- transforms (pseudo-spectral discretization, Sec. 2.3 / Sec. 3) ------ */
 /* uh = DFT(u), unnormalized.  u: N*N doubles; uh: (N/2+1)*N complex. */
 fch_status fch_forward(fch_plan_t plan, const double* u, fch_c128* uh);

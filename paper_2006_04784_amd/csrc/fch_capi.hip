@@ -33,6 +33,11 @@ struct fch_plan_s {
   double *rpart, *cpart;
   fch_stats stats;
   int psd_hint;
+  // kernel timing (fch_plan_profile)
+  int prof_on;
+  int prof_n;
+  hipEvent_t* prof_ev;    // 2 per record
+  int* prof_kind;
 };
 
 namespace {
@@ -194,8 +199,25 @@ fch_status readback(fch_plan_s* p) {
   return FCH_OK;
 }
 
+constexpr int kProfCap = 16384;
+
+// bracket the next launch with events when timing is on; returns the record
+int prof_begin(fch_plan_s* p, int kind) {
+  if (!p->prof_on || p->prof_n >= kProfCap) return -1;
+  const int i = p->prof_n++;
+  p->prof_kind[i] = kind;
+  (void)hipEventRecord(p->prof_ev[2 * i], p->stream);
+  return i;
+}
+void prof_end(fch_plan_s* p, int i) {
+  if (i >= 0) (void)hipEventRecord(p->prof_ev[2 * i + 1], p->stream);
+}
+
 fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
+  const int kind = (epi != fch::EPI_NONE && pro != fch::PRO_NONE) ? 1 : 2;
+  const int r = prof_begin(p, kind);
   HIPCHK(p->vt->col(epi, pro, a, p->stream));
+  prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
 }
@@ -203,7 +225,9 @@ fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
 fch_status row_mu(fch_plan_s* p, double* partial) {
   RowArgs a = row_args(p);
   a.partial = partial;
+  const int r = prof_begin(p, 0);
   HIPCHK(p->vt->row(fch::ROW_MU, a, p->stream));
+  prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
 }
@@ -362,8 +386,39 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
   return FCH_OK;
 }
 
+fch_status fch_plan_profile(fch_plan_t p, int32_t enable) {
+  if (!p) return FCH_E_INVALID;
+  if (enable && !p->prof_ev) {
+    p->prof_ev = new (std::nothrow) hipEvent_t[2 * kProfCap];
+    p->prof_kind = new (std::nothrow) int[kProfCap];
+    if (!p->prof_ev || !p->prof_kind) return FCH_E_NOMEM;
+    for (int i = 0; i < 2 * kProfCap; ++i) HIPCHK(hipEventCreate(&p->prof_ev[i]));
+  }
+  p->prof_on = enable ? 1 : 0;
+  return FCH_OK;
+}
+
+fch_status fch_plan_profile_read(fch_plan_t p, fch_profile* out) {
+  if (!p || !out) return FCH_E_INVALID;
+  std::memset(out, 0, sizeof(*out));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < p->prof_n; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]));
+    out->count[p->prof_kind[i]] += 1;
+    out->ms[p->prof_kind[i]] += ms;
+  }
+  p->prof_n = 0;
+  return FCH_OK;
+}
+
 fch_status fch_plan_destroy(fch_plan_t p) {
   if (!p) return FCH_E_INVALID;
+  if (p->prof_ev) {
+    for (int i = 0; i < 2 * kProfCap; ++i) (void)hipEventDestroy(p->prof_ev[i]);
+    delete[] p->prof_ev;
+    delete[] p->prof_kind;
+  }
   if (p->tw) (void)hipFree(p->tw);
   if (p->ctl) (void)hipFree(p->ctl);
   if (p->hctl) (void)hipHostFree(p->hctl);
@@ -441,11 +496,15 @@ fch_status fch_forward(fch_plan_t p, const double* u, fch_c128* uh) {
   RowArgs r = row_args(p);
   r.u_in = u;
   r.X_out = p->P0;
+  int pr = prof_begin(p, 3);
   HIPCHK(p->vt->row(fch::ROW_FWD, r, p->stream));
+  prof_end(p, pr);
   ColArgs a = col_args(p);
   a.X_in = p->P0;
   a.X_out = (cd*)uh;
+  pr = prof_begin(p, 3);
   HIPCHK(p->vt->col_fwd1(a, p->stream));
+  prof_end(p, pr);
   p->stats.launches += 2;
   p->stats.fft_calls += 1;
   return FCH_OK;
@@ -457,11 +516,15 @@ fch_status fch_inverse(fch_plan_t p, const fch_c128* uh, double* u) {
   ColArgs a = col_args(p);
   a.X_in = (const cd*)uh;
   a.X_out = p->P0;
+  int pr = prof_begin(p, 3);
   HIPCHK(p->vt->col_inv1(a, p->stream));
+  prof_end(p, pr);
   RowArgs r = row_args(p);
   r.X_in = p->P0;
   r.u_out = u;
+  pr = prof_begin(p, 3);
   HIPCHK(p->vt->row(fch::ROW_INV, r, p->stream));
+  prof_end(p, pr);
   p->stats.launches += 2;
   p->stats.fft_calls += 1;
   return FCH_OK;

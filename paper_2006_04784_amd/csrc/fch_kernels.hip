@@ -171,6 +171,33 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
 // ===========================================================================
 // Column pass
 // ===========================================================================
+
+// Columns kx = 0 and kx = N/2 of the half spectrum of a real field obey
+// U(ky) = conj U(N - ky).  Rounding in the column FFTs breaks this slightly;
+// the explicit linear terms of the schemes act on that non-real component
+// while the pointwise terms (computed from real fields) never see it, so it
+// would grow from step to step.  Every state written by a column pass is
+// therefore projected: U(ky) <- (U(ky) + conj U(N - ky)) / 2, exchanging
+// partners through LDS.  Call only where kx is 0 or N/2 (uniform per group).
+// (the first NF of the NV register fields are projected)
+template <int N, int E, int NF, int NV>
+__device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd (*lds)[N], int t) {
+  constexpr int T = N / E;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NF; ++q)
+#pragma unroll
+    for (int s = 0; s < E; ++s) lds[q][t + s * T] = f[q][s];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NF; ++q)
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const cd p = lds[q][(N - (t + s * T)) & (N - 1)];
+      f[q][s] = cd{0.5 * (f[q][s].x + p.x), 0.5 * (f[q][s].y - p.y)};
+    }
+  __syncthreads();
+}
 template <int N, int E, int EPI, int PRO>
 __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
   constexpr int T = N / E;
@@ -203,6 +230,10 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
     }
     fft<N, E, 2, -1>(v, base, tw, t);
 
+    // epilogue values: o[0] the state / output, o[1] the SAV q; Ua holds the
+    // field U and un (u^n) where later terms need them
+    cd o[2][E];
+    cd Ua[E], una[E], uma[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       const int ky = t + s * T;
@@ -222,27 +253,23 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
       } else {
         U = a.s0[g];
       }
+      Ua[s] = U;
+      una[s] = un;
+      uma[s] = um;
       // mu = -eps^2 |k|^2 omega + p - eps^2 eta1 |k|^2 U
       const cd mu = {-e2k2 * om.x + pp.x - e2k2 * c.eta1 * U.x,
                      -e2k2 * om.y + pp.y - e2k2 * c.eta1 * U.y};
       if constexpr (EPI == EPI_MU) {
-        a.out[g] = mu;
+        o[0][s] = mu;
         acc[0] += wgt * k2 * cnorm2(U);
-        unext[s] = U;
       } else if constexpr (EPI == EPI_F) {
-        a.out[g] = cscale(mu, -k2);
-        unext[s] = U;
+        o[0][s] = cscale(mu, -k2);
       } else if constexpr (EPI == EPI_IMEX) {
         const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
         const cd Nh = csub(mu, cscale(U, Lk));
         const double inv = 1.0 / (ctl->a + k2 * Lk);
-        const cd un1 = {(-ctl->b * un.x - ctl->c * um.x - k2 * Nh.x) * inv,
-                        (-ctl->b * un.y - ctl->c * um.y - k2 * Nh.y) * inv};
-        a.out[g] = un1;
-        if constexpr (PRO == PRO_NEXT_EXTRAP)
-          unext[s] = cadd(un1, cscale(csub(un1, un), ctl->gamma));
-        else
-          unext[s] = un1;
+        o[0][s] = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * Nh.x) * inv,
+                     (-ctl->b * un.y - ctl->c * um.y - k2 * Nh.y) * inv};
       } else if constexpr (EPI == EPI_SAV) {
         const double lsav = e2k2 * e2k2 - e2k2 * (c.eta1 + 2.0 * c.zeta);
         const double inv_s = 1.0 / ctl->s_star;
@@ -251,15 +278,10 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
         const double L1 = -e2k2 * (c.eta1 + 2.0 * c.zeta) - c.beta1 * c.alpha * e2k2 -
                           c.beta2 * c.alpha * c.alpha;
         const double inv = 1.0 / (ctl->a + k2 * L0);
-        const cd p = {(-ctl->b * un.x - ctl->c * um.x - k2 * L1 * U.x) * inv,
-                      (-ctl->b * un.y - ctl->c * um.y - k2 * L1 * U.y) * inv};
-        const cd qv = cscale(X, -k2 * inv);
-        a.out[g] = p;
-        a.aux[g] = qv;
-        const cd rp = {ctl->a * p.x + ctl->b * un.x + ctl->c * um.x,
-                       ctl->a * p.y + ctl->b * un.y + ctl->c * um.y};
-        acc[0] += wgt * cdotr(X, rp);
-        acc[1] += wgt * cdotr(X, qv);
+        o[0][s] = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * L1 * U.x) * inv,
+                     (-ctl->b * un.y - ctl->c * um.y - k2 * L1 * U.y) * inv};
+        o[1][s] = cscale(X, -k2 * inv);
+        Ua[s] = X;  // the SAV sums need X
       } else if constexpr (EPI == EPI_PSD) {
         const cd G = a.aux[g];
         cd d = {0.0, 0.0};
@@ -268,18 +290,46 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
           const double inv = -1.0 / (k2 * Lk + ctl->a);
           d = cd{(k2 * mu.x + ctl->a * U.x + G.x) * inv, (k2 * mu.y + ctl->a * U.y + G.y) * inv};
         }
-        const cd u1 = cadd(U, cscale(d, ctl->lambda));
-        a.out[g] = u1;
-        acc[0] += wgt * cnorm2(d);
-        acc[1] += wgt * cnorm2(u1);
-        unext[s] = u1;
+        o[0][s] = cadd(U, cscale(d, ctl->lambda));
+        o[1][s] = d;
       } else if constexpr (EPI == EPI_AM3) {
-        const cd F = cscale(mu, -k2);
-        a.out[g] = F;
+        o[0][s] = cscale(mu, -k2);
+      }
+    }
+    // states written by this pass are spectra of real fields (see hermitian_fix)
+    if constexpr (EPI == EPI_IMEX || EPI == EPI_PSD) {
+      if (kx == 0 || kx == M) hermitian_fix<N, E, 1, 2>(o, buf, t);
+    } else if constexpr (EPI == EPI_SAV) {
+      if (kx == 0 || kx == M) hermitian_fix<N, E, 2, 2>(o, buf, t);
+    }
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const size_t g = col + t + s * T;
+      a.out[g] = o[0][s];
+      if constexpr (EPI == EPI_MU || EPI == EPI_F) {
+        unext[s] = Ua[s];
+      } else if constexpr (EPI == EPI_IMEX) {
+        if constexpr (PRO == PRO_NEXT_EXTRAP)
+          unext[s] = cadd(o[0][s], cscale(csub(o[0][s], una[s]), ctl->gamma));
+        else
+          unext[s] = o[0][s];
+      } else if constexpr (EPI == EPI_SAV) {
+        a.aux[g] = o[1][s];
+        const cd p = o[0][s], un = una[s], um = uma[s];
+        const cd rp = {ctl->a * p.x + ctl->b * un.x + ctl->c * um.x,
+                       ctl->a * p.y + ctl->b * un.y + ctl->c * um.y};
+        acc[0] += wgt * cdotr(Ua[s], rp);
+        acc[1] += wgt * cdotr(Ua[s], o[1][s]);
+      } else if constexpr (EPI == EPI_PSD) {
+        acc[0] += wgt * cnorm2(o[1][s]);
+        acc[1] += wgt * cnorm2(o[0][s]);
+        unext[s] = o[0][s];
+      } else if constexpr (EPI == EPI_AM3) {
+        const cd F = o[0][s];
         const cd u_n = a.s1[g], fn = a.f_n[g], fm = a.f_nm1[g];
         const cd up = {u_n.x + ctl->w1 * F.x + ctl->w2 * fn.x + ctl->w3 * fm.x,
                        u_n.y + ctl->w1 * F.y + ctl->w2 * fn.y + ctl->w3 * fm.y};
-        acc[0] += wgt * cnorm2(csub(U, up));
+        acc[0] += wgt * cnorm2(csub(Ua[s], up));
         acc[1] += wgt * cnorm2(up);
       }
     }
@@ -347,6 +397,7 @@ __global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
       v[q][s] = (kx < H) ? a.X_in[(size_t)kx * N + t + s * T] : cd{0.0, 0.0};
   }
   fft<N, E, 2, DIR>(v, base, tw, t);
+  if (DIR < 0 && (kx0 == 0 || kx0 == N / 2)) hermitian_fix<N, E, 1, 2>(v, buf, t);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int kx = kx0 + q;

@@ -46,6 +46,10 @@ class fch_stats(C.Structure):
                 ("steps", C.c_int64), ("rejected", C.c_int64)]
 
 
+class fch_profile(C.Structure):
+    _fields_ = [("count", C.c_int64 * 4), ("ms", C.c_double * 4)]
+
+
 class fch_psd_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("lambda_", C.c_double),
                 ("fixed_iters", C.c_int32)]
@@ -93,6 +97,8 @@ _SIGS = {
     "fch_config_get": (_I, [_I, _I, C.POINTER(fch_launch_cfg)]),
     "fch_plan_stats": (_I, [_V, C.POINTER(fch_stats)]),
     "fch_plan_reset_stats": (_I, [_V]),
+    "fch_plan_profile": (_I, [_V, _I]),
+    "fch_plan_profile_read": (_I, [_V, C.POINTER(fch_profile)]),
     "fch_forward": (_I, [_V, _V, _V]),
     "fch_inverse": (_I, [_V, _V, _V]),
     "fch_chem_potential": (_I, [_V, _V, _V, _PD]),
@@ -237,6 +243,17 @@ class Plan:
 
     def reset_stats(self):
         _check(lib().fch_plan_reset_stats(self.h))
+
+    def profile(self, enable=True):
+        _check(lib().fch_plan_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        """Per kernel class: (launch count, summed milliseconds)."""
+        pr = fch_profile()
+        self._sync_stream()
+        _check(lib().fch_plan_profile_read(self.h, C.byref(pr)))
+        names = ("row_mu", "col_fused", "col_one_way", "transform")
+        return {n: (pr.count[i], pr.ms[i]) for i, n in enumerate(names)}
 
     # -- calls (same names as the C ABI, minus the prefix) -----------------
     def forward(self, u, out=None):

@@ -319,3 +319,22 @@ def test_sav_rejects_negative_shift(F, orc):
     with pytest.raises(F.FchError) as ei:
         plan.step_sav(dev(uh0), None, 1.0, 1.0, 1e-3, -1.0)
     assert ei.value.code == F.FCH_E_INVALID
+
+
+def test_long_trajectory_256_stays_on_oracle(F, orc):
+    """600 fixed steps at 256^2 (h/eps = 0.49): a non-real component in the
+    kx = 0 and kx = N/2 columns, seeded by rounding and amplified by the
+    explicit linear terms, once drove the GPU state off the oracle here."""
+    log("imex 256^2, 600 steps")
+    N, L = 256, 4 * np.pi
+    kw = model_kw(N, L)
+    plan, m = pair(F, orc, **kw)
+    uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=0))
+    ref = orc.run_fixed(m, "imex", uh0, 1e-3, 600)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.run(a, b, scheme="imex", nsteps=600, k=1e-3)
+    assert rel(host(a), ref) < 1e-8
+    # every state the library writes is the spectrum of a real field
+    for col in (0, N // 2):
+        c = a[col].cpu().numpy()
+        assert np.array_equal(c, np.conj(c[(-np.arange(N)) % N]))
