@@ -96,6 +96,9 @@ def main():
     uh0 = plan.forward(torch.from_numpy(u0).to(dev))
     a, b = uh0.clone(), torch.empty_like(uh0)
     plan.run(a, b, scheme="imex", nsteps=1, k=k, startup=True)
+    log("autotune launch variants")
+    tuned_cfg, tuned_us = plan.autotune(a, b, k=k, reps=20)
+    log("chosen %s (row %.2f us, column %.2f us)" % (tuned_cfg, tuned_us[0], tuned_us[1]))
     log("warmup %d steps" % args.warmup)
     plan.run(a, b, scheme="imex", nsteps=args.warmup, k=k, k_prev=k, startup=False)
     torch.cuda.synchronize()
@@ -254,7 +257,9 @@ def main():
         "config": {"workload": "m1: FCH 1024^2 on [0,16pi]^2, eps 0.1, eta (1.45, 2.0) eps, "
                                "q 0, fixed-step BDF2-IMEX k=1e-3, one circular bilayer r=0.3L",
                    "N": N, "scheme": "imex", "k": k,
-                   "launch_config": list(plan.get_config())},
+                   "launch_config": dict(zip(("row_R", "row_E", "row_twl", "col_E"),
+                                             plan.get_config())),
+                   "autotuned": True},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

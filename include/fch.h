@@ -90,16 +90,30 @@ fch_status fch_plan_set_stream(fch_plan_t plan, void* stream);
  * (intermediate half spectra, reduction partials).  No compute call allocates. */
 size_t     fch_plan_workspace_bytes(fch_plan_t plan);
 fch_status fch_plan_set_workspace(fch_plan_t plan, void* dptr, size_t bytes);
-/* Launch configuration: rows per row-pass workgroup (R), FFT elements per
- * thread in the row pass (row_E) and the column pass (col_E).  variant < 0
- * selects the built-in default for N.  Returns FCH_E_UNSUPPORTED for a
- * configuration that was not compiled. */
-typedef struct { int32_t row_R, row_E, col_E; } fch_launch_cfg;
+/* Launch configuration of the two kernel families: the row pass (R rows per
+ * workgroup, row_E FFT elements per thread, twiddle table in LDS when
+ * row_twl = 1, else read through the vector caches) and the column pass
+ * (col_E FFT elements per thread, one column per workgroup).  NULL selects
+ * the built-in default for N.  FCH_E_UNSUPPORTED for a configuration that was
+ * not compiled. */
+typedef struct { int32_t row_R, row_E, row_twl, col_E; } fch_launch_cfg;
 fch_status fch_plan_set_config(fch_plan_t plan, const fch_launch_cfg* cfg);
 fch_status fch_plan_get_config(fch_plan_t plan, fch_launch_cfg* cfg);
-/* Number of compiled configurations for a grid size, and the i-th of them. */
-int32_t    fch_config_count(int32_t N);
-fch_status fch_config_get(int32_t N, int32_t i, fch_launch_cfg* cfg);
+/* Compiled variants for a grid size: row-pass variants (row fields of cfg)
+ * and column-pass variants (col_E of cfg). */
+int32_t    fch_row_config_count(int32_t N);
+int32_t    fch_col_config_count(int32_t N);
+fch_status fch_config_get(int32_t N, int32_t row_i, int32_t col_i, fch_launch_cfg* cfg);
+/* Autotuner: times every compiled row-pass and column-pass variant on the
+ * fused BDF2-IMEX step (row pass, then column pass with the next step's
+ * prologue) of the given state, reps launches each with HIP events, and
+ * makes the fastest of each family the plan's configuration.  uh_n, uh_nm1
+ * are read only (copied into the workspace); k is the step used.  best (host
+ * out, nullable) receives the choice; us (host out, nullable, 2 doubles) the
+ * average microseconds per launch of the chosen row and column variants.
+ * Synchronizes the plan's stream. */
+fch_status fch_autotune(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1, double k,
+                        int32_t reps, fch_launch_cfg* best, double* us);
 
 typedef struct {
     int64_t fft_calls;     /* 2D real transforms (forward or inverse) of one N^2 field */

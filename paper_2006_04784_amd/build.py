@@ -15,15 +15,20 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfch.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["fch_kernels.hip", "fch_capi.hip"]
+SOURCES = ["fch_capi.hip", "fch_registry.hip", "fch_kern_small.hip"] + [
+    "fch_kern_n%d.hip" % n for n in (2048, 1024, 512, 256, 128, 64, 32, 16)]
 
 
 def build(verbose: bool = True) -> str:
+    t0 = time.time()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
     procs = []
+    jobs = int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))
     for src in SOURCES:
+        while sum(pr.poll() is None for _, pr in procs) >= jobs:
+            time.sleep(0.2)
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
         cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-c",
@@ -32,7 +37,6 @@ def build(verbose: bool = True) -> str:
                "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                "-o", obj, os.path.join(CSRC, src)]
         procs.append((src, subprocess.Popen(cmd)))
-    t0 = time.time()
     for src, pr in procs:
         if pr.wait() != 0:
             raise RuntimeError("hipcc failed on %s" % src)

@@ -21,7 +21,8 @@ struct fch_plan_s {
   fch_params prm;
   fch::Consts c;
   int N, H;
-  const fch::VTable* vt;
+  const fch::RowVT* rv;
+  const fch::ColVT* cv;
   hipStream_t stream;
   int device;
   cd* tw;
@@ -86,7 +87,8 @@ fch_status validate_params(const fch_params* p) {
       !std::isfinite(p->D0))
     return FCH_E_INVALID;
   if (!is_pow2(p->N) || p->N < 16) return p->N > 0 && p->N < 16 ? FCH_E_UNSUPPORTED : FCH_E_INVALID;
-  if (fch::vtable_count(p->N) == 0) return FCH_E_UNSUPPORTED;
+  if (fch::row_variant_count(p->N) == 0 || fch::col_variant_count(p->N) == 0)
+    return FCH_E_UNSUPPORTED;
   return FCH_OK;
 }
 
@@ -216,7 +218,7 @@ void prof_end(fch_plan_s* p, int i) {
 fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
   const int kind = (epi != fch::EPI_NONE && pro != fch::PRO_NONE) ? 1 : 2;
   const int r = prof_begin(p, kind);
-  HIPCHK(p->vt->col(epi, pro, a, p->stream));
+  HIPCHK(p->cv->col(epi, pro, a, p->stream));
   prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
@@ -226,7 +228,7 @@ fch_status row_mu(fch_plan_s* p, double* partial) {
   RowArgs a = row_args(p);
   a.partial = partial;
   const int r = prof_begin(p, 0);
-  HIPCHK(p->vt->row(fch::ROW_MU, a, p->stream));
+  HIPCHK(p->rv->row(fch::ROW_MU, a, p->stream));
   prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
@@ -237,7 +239,7 @@ fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
   std::memset(&f, 0, sizeof(f));
   f.c = p->c;
   f.rpart = rows ? p->rpart : nullptr;
-  f.nrow = p->N / p->vt->row_R;
+  f.nrow = p->N / p->rv->R;
   f.cpart = cols ? p->cpart : nullptr;
   f.ncol = p->H;
   f.ctl = p->ctl;
@@ -253,10 +255,6 @@ fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
     if (s_ != FCH_OK) return s_;       \
   } while (0)
 
-fch_status set_config(fch_plan_s* p, const fch::VTable* vt) {
-  p->vt = vt;
-  return FCH_OK;
-}
 
 // one chemical-potential evaluation of the field already column-inverted in
 // the pair buffer, ending in the given epilogue
@@ -284,6 +282,8 @@ fch_status status_from_ctl(fch_plan_s* p) {
 }
 
 }  // namespace
+
+static fch_status copy_spec(fch_plan_t p, cd* dst, const cd* src);
 
 // ===========================================================================
 extern "C" {
@@ -334,7 +334,8 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
   p->prm = *prm;
   p->N = prm->N;
   p->H = prm->N / 2 + 1;
-  p->vt = fch::vtable_get(prm->N, 0);
+  p->rv = fch::row_variant(prm->N, 0);
+  p->cv = fch::col_variant(prm->N, 0);
   p->psd_hint = 4;
   fch::Consts& c = p->c;
   c.N = prm->N;
@@ -447,33 +448,132 @@ fch_status fch_plan_set_workspace(fch_plan_t p, void* dptr, size_t bytes) {
   return FCH_OK;
 }
 
-int32_t fch_config_count(int32_t N) { return fch::vtable_count(N); }
+int32_t fch_row_config_count(int32_t N) { return fch::row_variant_count(N); }
+int32_t fch_col_config_count(int32_t N) { return fch::col_variant_count(N); }
 
-fch_status fch_config_get(int32_t N, int32_t i, fch_launch_cfg* cfg) {
-  const fch::VTable* vt = fch::vtable_get(N, i);
-  if (!vt || !cfg) return FCH_E_UNSUPPORTED;
-  cfg->row_R = vt->row_R;
-  cfg->row_E = vt->row_E;
-  cfg->col_E = vt->col_E;
+static void fill_cfg(const fch::RowVT* r, const fch::ColVT* c, fch_launch_cfg* cfg) {
+  cfg->row_R = r->R;
+  cfg->row_E = r->E;
+  cfg->row_twl = r->twl;
+  cfg->col_E = c->E;
+}
+
+fch_status fch_config_get(int32_t N, int32_t ri, int32_t ci, fch_launch_cfg* cfg) {
+  const fch::RowVT* r = fch::row_variant(N, ri);
+  const fch::ColVT* c = fch::col_variant(N, ci);
+  if (!r || !c || !cfg) return FCH_E_UNSUPPORTED;
+  fill_cfg(r, c, cfg);
   return FCH_OK;
 }
 
 fch_status fch_plan_set_config(fch_plan_t p, const fch_launch_cfg* cfg) {
   if (!p) return FCH_E_INVALID;
-  if (!cfg) return set_config(p, fch::vtable_get(p->N, 0));
-  for (int i = 0; i < fch::vtable_count(p->N); ++i) {
-    const fch::VTable* vt = fch::vtable_get(p->N, i);
-    if (vt->row_R == cfg->row_R && vt->row_E == cfg->row_E && vt->col_E == cfg->col_E)
-      return set_config(p, vt);
+  if (!cfg) {
+    p->rv = fch::row_variant(p->N, 0);
+    p->cv = fch::col_variant(p->N, 0);
+    return FCH_OK;
   }
-  return FCH_E_UNSUPPORTED;
+  const fch::RowVT* r = nullptr;
+  const fch::ColVT* c = nullptr;
+  for (int i = 0; i < fch::row_variant_count(p->N); ++i) {
+    const fch::RowVT* v = fch::row_variant(p->N, i);
+    if (v->R == cfg->row_R && v->E == cfg->row_E && v->twl == cfg->row_twl) r = v;
+  }
+  for (int i = 0; i < fch::col_variant_count(p->N); ++i) {
+    const fch::ColVT* v = fch::col_variant(p->N, i);
+    if (v->E == cfg->col_E) c = v;
+  }
+  if (!r || !c) return FCH_E_UNSUPPORTED;
+  p->rv = r;
+  p->cv = c;
+  return FCH_OK;
 }
 
 fch_status fch_plan_get_config(fch_plan_t p, fch_launch_cfg* cfg) {
   if (!p || !cfg) return FCH_E_INVALID;
-  cfg->row_R = p->vt->row_R;
-  cfg->row_E = p->vt->row_E;
-  cfg->col_E = p->vt->col_E;
+  fill_cfg(p->rv, p->cv, cfg);
+  return FCH_OK;
+}
+
+fch_status fch_autotune(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1, double k,
+                        int32_t reps, fch_launch_cfg* best, double* us) {
+  if (!p || !uh_n || !uh_nm1 || !finite_pos(k) || reps < 1) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  const int nr = fch::row_variant_count(p->N), nc = fch::col_variant_count(p->N);
+  const int rounds = (nr > nc ? nr : nc) * reps;
+  double* rsum = new (std::nothrow) double[nr + nc];
+  if (!rsum) return FCH_E_NOMEM;
+  double* csum = rsum + nr;
+  for (int i = 0; i < nr + nc; ++i) rsum[i] = 0.0;
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) { delete[] rsum; return FCH_E_HIP; }
+  const fch::RowVT* keep_r = p->rv;
+  const fch::ColVT* keep_c = p->cv;
+  fch_status st = FCH_OK;
+  // scratch copies of the state: the fused chain runs on Fc[0..2]
+  cd *cur = p->Fc[0], *prev = p->Fc[1];
+  if (copy_spec(p, cur, (const cd*)uh_n) != FCH_OK || copy_spec(p, prev, (const cd*)uh_nm1) != FCH_OK)
+    st = FCH_E_HIP;
+  StepCtl v = ctl_zero();
+  set_bdf2(v, k, k);
+  if (st == FCH_OK) st = ctl_set(p, v);
+  ColArgs a = col_args(p);
+  a.s0 = cur;
+  a.s1 = prev;
+  if (st == FCH_OK) st = col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a);
+  for (int it = 0; it < rounds + 2 && st == FCH_OK; ++it) {
+    const int ri = it % nr, ci = it % nc;
+    p->rv = fch::row_variant(p->N, ri);
+    p->cv = fch::col_variant(p->N, ci);
+    RowArgs r = row_args(p);
+    a.s0 = cur;
+    a.s1 = prev;
+    a.out = prev;
+    if (hipEventRecord(ev[0], p->stream) != hipSuccess ||
+        p->rv->row(fch::ROW_MU, r, p->stream) != hipSuccess ||
+        hipEventRecord(ev[1], p->stream) != hipSuccess ||
+        p->cv->col(fch::EPI_IMEX, fch::PRO_NEXT_EXTRAP, a, p->stream) != hipSuccess ||
+        hipEventRecord(ev[2], p->stream) != hipSuccess ||
+        hipEventSynchronize(ev[2]) != hipSuccess) {
+      st = FCH_E_HIP;
+      break;
+    }
+    std::swap(cur, prev);
+    float t_row = 0.f, t_col = 0.f;
+    (void)hipEventElapsedTime(&t_row, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&t_col, ev[1], ev[2]);
+    if (it >= 2) {  // the first rounds warm caches and code objects
+      rsum[ri] += t_row;
+      csum[ci] += t_col;
+    }
+  }
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  if (st != FCH_OK) {
+    p->rv = keep_r;
+    p->cv = keep_c;
+    delete[] rsum;
+    return st;
+  }
+  int br = 0, bc = 0;
+  for (int i = 1; i < nr; ++i)
+    if (rsum[i] < rsum[br]) br = i;
+  for (int i = 1; i < nc; ++i)
+    if (csum[i] < csum[bc]) bc = i;
+  // every variant ran rounds/n times; average per launch in microseconds
+  auto count = [&](int i, int n) {
+    int c = 0;
+    for (int it = 2; it < rounds + 2; ++it) c += (it % n == i);
+    return c > 0 ? c : 1;
+  };
+  p->rv = fch::row_variant(p->N, br);
+  p->cv = fch::col_variant(p->N, bc);
+  if (best) fill_cfg(p->rv, p->cv, best);
+  if (us) {
+    us[0] = 1e3 * rsum[br] / count(br, nr);
+    us[1] = 1e3 * csum[bc] / count(bc, nc);
+  }
+  delete[] rsum;
   return FCH_OK;
 }
 
@@ -497,13 +597,13 @@ fch_status fch_forward(fch_plan_t p, const double* u, fch_c128* uh) {
   r.u_in = u;
   r.X_out = p->P0;
   int pr = prof_begin(p, 3);
-  HIPCHK(p->vt->row(fch::ROW_FWD, r, p->stream));
+  HIPCHK(p->rv->row(fch::ROW_FWD, r, p->stream));
   prof_end(p, pr);
   ColArgs a = col_args(p);
   a.X_in = p->P0;
   a.X_out = (cd*)uh;
   pr = prof_begin(p, 3);
-  HIPCHK(p->vt->col_fwd1(a, p->stream));
+  HIPCHK(p->cv->col_fwd1(a, p->stream));
   prof_end(p, pr);
   p->stats.launches += 2;
   p->stats.fft_calls += 1;
@@ -517,13 +617,13 @@ fch_status fch_inverse(fch_plan_t p, const fch_c128* uh, double* u) {
   a.X_in = (const cd*)uh;
   a.X_out = p->P0;
   int pr = prof_begin(p, 3);
-  HIPCHK(p->vt->col_inv1(a, p->stream));
+  HIPCHK(p->cv->col_inv1(a, p->stream));
   prof_end(p, pr);
   RowArgs r = row_args(p);
   r.X_in = p->P0;
   r.u_out = u;
   pr = prof_begin(p, 3);
-  HIPCHK(p->vt->row(fch::ROW_INV, r, p->stream));
+  HIPCHK(p->rv->row(fch::ROW_INV, r, p->stream));
   prof_end(p, pr);
   p->stats.launches += 2;
   p->stats.fft_calls += 1;

@@ -72,19 +72,24 @@ struct FinArgs {
   int mode;
 };
 
-// Launch table of one compiled configuration for one grid size.
-struct VTable {
-  int N, row_R, row_E, col_E;
-  int row_threads, col_threads;
+// Launch tables of the compiled variants of one grid size.  Row-pass and
+// column-pass variants are chosen independently.
+struct RowVT {
+  int N, R, E, twl, threads;
   hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s);
+};
+struct ColVT {
+  int N, E, threads;
   hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s);
   hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s);
   hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s);
 };
 
-// registry (fch_kernels.hip)
-int vtable_count(int N);
-const VTable* vtable_get(int N, int i);
+// registry: the first entry of each list is the default for N
+int row_variant_count(int N);
+const RowVT* row_variant(int N, int i);
+int col_variant_count(int N);
+const ColVT* col_variant(int N, int i);
 
 hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);

@@ -1,4 +1,4 @@
-// fch_kernels.hip -- HIP kernels of the FCH pseudo-spectral BDF2 path for
+// fch_kernels_impl.hpp -- HIP kernel templates of the FCH pseudo-spectral BDF2 path for
 // gfx950, FP64.
 //
 // A 2D real transform is split into a row pass (length-N FFTs along x, one
@@ -16,11 +16,13 @@
 //                inverse FFT.
 // Two real rows are transformed as one complex sequence z = a + i b (the
 // row pass always handles pairs: (u, Lap u) in, (omega, p) out).
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include "fch_kernels.hpp"
 
 namespace fch {
+
 
 __device__ __forceinline__ double wavek2(const Consts& c, int kx, int ky) {
   const int N = c.N;
@@ -52,14 +54,16 @@ __device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, 
 // ===========================================================================
 // Row pass
 // ===========================================================================
-template <int N, int R, int E, int MODE>
+// TWL: twiddle table copied to LDS (1) or read from global memory through
+// the vector caches (0, frees N*16 bytes of LDS per workgroup)
+template <int N, int R, int E, int MODE, int TWL>
 __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
   constexpr int T = N / E;
   constexpr int NT = R * T;
   constexpr int M = N / 2;
   constexpr int H = M + 1;
   __shared__ cd Z[R][N];
-  __shared__ cd tw[N];
+  __shared__ cd twl[TWL ? N : 1];
   __shared__ double red[2 * NT];
   if (done && *done) return;
 
@@ -71,7 +75,11 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
   // ROW_FWD/ROW_INV: rows y0 .. y0+2R-1, sequence s pairs rows y0+s, y0+R+s.
   const int y0 = (MODE == ROW_MU) ? tile * R : tile * 2 * R;
 
-  for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+  const cd* tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = tid; i < N; i += NT) twl[i] = a.tw[i];
+    tw = twl;
+  }
 
   cd v[1][E];
   cd* const base[1] = {Z[seq]};
@@ -406,236 +414,6 @@ __global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
       for (int s = 0; s < E; ++s) a.X_out[(size_t)kx * N + t + s * T] = v[q][s];
     }
   }
-}
-
-// ===========================================================================
-// Small kernels: control block, reductions, SAV combine
-// ===========================================================================
-__global__ void k_ctl_set(StepCtl* ctl, StepCtl v) { *ctl = v; }
-
-__device__ __forceinline__ double sum_strided(const double* p, int n, int stride, int off,
-                                              double* red) {
-  constexpr int NT = 256;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) s += p[(size_t)i * stride + off];
-  double v[1] = {s};
-  __shared__ double tot;
-  block_reduce<NT, 1>(v, red, &tot);
-  __syncthreads();
-  return tot;
-}
-
-__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
-  __shared__ double red[256];
-  StepCtl* ctl = a.ctl;
-  const Consts& c = a.c;
-  if (a.mode == FIN_PSD && ctl->done) return;
-  double r0 = 0, r1 = 0, c0 = 0, c1 = 0;
-  if (a.rpart) {
-    r0 = sum_strided(a.rpart, a.nrow, 2, 0, red);
-    r1 = sum_strided(a.rpart, a.nrow, 2, 1, red);
-  }
-  if (a.cpart) {
-    c0 = sum_strided(a.cpart, a.ncol, 2, 0, red);
-    c1 = sum_strided(a.cpart, a.ncol, 2, 1, red);
-  }
-  if (threadIdx.x != 0) return;
-  switch (a.mode) {
-    case FIN_SAV_S: {
-      const double E1 = c.h2 * r0;
-      const double s2 = E1 + c.D0;
-      ctl->E1 = E1;
-      if (!isfinite(s2)) {
-        ctl->nonfinite = 1;
-        ctl->s_star = 1.0;
-      } else if (!(s2 > 0.0)) {
-        ctl->invalid = 1;
-        ctl->s_star = 1.0;
-      } else {
-        ctl->s_star = sqrt(s2);
-      }
-      break;
-    }
-    case FIN_SAV_R: {
-      const double gp = c.pars * c0, gq = c.pars * c1;
-      const double r = (-ctl->b * ctl->r_n - ctl->c * ctl->r_nm1 + 0.5 * gp) /
-                       (ctl->a - 0.5 * ctl->a * gq);
-      ctl->r_np1 = r;
-      if (!isfinite(r)) ctl->nonfinite = 1;
-      break;
-    }
-    case FIN_PSD: {
-      const double ratio = sqrt(c0 / c1);
-      ctl->ratio = ratio;
-      ctl->iters += 1;
-      if (!isfinite(ratio)) {
-        ctl->nonfinite = 1;
-        ctl->done = 3;
-      } else if (ctl->fixed_iters > 0) {
-        if (ctl->iters >= ctl->fixed_iters) ctl->done = 1;
-      } else if (ratio < ctl->tol) {
-        ctl->done = 1;
-      } else if (ctl->iters >= ctl->max_iter) {
-        ctl->done = 2;
-      }
-      break;
-    }
-    case FIN_AM3: {
-      const double e = sqrt(c0 / c1);
-      const double ee = e > 1e-300 ? e : 1e-300;
-      double kn = ctl->rho_s * cbrt(ctl->sigma_tol / ee) * ctl->k_np1;
-      if (ctl->cap > 0.0 && kn > ctl->cap * ctl->k_np1) kn = ctl->cap * ctl->k_np1;
-      if (kn > ctl->k_max) kn = ctl->k_max;
-      if (kn < ctl->k_min) kn = ctl->k_min;
-      ctl->err = e;
-      ctl->k_next = kn;
-      ctl->accept = (e <= ctl->sigma_tol) || (ctl->k_np1 <= ctl->k_min);
-      if (!isfinite(e)) ctl->nonfinite = 1;
-      break;
-    }
-    case FIN_ENERGY: {
-      ctl->energy = c.h2 * r1 - 0.5 * c.eps2 * c.eta1 * c.pars * c0;
-      if (!isfinite(ctl->energy)) ctl->nonfinite = 1;
-      break;
-    }
-  }
-}
-
-__global__ void k_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n) {
-  const double r = ctl->r_np1;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const cd o = out[i], qq = q[i];
-    out[i] = cd{fma(r, qq.x, o.x), fma(r, qq.y, o.y)};
-  }
-}
-
-hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(1), 0, s, ctl, v);
-  return hipGetLastError();
-}
-hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s) {
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_axpy_r, dim3((unsigned)blocks), dim3(256), 0, s, out, q, ctl, n);
-  return hipGetLastError();
-}
-
-// ===========================================================================
-// Launch tables
-// ===========================================================================
-template <int N, int R, int RE, int CE>
-struct Impl {
-  static constexpr int RT = R * (N / RE);
-  static constexpr int CT = N / CE;
-  static constexpr int H = N / 2 + 1;
-
-  static hipError_t row(int mode, const RowArgs& a, hipStream_t s) {
-    const int* done = (mode == ROW_MU) ? &a.ctl->done : nullptr;
-    switch (mode) {
-      case ROW_MU:
-        hipLaunchKernelGGL((k_row<N, R, RE, ROW_MU>), dim3(N / R), dim3(RT), 0, s, a, done);
-        break;
-      case ROW_FWD:
-        hipLaunchKernelGGL((k_row<N, R, RE, ROW_FWD>), dim3(N / (2 * R)), dim3(RT), 0, s, a,
-                           nullptr);
-        break;
-      case ROW_INV:
-        hipLaunchKernelGGL((k_row<N, R, RE, ROW_INV>), dim3(N / (2 * R)), dim3(RT), 0, s, a,
-                           nullptr);
-        break;
-      default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-
-  template <int EPI, int PRO>
-  static void lc(const ColArgs& a, hipStream_t s, const int* done) {
-    hipLaunchKernelGGL((k_col<N, CE, EPI, PRO>), dim3(H), dim3(CT), 0, s, a, done);
-  }
-
-  static hipError_t col(int epi, int pro, const ColArgs& a, hipStream_t s) {
-    const int* done = &a.ctl->done;
-#define FCH_COL(E_, P_)                \
-  if (epi == E_ && pro == P_) {        \
-    lc<E_, P_>(a, s, done);            \
-    return hipGetLastError();          \
-  }
-    FCH_COL(EPI_NONE, PRO_FIELD)
-    FCH_COL(EPI_NONE, PRO_EXTRAP)
-    FCH_COL(EPI_NONE, PRO_PSD_INIT)
-    FCH_COL(EPI_MU, PRO_NONE)
-    FCH_COL(EPI_F, PRO_NONE)
-    FCH_COL(EPI_IMEX, PRO_NONE)
-    FCH_COL(EPI_IMEX, PRO_NEXT_EXTRAP)
-    FCH_COL(EPI_IMEX, PRO_NEXT_FIELD)
-    FCH_COL(EPI_SAV, PRO_NONE)
-    FCH_COL(EPI_PSD, PRO_NEXT_FIELD)
-    FCH_COL(EPI_AM3, PRO_NONE)
-#undef FCH_COL
-    return hipErrorInvalidValue;
-  }
-
-  static hipError_t col_fwd1(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col1<N, CE, -1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
-    return hipGetLastError();
-  }
-  static hipError_t col_inv1(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col1<N, CE, +1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
-    return hipGetLastError();
-  }
-
-  static const VTable* table() {
-    static const VTable vt = {N, R, RE, CE, RT, CT, &row, &col, &col_fwd1, &col_inv1};
-    return &vt;
-  }
-};
-
-// Compiled configurations per grid size (the first one is the default).
-#define FCH_CFG(N, R, RE, CE) Impl<N, R, RE, CE>::table()
-static const VTable* const* configs_for(int N, int* count) {
-  static const VTable* const c16[] = {FCH_CFG(16, 2, 4, 4)};
-  static const VTable* const c32[] = {FCH_CFG(32, 2, 4, 4)};
-  static const VTable* const c64[] = {FCH_CFG(64, 2, 8, 8)};
-  static const VTable* const c128[] = {FCH_CFG(128, 2, 8, 8)};
-  static const VTable* const c256[] = {FCH_CFG(256, 2, 16, 8)};
-  static const VTable* const c512[] = {FCH_CFG(512, 2, 8, 8)};
-  static const VTable* const c1024[] = {FCH_CFG(1024, 4, 16, 8)};
-  static const VTable* const c2048[] = {FCH_CFG(2048, 2, 16, 16)};
-#define FCH_RET(arr)                                 \
-  {                                                  \
-    *count = (int)(sizeof(arr) / sizeof(arr[0]));    \
-    return arr;                                      \
-  }
-  switch (N) {
-    case 16: FCH_RET(c16)
-    case 32: FCH_RET(c32)
-    case 64: FCH_RET(c64)
-    case 128: FCH_RET(c128)
-    case 256: FCH_RET(c256)
-    case 512: FCH_RET(c512)
-    case 1024: FCH_RET(c1024)
-    case 2048: FCH_RET(c2048)
-    default: *count = 0; return nullptr;
-  }
-#undef FCH_RET
-}
-
-int vtable_count(int N) {
-  int n = 0;
-  configs_for(N, &n);
-  return n;
-}
-const VTable* vtable_get(int N, int i) {
-  int n = 0;
-  const VTable* const* arr = configs_for(N, &n);
-  if (!arr || i < 0 || i >= n) return nullptr;
-  return arr[i];
 }
 
 }  // namespace fch

@@ -1,0 +1,95 @@
+// fch_variants.hpp -- launch wrappers of the kernel templates for one grid
+// size; each fch_kern_n<N>.hip instantiates the variants of its N.
+#pragma once
+#include "fch_kernels_impl.hpp"
+
+namespace fch {
+
+template <int N, int R, int E, int TWL>
+struct RowImpl {
+  static constexpr int NT = R * (N / E);
+  static hipError_t row(int mode, const RowArgs& a, hipStream_t s) {
+    const int* done = (mode == ROW_MU) ? &a.ctl->done : nullptr;
+    switch (mode) {
+      case ROW_MU:
+        hipLaunchKernelGGL((k_row<N, R, E, ROW_MU, TWL>), dim3(N / R), dim3(NT), 0, s, a, done);
+        break;
+      case ROW_FWD:
+        hipLaunchKernelGGL((k_row<N, R, E, ROW_FWD, TWL>), dim3(N / (2 * R)), dim3(NT), 0, s, a,
+                           nullptr);
+        break;
+      case ROW_INV:
+        hipLaunchKernelGGL((k_row<N, R, E, ROW_INV, TWL>), dim3(N / (2 * R)), dim3(NT), 0, s, a,
+                           nullptr);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  static const RowVT* table() {
+    static const RowVT vt = {N, R, E, TWL, NT, &row};
+    return &vt;
+  }
+};
+
+template <int N, int E>
+struct ColImpl {
+  static constexpr int CT = N / E;
+  static constexpr int H = N / 2 + 1;
+
+  template <int EPI, int PRO>
+  static hipError_t lc(const ColArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_col<N, E, EPI, PRO>), dim3(H), dim3(CT), 0, s, a, &a.ctl->done);
+    return hipGetLastError();
+  }
+
+  static hipError_t col(int epi, int pro, const ColArgs& a, hipStream_t s) {
+#define FCH_COL(E_, P_) \
+  if (epi == E_ && pro == P_) return lc<E_, P_>(a, s);
+    FCH_COL(EPI_NONE, PRO_FIELD)
+    FCH_COL(EPI_NONE, PRO_EXTRAP)
+    FCH_COL(EPI_NONE, PRO_PSD_INIT)
+    FCH_COL(EPI_MU, PRO_NONE)
+    FCH_COL(EPI_F, PRO_NONE)
+    FCH_COL(EPI_IMEX, PRO_NONE)
+    FCH_COL(EPI_IMEX, PRO_NEXT_EXTRAP)
+    FCH_COL(EPI_IMEX, PRO_NEXT_FIELD)
+    FCH_COL(EPI_SAV, PRO_NONE)
+    FCH_COL(EPI_PSD, PRO_NEXT_FIELD)
+    FCH_COL(EPI_AM3, PRO_NONE)
+#undef FCH_COL
+    return hipErrorInvalidValue;
+  }
+  static hipError_t col_fwd1(const ColArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_col1<N, E, -1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+    return hipGetLastError();
+  }
+  static hipError_t col_inv1(const ColArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_col1<N, E, +1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+    return hipGetLastError();
+  }
+  static const ColVT* table() {
+    static const ColVT vt = {N, E, CT, &col, &col_fwd1, &col_inv1};
+    return &vt;
+  }
+};
+
+}  // namespace fch
+
+// Defines the variant lists of one grid size:
+//   FCH_VARIANTS(N, (RowImpl<...>::table(), ...), (ColImpl<...>::table(), ...))
+#define FCH_LIST(...) __VA_ARGS__
+#define FCH_VARIANTS(N, ROWS, COLS)                                              \
+  namespace fch {                                                                \
+  const RowVT* const* row_variants_##N(int* n) {                                 \
+    static const RowVT* const v[] = {ROWS};                                      \
+    *n = (int)(sizeof(v) / sizeof(v[0]));                                        \
+    return v;                                                                    \
+  }                                                                              \
+  const ColVT* const* col_variants_##N(int* n) {                                 \
+    static const ColVT* const v[] = {COLS};                                      \
+    *n = (int)(sizeof(v) / sizeof(v[0]));                                        \
+    return v;                                                                    \
+  }                                                                              \
+  }

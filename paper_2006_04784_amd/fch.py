@@ -38,7 +38,8 @@ class fch_params(C.Structure):
 
 
 class fch_launch_cfg(C.Structure):
-    _fields_ = [("row_R", C.c_int32), ("row_E", C.c_int32), ("col_E", C.c_int32)]
+    _fields_ = [("row_R", C.c_int32), ("row_E", C.c_int32), ("row_twl", C.c_int32),
+                ("col_E", C.c_int32)]
 
 
 class fch_stats(C.Structure):
@@ -93,8 +94,10 @@ _SIGS = {
     "fch_plan_set_workspace": (_I, [_V, _V, C.c_size_t]),
     "fch_plan_set_config": (_I, [_V, C.POINTER(fch_launch_cfg)]),
     "fch_plan_get_config": (_I, [_V, C.POINTER(fch_launch_cfg)]),
-    "fch_config_count": (_I, [_I]),
-    "fch_config_get": (_I, [_I, _I, C.POINTER(fch_launch_cfg)]),
+    "fch_row_config_count": (_I, [_I]),
+    "fch_col_config_count": (_I, [_I]),
+    "fch_config_get": (_I, [_I, _I, _I, C.POINTER(fch_launch_cfg)]),
+    "fch_autotune": (_I, [_V, _V, _V, _D, _I, C.POINTER(fch_launch_cfg), _PD]),
     "fch_plan_stats": (_I, [_V, C.POINTER(fch_stats)]),
     "fch_plan_reset_stats": (_I, [_V]),
     "fch_plan_profile": (_I, [_V, _I]),
@@ -149,12 +152,19 @@ def sav_constants(prm: fch_params):
 
 
 def config_list(N: int):
-    out = []
-    for i in range(lib().fch_config_count(N)):
+    """Compiled (row variants, column variants) of a grid size: row variants
+    as (R, E, twl), column variants as E."""
+    L = lib()
+    rows, cols = [], []
+    for i in range(L.fch_row_config_count(N)):
         c = fch_launch_cfg()
-        _check(lib().fch_config_get(N, i, C.byref(c)))
-        out.append((c.row_R, c.row_E, c.col_E))
-    return out
+        _check(L.fch_config_get(N, i, 0, C.byref(c)))
+        rows.append((c.row_R, c.row_E, c.row_twl))
+    for j in range(L.fch_col_config_count(N)):
+        c = fch_launch_cfg()
+        _check(L.fch_config_get(N, 0, j, C.byref(c)))
+        cols.append(c.col_E)
+    return rows, cols
 
 
 @dataclass
@@ -228,13 +238,25 @@ class Plan:
         return lib().fch_alpha_m(C.byref(self.prm))
 
     def set_config(self, cfg):
+        """cfg = (row_R, row_E, row_twl, col_E), or None for the default."""
         c = None if cfg is None else fch_launch_cfg(*cfg)
         _check(lib().fch_plan_set_config(self.h, None if c is None else C.byref(c)))
 
     def get_config(self):
         c = fch_launch_cfg()
         _check(lib().fch_plan_get_config(self.h, C.byref(c)))
-        return (c.row_R, c.row_E, c.col_E)
+        return (c.row_R, c.row_E, c.row_twl, c.col_E)
+
+    def autotune(self, uh_n, uh_nm1, k=1e-3, reps=20):
+        """Pick the fastest compiled row/column variants on the fused IMEX step;
+        returns (config, (row_us, col_us))."""
+        self._chk_spec(uh_n, uh_nm1)
+        c = fch_launch_cfg()
+        us = (C.c_double * 2)()
+        self._sync_stream()
+        _check(lib().fch_autotune(self.h, _p(uh_n), _p(uh_nm1), k, reps, C.byref(c),
+                                  C.cast(us, _PD)))
+        return (c.row_R, c.row_E, c.row_twl, c.col_E), (us[0], us[1])
 
     def stats(self):
         s = fch_stats()

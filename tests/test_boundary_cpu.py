@@ -74,9 +74,17 @@ def test_plan_create_rejects_bad_params_before_touching_the_device(fch):
 
 def test_compiled_configurations(fch):
     for N in (16, 32, 64, 128, 256, 512, 1024, 2048):
-        cfgs = fch.config_list(N)
-        assert cfgs, N
-        for (R, rE, cE) in cfgs:
-            assert N % rE == 0 and N % cE == 0 and N % (2 * R) == 0
-    assert fch.lib().fch_config_count(4096) == 0
-    assert fch.lib().fch_config_count(100) == 0
+        rows, cols = fch.config_list(N)
+        assert rows and cols, N
+        for (R, rE, twl) in rows:
+            assert N % rE == 0 and N % (2 * R) == 0 and twl in (0, 1)
+            assert rE == N or N >= rE * rE          # radix schedule E ... E
+            # LDS: R rows + optional twiddles + reduction scratch <= 160 KiB
+            assert 16 * R * N + 16 * N * twl + 16 * R * (N // rE) <= 160 * 1024
+        for cE in cols:
+            assert N % cE == 0 and (cE == N or N >= cE * cE)
+            assert 2 * 16 * N + 16 * N + 16 * (N // cE) <= 160 * 1024
+    assert fch.lib().fch_row_config_count(4096) == 0
+    assert fch.lib().fch_col_config_count(100) == 0
+    c = fch.fch_launch_cfg()
+    assert fch.lib().fch_config_get(1024, 99, 0, C.byref(c)) == fch.FCH_E_UNSUPPORTED

@@ -338,3 +338,46 @@ def test_long_trajectory_256_stays_on_oracle(F, orc):
     for col in (0, N // 2):
         c = a[col].cpu().numpy()
         assert np.array_equal(c, np.conj(c[(-np.arange(N)) % N]))
+
+
+@pytest.mark.parametrize("N", [16, 64, 256, 512, 1024, 2048])
+def test_every_launch_variant(F, orc, N):
+    """Each compiled row-pass and column-pass variant gives the oracle's
+    transforms and IMEX step."""
+    log("launch variants N=%d" % N)
+    rows, cols = F.config_list(N)
+    L = N * 4 * np.pi / 256
+    kw = model_kw(N, L)
+    plan, m = pair(F, orc, **kw)
+    u0 = inputs.circle_bilayer(N, L, 0.1, seed=2)
+    uh0 = orc.r2c(u0)
+    u1 = orc.imex_step(m, uh0, None, 1e-3, -1.0)
+    ref = orc.imex_step(m, u1, uh0, 1e-3, 1e-3)
+    for i in range(max(len(rows), len(cols))):
+        r, c = rows[i % len(rows)], cols[i % len(cols)]
+        plan.set_config((r[0], r[1], r[2], c))
+        assert plan.get_config() == (r[0], r[1], r[2], c)
+        uh = plan.forward(torch.from_numpy(u0).cuda())
+        assert rel(host(uh), uh0) < 1e-13, (r, c)
+        assert rel(plan.inverse(uh).cpu().numpy(), u0) < 1e-13, (r, c)
+        out = plan.step_imex(dev(u1), dev(uh0), 1e-3, 1e-3)
+        assert rel(host(out), ref) < 1e-10, (r, c)
+        a, b = dev(u1), dev(uh0)
+        plan.run(a, b, scheme="imex", nsteps=1, k=1e-3, k_prev=1e-3, startup=False)
+        assert rel(host(a), ref) < 1e-10, (r, c)
+
+
+def test_autotune_picks_a_compiled_variant(F, orc):
+    log("autotune 256")
+    N, L = 256, 4 * np.pi
+    plan, m = pair(F, orc, **model_kw(N, L))
+    uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=0))
+    u1 = orc.imex_step(m, uh0, None, 1e-3, -1.0)
+    a, b = dev(u1), dev(uh0)
+    a0, b0 = a.clone(), b.clone()
+    cfg, us = plan.autotune(a, b, k=1e-3, reps=3)
+    rows, cols = F.config_list(N)
+    assert cfg[:3] in rows and cfg[3] in cols and us[0] > 0 and us[1] > 0
+    assert torch.equal(a, a0) and torch.equal(b, b0)     # inputs untouched
+    out = plan.step_imex(a, b, 1e-3, 1e-3)
+    assert rel(host(out), orc.imex_step(m, u1, uh0, 1e-3, 1e-3)) < 1e-10
