@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip SAV/PSD/adaptive/FFT extras")
+    ap.add_argument("--config", type=str, default="",
+                    help="row_R,row_E,row_twl,col_E,col_twl launch config instead of autotuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB copy (counter calibration)")
     args = ap.parse_args()
@@ -96,9 +98,13 @@ def main():
     uh0 = plan.forward(torch.from_numpy(u0).to(dev))
     a, b = uh0.clone(), torch.empty_like(uh0)
     plan.run(a, b, scheme="imex", nsteps=1, k=k, startup=True)
-    log("autotune launch variants")
-    tuned_cfg, tuned_us = plan.autotune(a, b, k=k, reps=20)
-    log("chosen %s (row %.2f us, column %.2f us)" % (tuned_cfg, tuned_us[0], tuned_us[1]))
+    if args.config:
+        plan.set_config(tuple(int(x) for x in args.config.split(",")))
+        log("launch config %s (given)" % (plan.get_config(),))
+    else:
+        log("autotune launch variants")
+        tuned_cfg, tuned_us = plan.autotune(a, b, k=k, reps=20)
+        log("chosen %s (row %.2f us, column %.2f us)" % (tuned_cfg, tuned_us[0], tuned_us[1]))
     log("warmup %d steps" % args.warmup)
     plan.run(a, b, scheme="imex", nsteps=args.warmup, k=k, k_prev=k, startup=False)
     torch.cuda.synchronize()
@@ -257,9 +263,9 @@ def main():
         "config": {"workload": "m1: FCH 1024^2 on [0,16pi]^2, eps 0.1, eta (1.45, 2.0) eps, "
                                "q 0, fixed-step BDF2-IMEX k=1e-3, one circular bilayer r=0.3L",
                    "N": N, "scheme": "imex", "k": k,
-                   "launch_config": dict(zip(("row_R", "row_E", "row_twl", "col_E"),
+                   "launch_config": dict(zip(("row_R", "row_E", "row_twl", "col_E", "col_twl"),
                                              plan.get_config())),
-                   "autotuned": True},
+                   "autotuned": not args.config},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -93,14 +93,15 @@ fch_status fch_plan_set_workspace(fch_plan_t plan, void* dptr, size_t bytes);
 /* Launch configuration of the two kernel families: the row pass (R rows per
  * workgroup, row_E FFT elements per thread, twiddle table in LDS when
  * row_twl = 1, else read through the vector caches) and the column pass
- * (col_E FFT elements per thread, one column per workgroup).  NULL selects
+ * (col_E FFT elements per thread, one column per workgroup, twiddles in LDS
+ * when col_twl = 1).  NULL selects
  * the built-in default for N.  FCH_E_UNSUPPORTED for a configuration that was
  * not compiled. */
-typedef struct { int32_t row_R, row_E, row_twl, col_E; } fch_launch_cfg;
+typedef struct { int32_t row_R, row_E, row_twl, col_E, col_twl; } fch_launch_cfg;
 fch_status fch_plan_set_config(fch_plan_t plan, const fch_launch_cfg* cfg);
 fch_status fch_plan_get_config(fch_plan_t plan, fch_launch_cfg* cfg);
 /* Compiled variants for a grid size: row-pass variants (row fields of cfg)
- * and column-pass variants (col_E of cfg). */
+ * and column-pass variants (col fields of cfg). */
 int32_t    fch_row_config_count(int32_t N);
 int32_t    fch_col_config_count(int32_t N);
 fch_status fch_config_get(int32_t N, int32_t row_i, int32_t col_i, fch_launch_cfg* cfg);

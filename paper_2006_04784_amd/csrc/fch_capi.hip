@@ -456,6 +456,7 @@ static void fill_cfg(const fch::RowVT* r, const fch::ColVT* c, fch_launch_cfg* c
   cfg->row_E = r->E;
   cfg->row_twl = r->twl;
   cfg->col_E = c->E;
+  cfg->col_twl = c->twl;
 }
 
 fch_status fch_config_get(int32_t N, int32_t ri, int32_t ci, fch_launch_cfg* cfg) {
@@ -481,7 +482,7 @@ fch_status fch_plan_set_config(fch_plan_t p, const fch_launch_cfg* cfg) {
   }
   for (int i = 0; i < fch::col_variant_count(p->N); ++i) {
     const fch::ColVT* v = fch::col_variant(p->N, i);
-    if (v->E == cfg->col_E) c = v;
+    if (v->E == cfg->col_E && v->twl == cfg->col_twl) c = v;
   }
   if (!r || !c) return FCH_E_UNSUPPORTED;
   p->rv = r;

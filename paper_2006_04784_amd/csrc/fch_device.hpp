@@ -100,6 +100,13 @@ __device__ __forceinline__ void dft(cd* v) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS layout of FFT scratch: one padding slot after every 8 complex
+// elements (128 bytes, one row of the 32 four-byte banks).  Stockham stores
+// at lane strides of 2..16 elements then spread over distinct bank groups.
+__host__ __device__ constexpr int lp(int i) { return i + (i >> 3); }
+// elements of a padded length-n sequence
+__host__ __device__ constexpr int lp_size(int n) { return n + (n >> 3) + 1; }
+
 // Radix schedule of a length-L transform with E elements per thread: the
 // first and the last pass have radix E (so a thread's registers hold
 // positions t + s*T both before the first and after the last pass, T = L/E),
@@ -156,7 +163,7 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
 #pragma unroll
       for (int b = 0; b < B; ++b)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][b * R + r] = lds[q][t + b * T + r * (L / R)];
+        for (int r = 0; r < R; ++r) v[q][b * R + r] = lds[q][lp(t + b * T + r * (L / R))];
   }
   if constexpr (Ns > 1) {
 #pragma unroll
@@ -184,7 +191,7 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
 #pragma unroll
       for (int q = 0; q < NSEQ; ++q)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[q][base + r * Ns] = v[q][b * R + r];
+        for (int r = 0; r < R; ++r) lds[q][lp(base + r * Ns)] = v[q][b * R + r];
     }
     __syncthreads();
     fft_pass<L, E, NSEQ, DIR, P + 1>(v, lds, tw, t);
@@ -192,7 +199,8 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
 }
 
 // Length-L FFT of NSEQ sequences.  On entry and on exit v[q][s] is position
-// t + s*T of sequence q.  lds[q] is an L-element LDS scratch per sequence.
+// t + s*T of sequence q.  lds[q] is an LDS scratch of lp_size(L) elements per
+// sequence, indexed through lp().
 // Unnormalized in both directions.
 template <int L, int E, int NSEQ, int DIR>
 __device__ __forceinline__ void fft(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ], const cd* tw, int t) {

@@ -79,7 +79,7 @@ struct RowVT {
   hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s);
 };
 struct ColVT {
-  int N, E, threads;
+  int N, E, twl, threads;
   hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s);
   hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s);
   hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s);

@@ -62,7 +62,11 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
   constexpr int NT = R * T;
   constexpr int M = N / 2;
   constexpr int H = M + 1;
-  __shared__ cd Z[R][N];
+  // row r of the scratch starts at r*ZS; ZS = 8/R (mod 8) places the R rows
+  // of one kx in distinct bank groups
+  constexpr int ZS0 = lp_size(N);
+  constexpr int ZS = ZS0 + (((8 / R) - ZS0 % 8) % 8 + 8) % 8;
+  __shared__ cd Zs[R * ZS];
   __shared__ cd twl[TWL ? N : 1];
   __shared__ double red[2 * NT];
   if (done && *done) return;
@@ -82,33 +86,46 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
   }
 
   cd v[1][E];
-  cd* const base[1] = {Z[seq]};
+  cd* const base[1] = {Zs + seq * ZS};
 
   if constexpr (MODE == ROW_MU || MODE == ROW_INV) {
-    // gather the column-inverted half spectra of R rows; build the full
-    // length-N spectrum of z = a + i b from the two Hermitian halves
-    for (int idx = tid; idx < R * H; idx += NT) {
-      const int kx = idx / R, rr = idx - kx * R;
-      cd xa, xb;
-      if constexpr (MODE == ROW_MU) {
+    // gather the column-inverted half spectra of R rows (all loads issued
+    // before any use), then build the full length-N spectrum of z = a + i b
+    // from the two Hermitian halves
+    constexpr int NIT = (R * H + NT - 1) / NT;
+    cd ga[NIT], gb[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + it * NT;
+      if (idx < R * H) {
+        const int kx = idx / R, rr = idx - kx * R;
         const size_t g = (size_t)kx * N + y0 + rr;
-        xa = a.P0[g];
-        xb = a.P1[g];
-      } else {
-        const size_t g = (size_t)kx * N + y0 + rr;
-        xa = a.X_in[g];
-        xb = a.X_in[g + R];
+        if constexpr (MODE == ROW_MU) {
+          ga[it] = a.P0[g];
+          gb[it] = a.P1[g];
+        } else {
+          ga[it] = a.X_in[g];
+          gb[it] = a.X_in[g + R];
+        }
       }
-      if (kx == 0 || kx == M) {
-        Z[rr][kx] = cd{xa.x, xb.x};  // real parts only: C2R of the Hermitian extension
-      } else {
-        Z[rr][kx] = cd{xa.x - xb.y, xa.y + xb.x};
-        Z[rr][N - kx] = cd{xa.x + xb.y, xb.x - xa.y};
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + it * NT;
+      if (idx < R * H) {
+        const int kx = idx / R, rr = idx - kx * R;
+        const cd xa = ga[it], xb = gb[it];
+        if (kx == 0 || kx == M) {
+          Zs[rr * ZS + lp(kx)] = cd{xa.x, xb.x};  // real parts only: C2R of the Hermitian extension
+        } else {
+          Zs[rr * ZS + lp(kx)] = cd{xa.x - xb.y, xa.y + xb.x};
+          Zs[rr * ZS + lp(N - kx)] = cd{xa.x + xb.y, xb.x - xa.y};
+        }
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < E; ++s) v[0][s] = Z[seq][t + s * T];
+    for (int s = 0; s < E; ++s) v[0][s] = Zs[seq * ZS + lp(t + s * T)];
     fft<N, E, 1, +1>(v, base, tw, t);
   }
 
@@ -151,14 +168,18 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
   fft<N, E, 1, -1>(v, base, tw, t);
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < E; ++s) Z[seq][t + s * T] = v[0][s];
+  for (int s = 0; s < E; ++s) Zs[seq * ZS + lp(t + s * T)] = v[0][s];
   __syncthreads();
 
   // untangle: A[k] = (Z[k] + conj Z[N-k])/2, B[k] = (Z[k] - conj Z[N-k])/(2i)
-  for (int idx = tid; idx < R * H; idx += NT) {
+  constexpr int NIT2 = (R * H + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < NIT2; ++it) {
+    const int idx = tid + it * NT;
+    if (idx >= R * H) break;
     const int kx = idx / R, rr = idx - kx * R;
-    const cd zk = Z[rr][kx];
-    const cd zn = Z[rr][(N - kx) & (N - 1)];
+    const cd zk = Zs[rr * ZS + lp(kx)];
+    const cd zn = Zs[rr * ZS + lp((N - kx) & (N - 1))];
     const cd xa = {0.5 * (zk.x + zn.x), 0.5 * (zk.y - zn.y)};
     const cd xb = {0.5 * (zk.y + zn.y), -0.5 * (zk.x - zn.x)};
     const size_t g = (size_t)kx * N + y0 + rr;
@@ -189,29 +210,29 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
 // partners through LDS.  Call only where kx is 0 or N/2 (uniform per group).
 // (the first NF of the NV register fields are projected)
 template <int N, int E, int NF, int NV>
-__device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd (*lds)[N], int t) {
+__device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd* const (&lds)[2], int t) {
   constexpr int T = N / E;
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NF; ++q)
 #pragma unroll
-    for (int s = 0; s < E; ++s) lds[q][t + s * T] = f[q][s];
+    for (int s = 0; s < E; ++s) lds[q][lp(t + s * T)] = f[q][s];
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NF; ++q)
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      const cd p = lds[q][(N - (t + s * T)) & (N - 1)];
+      const cd p = lds[q][lp((N - (t + s * T)) & (N - 1))];
       f[q][s] = cd{0.5 * (f[q][s].x + p.x), 0.5 * (f[q][s].y - p.y)};
     }
   __syncthreads();
 }
-template <int N, int E, int EPI, int PRO>
+template <int N, int E, int EPI, int PRO, int TWL>
 __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
   constexpr int T = N / E;
   constexpr int M = N / 2;
-  __shared__ cd buf[2][N];
-  __shared__ cd tw[N];
+  __shared__ cd buf[2][lp_size(N)];
+  __shared__ cd twl[TWL ? N : 1];
   __shared__ double red[2 * T];
   if (done && *done) return;
 
@@ -221,8 +242,12 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
   const size_t col = (size_t)kx * N;
   const double wgt = (kx == 0 || kx == M) ? 1.0 : 2.0;  // Parseval weight of the half spectrum
 
-  for (int i = t; i < N; i += T) tw[i] = a.tw[i];
-  __syncthreads();
+  const cd* tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = t; i < N; i += T) twl[i] = a.tw[i];
+    __syncthreads();
+    tw = twl;
+  }
 
   cd v[2][E];
   cd* const base[2] = {buf[0], buf[1]};
@@ -231,10 +256,23 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
   const StepCtl* ctl = a.ctl;
 
   if constexpr (EPI != EPI_NONE) {
+    // state values of this column are loaded before the FFT so that their
+    // latency overlaps it
+    cd pre0[E], pre1[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      v[0][s] = a.P0[col + t + s * T];
-      v[1][s] = a.P1[col + t + s * T];
+      const size_t g = col + t + s * T;
+      v[0][s] = a.P0[g];
+      v[1][s] = a.P1[g];
+      if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
+        pre0[s] = a.s0[g];
+        pre1[s] = a.s1[g];
+      } else if constexpr (EPI == EPI_PSD) {
+        pre0[s] = a.out[g];
+        pre1[s] = a.aux[g];
+      } else {
+        pre0[s] = a.s0[g];
+      }
     }
     fft<N, E, 2, -1>(v, base, tw, t);
 
@@ -253,13 +291,11 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
       cd U;
       cd un = {0, 0}, um = {0, 0};
       if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
-        un = a.s0[g];
-        um = a.s1[g];
+        un = pre0[s];
+        um = pre1[s];
         U = cadd(un, cscale(csub(un, um), ctl->gamma));
-      } else if constexpr (EPI == EPI_PSD) {
-        U = a.out[g];
       } else {
-        U = a.s0[g];
+        U = pre0[s];
       }
       Ua[s] = U;
       una[s] = un;
@@ -291,7 +327,7 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
         o[1][s] = cscale(X, -k2 * inv);
         Ua[s] = X;  // the SAV sums need X
       } else if constexpr (EPI == EPI_PSD) {
-        const cd G = a.aux[g];
+        const cd G = pre1[s];
         cd d = {0.0, 0.0};
         if (k2 != 0.0) {
           const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
@@ -306,9 +342,9 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
     }
     // states written by this pass are spectra of real fields (see hermitian_fix)
     if constexpr (EPI == EPI_IMEX || EPI == EPI_PSD) {
-      if (kx == 0 || kx == M) hermitian_fix<N, E, 1, 2>(o, buf, t);
+      if (kx == 0 || kx == M) hermitian_fix<N, E, 1, 2>(o, base, t);
     } else if constexpr (EPI == EPI_SAV) {
-      if (kx == 0 || kx == M) hermitian_fix<N, E, 2, 2>(o, buf, t);
+      if (kx == 0 || kx == M) hermitian_fix<N, E, 2, 2>(o, base, t);
     }
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -385,16 +421,20 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
 
 // single-field column transforms (boundary fch_forward / fch_inverse):
 // two columns per workgroup, one sequence each
-template <int N, int E, int DIR>
+template <int N, int E, int DIR, int TWL>
 __global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
   constexpr int T = N / E;
   constexpr int H = N / 2 + 1;
-  __shared__ cd buf[2][N];
-  __shared__ cd tw[N];
+  __shared__ cd buf[2][lp_size(N)];
+  __shared__ cd twl[TWL ? N : 1];
   const int t = threadIdx.x;
   const int kx0 = 2 * blockIdx.x;
-  for (int i = t; i < N; i += T) tw[i] = a.tw[i];
-  __syncthreads();
+  const cd* tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = t; i < N; i += T) twl[i] = a.tw[i];
+    __syncthreads();
+    tw = twl;
+  }
   cd v[2][E];
   cd* const base[2] = {buf[0], buf[1]};
 #pragma unroll
@@ -405,7 +445,7 @@ __global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
       v[q][s] = (kx < H) ? a.X_in[(size_t)kx * N + t + s * T] : cd{0.0, 0.0};
   }
   fft<N, E, 2, DIR>(v, base, tw, t);
-  if (DIR < 0 && (kx0 == 0 || kx0 == N / 2)) hermitian_fix<N, E, 1, 2>(v, buf, t);
+  if (DIR < 0 && (kx0 == 0 || kx0 == N / 2)) hermitian_fix<N, E, 1, 2>(v, base, t);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int kx = kx0 + q;

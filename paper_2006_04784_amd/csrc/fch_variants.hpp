@@ -33,14 +33,14 @@ struct RowImpl {
   }
 };
 
-template <int N, int E>
+template <int N, int E, int TWL>
 struct ColImpl {
   static constexpr int CT = N / E;
   static constexpr int H = N / 2 + 1;
 
   template <int EPI, int PRO>
   static hipError_t lc(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col<N, E, EPI, PRO>), dim3(H), dim3(CT), 0, s, a, &a.ctl->done);
+    hipLaunchKernelGGL((k_col<N, E, EPI, PRO, TWL>), dim3(H), dim3(CT), 0, s, a, &a.ctl->done);
     return hipGetLastError();
   }
 
@@ -62,15 +62,15 @@ struct ColImpl {
     return hipErrorInvalidValue;
   }
   static hipError_t col_fwd1(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col1<N, E, -1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL((k_col1<N, E, -1, TWL>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t col_inv1(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col1<N, E, +1>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+    hipLaunchKernelGGL((k_col1<N, E, +1, TWL>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
     return hipGetLastError();
   }
   static const ColVT* table() {
-    static const ColVT vt = {N, E, CT, &col, &col_fwd1, &col_inv1};
+    static const ColVT vt = {N, E, TWL, CT, &col, &col_fwd1, &col_inv1};
     return &vt;
   }
 };

@@ -39,7 +39,7 @@ class fch_params(C.Structure):
 
 class fch_launch_cfg(C.Structure):
     _fields_ = [("row_R", C.c_int32), ("row_E", C.c_int32), ("row_twl", C.c_int32),
-                ("col_E", C.c_int32)]
+                ("col_E", C.c_int32), ("col_twl", C.c_int32)]
 
 
 class fch_stats(C.Structure):
@@ -153,7 +153,7 @@ def sav_constants(prm: fch_params):
 
 def config_list(N: int):
     """Compiled (row variants, column variants) of a grid size: row variants
-    as (R, E, twl), column variants as E."""
+    as (R, E, twl), column variants as (E, twl)."""
     L = lib()
     rows, cols = [], []
     for i in range(L.fch_row_config_count(N)):
@@ -163,7 +163,7 @@ def config_list(N: int):
     for j in range(L.fch_col_config_count(N)):
         c = fch_launch_cfg()
         _check(L.fch_config_get(N, 0, j, C.byref(c)))
-        cols.append(c.col_E)
+        cols.append((c.col_E, c.col_twl))
     return rows, cols
 
 
@@ -238,14 +238,14 @@ class Plan:
         return lib().fch_alpha_m(C.byref(self.prm))
 
     def set_config(self, cfg):
-        """cfg = (row_R, row_E, row_twl, col_E), or None for the default."""
+        """cfg = (row_R, row_E, row_twl, col_E, col_twl), or None for the default."""
         c = None if cfg is None else fch_launch_cfg(*cfg)
         _check(lib().fch_plan_set_config(self.h, None if c is None else C.byref(c)))
 
     def get_config(self):
         c = fch_launch_cfg()
         _check(lib().fch_plan_get_config(self.h, C.byref(c)))
-        return (c.row_R, c.row_E, c.row_twl, c.col_E)
+        return (c.row_R, c.row_E, c.row_twl, c.col_E, c.col_twl)
 
     def autotune(self, uh_n, uh_nm1, k=1e-3, reps=20):
         """Pick the fastest compiled row/column variants on the fused IMEX step;
@@ -256,7 +256,7 @@ class Plan:
         self._sync_stream()
         _check(lib().fch_autotune(self.h, _p(uh_n), _p(uh_nm1), k, reps, C.byref(c),
                                   C.cast(us, _PD)))
-        return (c.row_R, c.row_E, c.row_twl, c.col_E), (us[0], us[1])
+        return (c.row_R, c.row_E, c.row_twl, c.col_E, c.col_twl), (us[0], us[1])
 
     def stats(self):
         s = fch_stats()

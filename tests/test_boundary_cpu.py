@@ -80,10 +80,10 @@ def test_compiled_configurations(fch):
             assert N % rE == 0 and N % (2 * R) == 0 and twl in (0, 1)
             assert rE == N or N >= rE * rE          # radix schedule E ... E
             # LDS: R rows + optional twiddles + reduction scratch <= 160 KiB
-            assert 16 * R * N + 16 * N * twl + 16 * R * (N // rE) <= 160 * 1024
-        for cE in cols:
-            assert N % cE == 0 and (cE == N or N >= cE * cE)
-            assert 2 * 16 * N + 16 * N + 16 * (N // cE) <= 160 * 1024
+            assert 16 * R * (N + N // 8 + 9) + 16 * N * twl + 16 * R * (N // rE) <= 160 * 1024
+        for (cE, ctw) in cols:
+            assert N % cE == 0 and (cE == N or N >= cE * cE) and ctw in (0, 1)
+            assert 2 * 16 * (N + N // 8 + 1) + 16 * N * ctw + 16 * (N // cE) <= 160 * 1024
     assert fch.lib().fch_row_config_count(4096) == 0
     assert fch.lib().fch_col_config_count(100) == 0
     c = fch.fch_launch_cfg()

@@ -355,8 +355,8 @@ def test_every_launch_variant(F, orc, N):
     ref = orc.imex_step(m, u1, uh0, 1e-3, 1e-3)
     for i in range(max(len(rows), len(cols))):
         r, c = rows[i % len(rows)], cols[i % len(cols)]
-        plan.set_config((r[0], r[1], r[2], c))
-        assert plan.get_config() == (r[0], r[1], r[2], c)
+        plan.set_config((r[0], r[1], r[2], c[0], c[1]))
+        assert plan.get_config() == (r[0], r[1], r[2], c[0], c[1])
         uh = plan.forward(torch.from_numpy(u0).cuda())
         assert rel(host(uh), uh0) < 1e-13, (r, c)
         assert rel(plan.inverse(uh).cpu().numpy(), u0) < 1e-13, (r, c)
@@ -377,7 +377,7 @@ def test_autotune_picks_a_compiled_variant(F, orc):
     a0, b0 = a.clone(), b.clone()
     cfg, us = plan.autotune(a, b, k=1e-3, reps=3)
     rows, cols = F.config_list(N)
-    assert cfg[:3] in rows and cfg[3] in cols and us[0] > 0 and us[1] > 0
+    assert cfg[:3] in rows and cfg[3:] in cols and us[0] > 0 and us[1] > 0
     assert torch.equal(a, a0) and torch.equal(b, b0)     # inputs untouched
     out = plan.step_imex(a, b, 1e-3, 1e-3)
     assert rel(host(out), orc.imex_step(m, u1, uh0, 1e-3, 1e-3)) < 1e-10
