@@ -226,6 +226,54 @@ typedef struct {
 fch_status fch_run(fch_plan_t plan, const fch_run_opts* opts, fch_c128* uh_n, fch_c128* uh_nm1,
                    double* rs, fch_run_info* info);
 
+/* ---- batched ensembles ---------------------------------------------------- */
+/* Many independent adaptive BDF2-IMEX runs (Sec. 3.2 step control, each
+ * member with its own parameters, state and step size) advanced together.
+ * Members are grouped by N into size classes; an attempt runs, for every
+ * class, the batched column pass (u*, Lap u*), row pass, column pass (the
+ * IMEX step, then u~, Lap u~), row pass, column pass (F(u~), AM3 sums) and a
+ * per-member controller that accepts or rejects, picks the next step and
+ * rotates the state and F buffers on the device.  Classes run on their own
+ * streams; with use_graph the whole attempt is captured once into a HIP
+ * graph and replayed.  The host reads member status every sync_every
+ * attempts.  Members finish at t_end or after max_steps accepted steps. */
+typedef struct fch_ensemble_s* fch_ensemble_t;
+typedef struct {
+    fch_adapt_opts adapt;
+    double  t_end;       /* end time of every member                              */
+    int64_t max_steps;   /* cap on accepted steps per member (startup included)   */
+    double  k_first;     /* first-order startup step; <= 0 selects adapt.k_min    */
+} fch_ensemble_opts;
+typedef struct { int64_t attempts, accepted, rejected; int32_t active; } fch_ensemble_info;
+typedef struct {
+    int32_t N, done, nonfinite;
+    int64_t accepted, rejected;
+    double  t, k_last, k_next, err;
+} fch_member_info;
+/* Host-side setup: one plan (twiddles, launch variants) per size class on the
+ * current device.  members: count parameter sets (N in 16..2048). */
+fch_status fch_ensemble_create(const fch_params* members, int32_t count,
+                               const fch_ensemble_opts* opts, fch_ensemble_t* out);
+fch_status fch_ensemble_destroy(fch_ensemble_t ens);
+fch_status fch_ensemble_set_stream(fch_ensemble_t ens, void* stream);
+/* Device workspace for every member (three states, three F spectra, the
+ * pair buffer, partial sums, the step log) and each class plan. */
+size_t     fch_ensemble_workspace_bytes(fch_ensemble_t ens);
+fch_status fch_ensemble_set_workspace(fch_ensemble_t ens, void* dptr, size_t bytes);
+/* Loads member i from a physical N*N state (device): forward transform,
+ * F(u^0), a first-order step of size k_first, F(u^1).  Synchronizes. */
+fch_status fch_ensemble_load(fch_ensemble_t ens, int32_t member, const double* u0);
+/* Autotunes each class's launch variants on its first member (after load). */
+fch_status fch_ensemble_autotune(fch_ensemble_t ens, int32_t reps);
+/* Runs attempts until every member finished or max_attempts attempts ran. */
+fch_status fch_ensemble_run(fch_ensemble_t ens, int64_t max_attempts, int32_t sync_every,
+                            int32_t use_graph, fch_ensemble_info* info);
+/* Status of member i (host out); uh (device out, nullable) receives its last
+ * accepted state; klog (host out, nullable, max_steps doubles) its accepted
+ * step sizes.  Synchronizes. */
+fch_status fch_ensemble_member(fch_ensemble_t ens, int32_t member, fch_c128* uh, double* klog,
+                               fch_member_info* info);
+
 const char* fch_status_string(fch_status s);
 
 #ifdef __cplusplus

@@ -10,36 +10,13 @@
 
 #include "fch.h"
 #include "fch_kernels.hpp"
+#include "fch_plan.hpp"
 
 using fch::cd;
 using fch::ColArgs;
 using fch::FinArgs;
 using fch::RowArgs;
 using fch::StepCtl;
-
-struct fch_plan_s {
-  fch_params prm;
-  fch::Consts c;
-  int N, H;
-  const fch::RowVT* rv;
-  const fch::ColVT* cv;
-  hipStream_t stream;
-  int device;
-  cd* tw;
-  StepCtl* ctl;
-  StepCtl* hctl;  // pinned mirror for read-back
-  char* ws;
-  size_t ws_bytes;
-  cd *P0, *P1, *aux, *st, *Fc[3];
-  double *rpart, *cpart;
-  fch_stats stats;
-  int psd_hint;
-  // kernel timing (fch_plan_profile)
-  int prof_on;
-  int prof_n;
-  hipEvent_t* prof_ev;    // 2 per record
-  int* prof_kind;
-};
 
 namespace {
 
@@ -283,6 +260,38 @@ fch_status status_from_ctl(fch_plan_s* p) {
 
 }  // namespace
 
+namespace fch {
+Consts consts_from_params(const fch_params& prm) {
+  Consts c;
+  c.N = prm.N;
+  c.L = prm.L;
+  c.eps = prm.eps;
+  c.inv_eps = 1.0 / prm.eps;
+  c.eps2 = prm.eps * prm.eps;
+  c.eta1 = eff_eta(prm, prm.eta1);
+  c.eta2 = eff_eta(prm, prm.eta2);
+  c.q = prm.q;
+  c.gw3 = prm.gamma_w / 3.0;
+  c.bm = prm.b_minus;
+  c.bp = prm.b_plus;
+  c.bshift = 0.5 * (3.0 * prm.b_plus - prm.b_minus);
+  c.alpha = fch_alpha_m(&prm);
+  c.beta1 = prm.beta1;
+  c.beta2 = prm.beta2;
+  c.zeta = prm.zeta;
+  c.D0 = prm.D0;
+  const double tk = 2.0 * M_PI / prm.L;
+  c.kscale = tk * tk;
+  c.invN2 = 1.0 / ((double)prm.N * (double)prm.N);
+  const double h = prm.L / prm.N;
+  c.h2 = h * h;
+  c.pars = prm.L * prm.L / ((double)prm.N * prm.N * (double)prm.N * prm.N);
+  return c;
+}
+
+fch_status validate_params_internal(const fch_params* p) { return validate_params(p); }
+}  // namespace fch
+
 static fch_status copy_spec(fch_plan_t p, cd* dst, const cd* src);
 
 // ===========================================================================
@@ -337,30 +346,7 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
   p->rv = fch::row_variant(prm->N, 0);
   p->cv = fch::col_variant(prm->N, 0);
   p->psd_hint = 4;
-  fch::Consts& c = p->c;
-  c.N = prm->N;
-  c.L = prm->L;
-  c.eps = prm->eps;
-  c.inv_eps = 1.0 / prm->eps;
-  c.eps2 = prm->eps * prm->eps;
-  c.eta1 = eff_eta(*prm, prm->eta1);
-  c.eta2 = eff_eta(*prm, prm->eta2);
-  c.q = prm->q;
-  c.gw3 = prm->gamma_w / 3.0;
-  c.bm = prm->b_minus;
-  c.bp = prm->b_plus;
-  c.bshift = 0.5 * (3.0 * prm->b_plus - prm->b_minus);
-  c.alpha = fch_alpha_m(prm);
-  c.beta1 = prm->beta1;
-  c.beta2 = prm->beta2;
-  c.zeta = prm->zeta;
-  c.D0 = prm->D0;
-  const double tk = 2.0 * M_PI / prm->L;
-  c.kscale = tk * tk;
-  c.invN2 = 1.0 / ((double)prm->N * (double)prm->N);
-  const double h = prm->L / prm->N;
-  c.h2 = h * h;
-  c.pars = prm->L * prm->L / ((double)prm->N * prm->N * (double)prm->N * prm->N);
+  p->c = fch::consts_from_params(*prm);
 
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FCH_E_HIP; }
   // twiddles exp(-2 pi i m / N), evaluated in extended precision

@@ -110,6 +110,73 @@ __global__ void k_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n) {
   }
 }
 
+// Per-member controller of a batched adaptive BDF2-IMEX attempt (Sec. 3.2,
+// Steps 3-4 and Step 0 of the next step): relative AM3 error from the
+// column partial sums, accept / reject, the next trial step, slot rotation,
+// and the BDF2 / AM3 scalars of the next attempt.
+__global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) {
+  __shared__ double red[256];
+  EnsMember* m = mem + first + blockIdx.x;
+  if (m->ctl.done) return;
+  const double c0 = sum_strided(m->cpart, m->H, 2, 0, red);
+  const double c1 = sum_strided(m->cpart, m->H, 2, 1, red);
+  if (threadIdx.x != 0) return;
+  StepCtl& ctl = m->ctl;
+  const double kt = ctl.k_np1;
+  const double e = sqrt(c0 / c1);
+  const double ee = e > 1e-300 ? e : 1e-300;
+  double kn = ctl.rho_s * cbrt(ctl.sigma_tol / ee) * kt;
+  if (ctl.cap > 0.0 && kn > ctl.cap * kt) kn = ctl.cap * kt;
+  if (kn > ctl.k_max) kn = ctl.k_max;
+  if (kn < ctl.k_min) kn = ctl.k_min;
+  const int accept = (e <= ctl.sigma_tol) || (kt <= ctl.k_min);
+  ctl.err = e;
+  ctl.k_next = kn;
+  ctl.accept = accept;
+  if (!isfinite(e)) {
+    ctl.nonfinite = 1;
+    ctl.done = 1;
+    return;
+  }
+  if (accept) {
+    const int op = m->prev;
+    m->prev = m->cur;
+    m->cur = m->trial;
+    m->trial = op;
+    const int ofm = m->fm;
+    m->fm = m->fn;
+    m->fn = m->ft;
+    m->ft = ofm;
+    m->t += kt;
+    if (m->accepted < m->klog_cap) m->klog[m->accepted] = kt;
+    m->accepted += 1;
+    ctl.k_n = kt;
+  } else {
+    m->rejected += 1;
+  }
+  if (m->t >= m->t_end * (1.0 - 1e-14) || m->accepted >= m->max_accepted) {
+    ctl.done = 1;
+    return;
+  }
+  double k1 = kn;
+  if (k1 > m->t_end - m->t) k1 = m->t_end - m->t;
+  const double k0 = ctl.k_n;
+  ctl.k_np1 = k1;
+  ctl.a = 1.0 / k1 + 1.0 / (k1 + k0);
+  ctl.b = -1.0 / k1 - 1.0 / k0;
+  ctl.c = 1.0 / k0 - 1.0 / (k1 + k0);
+  const double g = k1 / k0;
+  ctl.gamma = g;
+  ctl.w1 = k1 / 6.0 * (3.0 + 2.0 * g) / (1.0 + g);
+  ctl.w2 = k1 / 6.0 * (3.0 + g);
+  ctl.w3 = -k1 / 6.0 * g * g / (1.0 + g);
+}
+
+hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_ens_control, dim3(count), dim3(256), 0, s, m, first);
+  return hipGetLastError();
+}
+
 hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(1), 0, s, ctl, v);
   return hipGetLastError();

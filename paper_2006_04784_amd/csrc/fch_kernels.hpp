@@ -72,17 +72,43 @@ struct FinArgs {
   int mode;
 };
 
+// One member of a batched ensemble (device memory).  The batched kernels
+// read their buffers through the ring slots; the per-member controller
+// rotates the slots on accepted steps and writes the next attempt's scalars
+// into ctl, so an attempt is a fixed launch sequence that can be captured.
+struct EnsMember {
+  Consts c;
+  StepCtl ctl;  // ctl.done = 1 once the member finished
+  const cd* tw;
+  cd* ring[3];   // states: slots cur, prev, trial
+  cd* fring[3];  // F = Lap mu of the states: slots fn, fm, ft
+  cd* P0;
+  cd* P1;
+  double* cpart;  // 2 per column
+  double* klog;   // accepted step sizes
+  long long klog_cap;
+  int cur, prev, trial, fn, fm, ft;
+  double t, t_end;
+  long long accepted, rejected, max_accepted;
+  int H;
+  int pad;
+};
+enum EnsStage { ENS_PRO = 0, ENS_IMEX = 1, ENS_AM3 = 2 };
+
 // Launch tables of the compiled variants of one grid size.  Row-pass and
 // column-pass variants are chosen independently.
 struct RowVT {
   int N, R, E, twl, threads;
   hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s);
+  // batched row pass (chemical-potential pieces) over members [first, first+count)
+  hipError_t (*row_ens)(EnsMember* m, int first, int count, hipStream_t s);
 };
 struct ColVT {
   int N, E, twl, threads;
   hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s);
   hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s);
   hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s);
+  hipError_t (*col_ens)(int stage, EnsMember* m, int first, int count, hipStream_t s);
 };
 
 // registry: the first entry of each list is the default for N
@@ -94,5 +120,7 @@ const ColVT* col_variant(int N, int i);
 hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s);
+// per-member AM3 decision, slot rotation and next-attempt scalars
+hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s);
 
 }  // namespace fch

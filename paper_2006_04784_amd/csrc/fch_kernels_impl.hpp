@@ -57,7 +57,7 @@ __device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, 
 // TWL: twiddle table copied to LDS (1) or read from global memory through
 // the vector caches (0, frees N*16 bytes of LDS per workgroup)
 template <int N, int R, int E, int MODE, int TWL>
-__global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
+__device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   constexpr int T = N / E;
   constexpr int NT = R * T;
   constexpr int M = N / 2;
@@ -228,7 +228,7 @@ __device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd* const (&lds)[2
   __syncthreads();
 }
 template <int N, int E, int EPI, int PRO, int TWL>
-__global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
+__device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
   constexpr int T = N / E;
   constexpr int M = N / 2;
   __shared__ cd buf[2][lp_size(N)];
@@ -416,6 +416,79 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
 
   if constexpr (EPI == EPI_MU || EPI == EPI_SAV || EPI == EPI_PSD || EPI == EPI_AM3) {
     if (a.partial) block_reduce<T, 2>(acc, red, a.partial + 2 * kx);
+  }
+}
+
+template <int N, int R, int E, int MODE, int TWL>
+__global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
+  row_body<N, R, E, MODE, TWL>(a, done);
+}
+
+template <int N, int E, int EPI, int PRO, int TWL>
+__global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
+  col_body<N, E, EPI, PRO, TWL>(a, done);
+}
+
+// ---- batched ensemble entry points (member = blockIdx.y) --------------------
+__device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
+  a.c = m->c;
+  a.P0 = m->P0;
+  a.P1 = m->P1;
+  a.s0 = nullptr;
+  a.s1 = nullptr;
+  a.out = nullptr;
+  a.aux = nullptr;
+  a.guess = nullptr;
+  a.f_n = nullptr;
+  a.f_nm1 = nullptr;
+  a.X_in = nullptr;
+  a.X_out = nullptr;
+  a.partial = nullptr;
+  a.ctl = const_cast<StepCtl*>(&m->ctl);
+  a.tw = m->tw;
+}
+
+template <int N, int R, int E, int TWL>
+__global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first) {
+  EnsMember* m = mem + first + blockIdx.y;
+  RowArgs a;
+  a.c = m->c;
+  a.P0 = m->P0;
+  a.P1 = m->P1;
+  a.u_in = nullptr;
+  a.u_out = nullptr;
+  a.X_in = nullptr;
+  a.X_out = nullptr;
+  a.partial = nullptr;
+  a.ctl = &m->ctl;
+  a.tw = m->tw;
+  row_body<N, R, E, ROW_MU, TWL>(a, &m->ctl.done);
+}
+
+// one attempt of adaptive BDF2-IMEX: PRO (u* and Lap u* of the step),
+// IMEX (the step, then u~ and Lap u~ for F(u~)), AM3 (F(u~) and the error sums)
+template <int N, int E, int TWL, int STAGE>
+__global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
+  EnsMember* m = mem + first + blockIdx.y;
+  ColArgs a;
+  ens_col_args(m, a);
+  if constexpr (STAGE == ENS_PRO) {
+    a.s0 = m->ring[m->cur];
+    a.s1 = m->ring[m->prev];
+    col_body<N, E, EPI_NONE, PRO_EXTRAP, TWL>(a, &m->ctl.done);
+  } else if constexpr (STAGE == ENS_IMEX) {
+    a.s0 = m->ring[m->cur];
+    a.s1 = m->ring[m->prev];
+    a.out = m->ring[m->trial];
+    col_body<N, E, EPI_IMEX, PRO_NEXT_FIELD, TWL>(a, &m->ctl.done);
+  } else {
+    a.s0 = m->ring[m->trial];
+    a.s1 = m->ring[m->cur];
+    a.f_n = m->fring[m->fn];
+    a.f_nm1 = m->fring[m->fm];
+    a.out = m->fring[m->ft];
+    a.partial = m->cpart;
+    col_body<N, E, EPI_AM3, PRO_NONE, TWL>(a, &m->ctl.done);
   }
 }
 

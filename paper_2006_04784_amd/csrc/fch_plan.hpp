@@ -1,0 +1,37 @@
+// fch_plan.hpp -- the plan object shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fch.h"
+#include "fch_kernels.hpp"
+
+struct fch_plan_s {
+  fch_params prm;
+  fch::Consts c;
+  int N, H;
+  const fch::RowVT* rv;
+  const fch::ColVT* cv;
+  hipStream_t stream;
+  int device;
+  fch::cd* tw;
+  fch::StepCtl* ctl;
+  fch::StepCtl* hctl;  // pinned mirror for read-back
+  char* ws;
+  size_t ws_bytes;
+  fch::cd *P0, *P1, *aux, *st, *Fc[3];
+  double *rpart, *cpart;
+  fch_stats stats;
+  int psd_hint;
+  // kernel timing (fch_plan_profile)
+  int prof_on;
+  int prof_n;
+  hipEvent_t* prof_ev;    // 2 per record
+  int* prof_kind;
+};
+
+
+namespace fch {
+// model constants of a parameter set (effective eta, alpha_m, wavenumber scale)
+Consts consts_from_params(const fch_params& prm);
+fch_status validate_params_internal(const fch_params* p);
+}  // namespace fch

@@ -27,8 +27,12 @@ struct RowImpl {
     }
     return hipGetLastError();
   }
+  static hipError_t row_ens(EnsMember* m, int first, int count, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_ens<N, R, E, TWL>), dim3(N / R, count), dim3(NT), 0, s, m, first);
+    return hipGetLastError();
+  }
   static const RowVT* table() {
-    static const RowVT vt = {N, R, E, TWL, NT, &row};
+    static const RowVT vt = {N, R, E, TWL, NT, &row, &row_ens};
     return &vt;
   }
 };
@@ -69,8 +73,25 @@ struct ColImpl {
     hipLaunchKernelGGL((k_col1<N, E, +1, TWL>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
     return hipGetLastError();
   }
+  static hipError_t col_ens(int stage, EnsMember* m, int first, int count, hipStream_t s) {
+    const dim3 grid(H, count);
+    switch (stage) {
+      case ENS_PRO:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_PRO>), grid, dim3(CT), 0, s, m, first);
+        break;
+      case ENS_IMEX:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_IMEX>), grid, dim3(CT), 0, s, m, first);
+        break;
+      case ENS_AM3:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_AM3>), grid, dim3(CT), 0, s, m, first);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   static const ColVT* table() {
-    static const ColVT vt = {N, E, TWL, CT, &col, &col_fwd1, &col_inv1};
+    static const ColVT vt = {N, E, TWL, CT, &col, &col_fwd1, &col_inv1, &col_ens};
     return &vt;
   }
 };

@@ -78,6 +78,22 @@ class fch_run_info(C.Structure):
                 ("k_next", C.c_double)]
 
 
+class fch_ensemble_opts(C.Structure):
+    _fields_ = [("adapt", fch_adapt_opts), ("t_end", C.c_double), ("max_steps", C.c_int64),
+                ("k_first", C.c_double)]
+
+
+class fch_ensemble_info(C.Structure):
+    _fields_ = [("attempts", C.c_int64), ("accepted", C.c_int64), ("rejected", C.c_int64),
+                ("active", C.c_int32)]
+
+
+class fch_member_info(C.Structure):
+    _fields_ = [("N", C.c_int32), ("done", C.c_int32), ("nonfinite", C.c_int32),
+                ("accepted", C.c_int64), ("rejected", C.c_int64), ("t", C.c_double),
+                ("k_last", C.c_double), ("k_next", C.c_double), ("err", C.c_double)]
+
+
 _V = C.c_void_p
 _D = C.c_double
 _I = C.c_int32
@@ -114,6 +130,16 @@ _SIGS = {
                           _PD, _PD]),
     "fch_rhs": (_I, [_V, _V, _V]),
     "fch_run": (_I, [_V, C.POINTER(fch_run_opts), _V, _V, _PD, C.POINTER(fch_run_info)]),
+    "fch_ensemble_create": (_I, [C.POINTER(fch_params), _I, C.POINTER(fch_ensemble_opts),
+                                 C.POINTER(_V)]),
+    "fch_ensemble_destroy": (_I, [_V]),
+    "fch_ensemble_set_stream": (_I, [_V, _V]),
+    "fch_ensemble_workspace_bytes": (C.c_size_t, [_V]),
+    "fch_ensemble_set_workspace": (_I, [_V, _V, C.c_size_t]),
+    "fch_ensemble_load": (_I, [_V, _I, _V]),
+    "fch_ensemble_autotune": (_I, [_V, _I]),
+    "fch_ensemble_run": (_I, [_V, C.c_int64, _I, _I, C.POINTER(fch_ensemble_info)]),
+    "fch_ensemble_member": (_I, [_V, _I, _V, _PD, C.POINTER(fch_member_info)]),
     "fch_status_string": (C.c_char_p, [_I]),
 }
 
@@ -373,3 +399,84 @@ class Plan:
         d = {k_: getattr(info, k_) for k_, _ in fch_run_info._fields_}
         d["rs"] = (r[0], r[1])
         return d
+
+
+class Ensemble:
+    """Batched adaptive BDF2-IMEX runs (fch_ensemble_* of the C ABI).
+
+    members: list of dicts of Plan keyword arguments (N, L, eps, eta1, eta2, ...)."""
+
+    def __init__(self, members, adapt: AdaptOpts = None, t_end=1.0, max_steps=1000, k_first=0.0,
+                 device="cuda:0"):
+        self.device = torch.device(device)
+        prms = []
+        for kw in members:
+            kw = dict(kw)
+            prm = fch_params(kw["N"], kw["L"], kw["eps"], kw["eta1"], kw["eta2"], kw.get("p", 1),
+                             kw.get("q", 0.0), kw.get("gamma_w", 0.3), kw.get("b_minus", -1.0),
+                             kw.get("b_plus", 1.0), kw.get("beta1", 2.0), kw.get("beta2", 1.0),
+                             0.0, 0.0)
+            z, d = sav_constants(prm)
+            prm.zeta, prm.D0 = kw.get("zeta", z), kw.get("D0", d)
+            prms.append(prm)
+        arr = (fch_params * len(prms))(*prms)
+        self.Ns = [m["N"] for m in members]
+        self.max_steps = max_steps
+        opts = fch_ensemble_opts((adapt or AdaptOpts()).c(), t_end, max_steps, k_first)
+        h = _V()
+        with torch.cuda.device(self.device):
+            _check(lib().fch_ensemble_create(arr, len(prms), C.byref(opts), C.byref(h)))
+        self.h = h
+        nbytes = lib().fch_ensemble_workspace_bytes(h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        _check(lib().fch_ensemble_set_workspace(h, _V(self.ws.data_ptr() + off), nbytes))
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().fch_ensemble_set_stream(self.h, _V(s)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fch_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, i, u0):
+        N = self.Ns[i]
+        if u0.dtype != torch.float64 or tuple(u0.shape) != (N, N) or not u0.is_contiguous():
+            raise ValueError("expected contiguous float64 (N, N) for member %d" % i)
+        self._sync_stream()
+        _check(lib().fch_ensemble_load(self.h, i, _p(u0)))
+
+    def autotune(self, reps=10):
+        self._sync_stream()
+        _check(lib().fch_ensemble_autotune(self.h, reps))
+
+    def run(self, max_attempts=100000, sync_every=50, use_graph=True):
+        info = fch_ensemble_info()
+        self._sync_stream()
+        _check(lib().fch_ensemble_run(self.h, max_attempts, sync_every, int(use_graph),
+                                      C.byref(info)))
+        return {k: getattr(info, k) for k, _ in fch_ensemble_info._fields_}
+
+    def member(self, i, state=True, klog=True):
+        import numpy as np
+        N = self.Ns[i]
+        uh = torch.empty((N // 2 + 1, N), dtype=torch.complex128, device=self.device) \
+            if state else None
+        log = np.zeros(self.max_steps) if klog else None
+        info = fch_member_info()
+        self._sync_stream()
+        _check(lib().fch_ensemble_member(self.h, i, _p(uh),
+                                         log.ctypes.data_as(_PD) if klog else None,
+                                         C.byref(info)))
+        d = {k: getattr(info, k) for k, _ in fch_member_info._fields_}
+        if klog:
+            log = log[:min(d["accepted"], self.max_steps)]
+        return uh, log, d

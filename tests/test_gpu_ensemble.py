@@ -1,0 +1,121 @@
+"""GPU tests of the batched ensemble (device-side adaptive step control in
+captured HIP graphs): each member against an independent single run and the
+oracle, graph replay against eager launches, and mixed grid sizes."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2006_04784_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_04784_amd import fch
+    fch.lib()
+    return fch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def members_small():
+    out = []
+    for i, (N, e1, e2) in enumerate([(64, 1.45, 2.0), (128, 1.3, 1.7), (64, 1.55, 2.3),
+                                     (128, 1.2, 2.5), (32, 1.5, 1.9)]):
+        L = N * 4 * np.pi / 256 if N >= 64 else 2 * np.pi
+        out.append(dict(N=N, L=L, eps=0.1, eta1=e1, eta2=e2, zeta=1.1, D0=L * L * 1.05))
+    return out
+
+
+def initial(m, seed):
+    return inputs.circle_bilayer(m["N"], m["L"], m["eps"], seed=seed)
+
+
+def build(F, mem, use_max=40, t_end=10.0):
+    ens = F.Ensemble(mem, adapt=F.AdaptOpts(sigma_tol=1e-5), t_end=t_end, max_steps=use_max)
+    for i, m in enumerate(mem):
+        ens.load(i, torch.from_numpy(initial(m, seed=10 + i)).cuda())
+    return ens
+
+
+def test_ensemble_members_match_single_runs(F):
+    log("ensemble vs single runs")
+    mem = members_small()
+    ens = build(F, mem)
+    info = ens.run(max_attempts=1000, sync_every=7, use_graph=True)
+    assert info["active"] == 0
+    for i, m in enumerate(mem):
+        uh, klog, mi = ens.member(i)
+        assert mi["done"] and mi["accepted"] == 40 and not mi["nonfinite"]
+        plan = F.Plan(**m)
+        a = plan.forward(torch.from_numpy(initial(m, seed=10 + i)).cuda())
+        b = torch.empty_like(a)
+        ri = plan.run(a, b, scheme="imex", adaptive=True, startup=True, t_end=10.0,
+                      adapt=F.AdaptOpts(sigma_tol=1e-5), nsteps=40)
+        assert ri["accepted"] == mi["accepted"]
+        assert rel(uh.cpu().numpy(), a.cpu().numpy()) < 1e-12
+        assert abs(ri["t"] - mi["t"]) < 1e-12 * ri["t"]
+
+
+def test_ensemble_member_replayed_by_oracle(F, orc):
+    log("ensemble member oracle replay")
+    mem = members_small()[:2]
+    ens = build(F, mem, use_max=30)
+    ens.run(max_attempts=500, sync_every=5, use_graph=True)
+    for i, m in enumerate(mem):
+        uh, klog, mi = ens.member(i)
+        om = orc.Model(**m)
+        u0 = orc.r2c(initial(m, seed=10 + i))
+        prev, cur = u0, orc.imex_step(om, u0, None, klog[0], -1.0)
+        for j in range(1, len(klog)):
+            prev, cur = cur, orc.imex_step(om, cur, prev, klog[j], klog[j - 1])
+        assert len(klog) == 30 and klog[-1] > 100 * klog[0]
+        assert rel(uh.cpu().numpy().T, cur) < 1e-8
+
+
+def test_graph_replay_equals_eager(F):
+    log("ensemble graph vs eager")
+    mem = members_small()
+    e1 = build(F, mem, use_max=25)
+    e1.run(max_attempts=1000, sync_every=1, use_graph=False)
+    e2 = build(F, mem, use_max=25)
+    # several replays, each followed by the host's own read-back and sync
+    for _ in range(200):
+        info = e2.run(max_attempts=1, sync_every=1, use_graph=True)
+        torch.cuda.synchronize()
+        if info["active"] == 0:
+            break
+    for i in range(len(mem)):
+        u1, k1, m1 = e1.member(i)
+        u2, k2, m2 = e2.member(i)
+        assert m1["accepted"] == m2["accepted"] and m1["rejected"] == m2["rejected"]
+        assert np.array_equal(k1, k2)
+        assert torch.equal(u1, u2)
+
+
+def test_mixed_sizes_autotuned(F):
+    log("ensemble mixed sizes autotuned")
+    rng = np.random.default_rng(7)
+    mem = []
+    for N in (256, 128, 512, 256):
+        L = N * 4 * np.pi / 256
+        mem.append(dict(N=N, L=L, eps=0.1, eta1=rng.uniform(1.2, 1.6),
+                        eta2=rng.uniform(1.5, 2.5)))
+    ens = build(F, mem, use_max=20)
+    ens.autotune(reps=2)
+    info = ens.run(max_attempts=1000, sync_every=10, use_graph=True)
+    assert info["active"] == 0 and info["accepted"] == 20 * len(mem)
+    for i, m in enumerate(mem):
+        uh, klog, mi = ens.member(i)
+        assert torch.isfinite(uh).all() and mi["accepted"] == 20
