@@ -216,6 +216,45 @@ def main():
         extra["fft2d_GBps"] = round(fft_bytes / per_fft / 1e9, 1)
         extra["fft2d_bytes"] = fft_bytes
         del U, Uh
+    if not args.no_extra:
+        # batched ensemble: 64 adaptive IMEX runs of mixed size in captured graphs
+        log("ensemble of 64 mixed-size adaptive runs")
+        rng = np.random.default_rng(2024)
+        mem = []
+        for i in range(64):
+            Ni = int(rng.choice([128, 256, 512, 1024]))
+            Li = Ni * 4 * np.pi / 256
+            mem.append(dict(N=Ni, L=Li, eps=0.1, eta1=float(rng.uniform(1.2, 1.6)),
+                            eta2=float(rng.uniform(1.5, 2.5))))
+        ens_steps = 600
+        ens = fch.Ensemble(mem, adapt=fch.AdaptOpts(sigma_tol=1e-5), t_end=1e9,
+                           max_steps=ens_steps)
+        for i, mi in enumerate(mem):
+            ens.load(i, torch.from_numpy(inputs.circle_bilayer(
+                mi["N"], mi["L"], 0.1, seed=100 + i)).to(dev))
+        ens.autotune(reps=3)
+        ens.run(max_attempts=20, sync_every=20, use_graph=True)     # warm-up attempts
+        torch.cuda.synchronize()
+        before = sum(ens.member(i, state=False, klog=False)[2]["accepted"] for i in range(64))
+        t0 = time.perf_counter()
+        info = ens.run(max_attempts=100000, sync_every=100, use_graph=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        extra["ensemble_accepted_steps_per_s"] = round((info["accepted"] - before) / el, 1)
+        extra["ensemble"] = {"members": 64, "sizes": {str(n): sum(m["N"] == n for m in mem)
+                                                      for n in (128, 256, 512, 1024)},
+                             "steps_per_member": ens_steps, "attempts": info["attempts"],
+                             "rejected": info["rejected"], "seconds": round(el, 3)}
+        ens.close()
+    if not args.no_extra:
+        # learned PSD warm start at 256^2: PSD FFT calls per step, learned vs plain
+        log("learned PSD warm start (data, training, held-out comparison)")
+        from paper_2006_04784_amd import learned
+        ev, _net, _plan = learned.run_experiment(range(16), [900, 901], nsteps=80, epochs=20,
+                                                 batch=16, log=None, device=dev)
+        ev.pop("per_step")
+        extra["learned_warm_start"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                       for k, v in ev.items()}
     if args.copy_probe:
         # a plain elementwise copy of known size: 256 MiB read, 256 MiB written
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

@@ -274,6 +274,57 @@ fch_status fch_ensemble_run(fch_ensemble_t ens, int64_t max_attempts, int32_t sy
 fch_status fch_ensemble_member(fch_ensemble_t ens, int32_t member, fch_c128* uh, double* klog,
                                fch_member_info* info);
 
+/* ---- learned PSD warm start (network kernels) ----------------------------- */
+/* A 3x3 periodic convolutional network maps (u^n, u^{n-1}, k) to a correction
+ * of the extrapolated initial iterate of eq. recurrence; PSD then iterates
+ * from the corrected guess to the same stopping tolerance.  Tensors are
+ * device memory owned by the caller:
+ *   activations bf16 [B][H][W][32] (NHWC, unused channels zero),
+ *   weights     bf16 [9][cout][32] (tap = (dy+1)*3 + (dx+1), out, in channel),
+ *   bias        f32  [cout], net output f32 [B][H][W];
+ * cout = 32 for hidden layers (SiLU), 16 for the output layer (channel 0 is
+ * the output, no activation).  H % 16 == 0, W % 32 == 0.  Products run on the
+ * BF16 matrix cores with FP32 accumulation; stored activations are rounded
+ * to bfloat16 (nearest, ties to even).  stream: a hipStream_t. */
+/* z = bias + conv(x, w); hidden: z and y = SiLU(z) (bf16); output: o (f32). */
+fch_status fch_nn_conv_fwd(int32_t B, int32_t H, int32_t W, int32_t cout, const void* x,
+                           const void* w, const float* bias, void* z, void* y, float* o,
+                           void* stream);
+/* dz_prev = SiLU'(z_prev) * (gradient of the layer input), bf16; wt: scratch
+ * of 9*32*32 bf16 (the flipped, transposed weights). */
+fch_status fch_nn_conv_bwd_data(int32_t B, int32_t H, int32_t W, int32_t cout, const void* dz,
+                                const void* w, const void* z_prev, void* dz_prev, void* wt,
+                                void* stream);
+/* dw_db (f32): [9][cout][32] weight gradient then [cout] bias gradient, summed
+ * over all pixels in a fixed order; scratch: fch_nn_bwd_w_scratch_floats f32. */
+size_t     fch_nn_bwd_w_scratch_floats(int32_t B, int32_t H, int32_t W);
+fch_status fch_nn_conv_bwd_w(int32_t B, int32_t H, int32_t W, int32_t cout, const void* dz,
+                             const void* x, float* dw_db, float* scratch, void* stream);
+/* partial sums of (o - t)^2 / n per block (part[nblocks]; their sum is the
+ * mean squared error) and the output-layer
+ * gradient dz (bf16, 32 channels, channel 0 = 2 (o - t) / n). */
+fch_status fch_nn_mse(int32_t n, const float* o, const float* target, void* dz, float* part,
+                      int32_t nblocks, void* stream);
+/* Adam step on FP32 parameters (bias-corrected, step >= 1); p_bf16 (nullable)
+ * receives the rounded copy used by the convolutions. */
+fch_status fch_nn_adam(int32_t n, float* p, const float* g, float* m, float* v, void* p_bf16,
+                       double lr, double beta1, double beta2, double eps, int32_t step,
+                       void* stream);
+fch_status fch_nn_to_bf16(int32_t n, const float* p, void* p_bf16, void* stream);
+/* Features of B samples of physical fields (f64 [B][H][W]); k: [B][2] = (k_{n+1},
+ * k_n).  d = (u^n - u^{n-1}) k_{n+1}/k_n, scale s = RMS(d) (f64 [B] out),
+ * x = [u^n, d/s, (log10 k_{n+1} + 3)/2, 0, ...] (bf16), and the target
+ * (u^{n+1} - u^n - d)/s (f32, only when u_np1 and target are non-NULL). */
+fch_status fch_nn_features(int32_t B, int32_t H, int32_t W, const double* u_n, const double* u_nm1,
+                           const double* u_np1, const double* k, void* x, float* target,
+                           double* scale, void* stream);
+/* g = u^n + d + s * o (physical f64 [B][H][W]). */
+fch_status fch_nn_guess(int32_t B, int32_t H, int32_t W, const double* u_n, const double* u_nm1,
+                        const double* k, const double* scale, const float* o, double* g,
+                        void* stream);
+/* sums of fixed-size partials: out[i] = sum_k part[k*len + i] (f32) */
+fch_status fch_nn_reduce(int32_t nparts, int32_t len, const float* part, float* out, void* stream);
+
 const char* fch_status_string(fch_status s);
 
 #ifdef __cplusplus

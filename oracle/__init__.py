@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fch_oracle.c")
+_SRC_NN = os.path.join(_HERE, "nn_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +30,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared",
-               "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-std=c11", "-Wall", "-o", tmp, _SRC, _SRC_NN, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -110,6 +111,13 @@ def _load():
         "oracle_adapt_decide": (None, [C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, C.c_double,
                                        C.POINTER(C.c_int), _D]),
+        "nn_bf16": (C.c_double, [C.c_double]),
+        "nn_conv_fwd": (None, [C.c_int, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D, _D, _D,
+                               C.c_int]),
+        "nn_conv_bwd_data": (None, [C.c_int, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D,
+                                    C.c_int]),
+        "nn_conv_bwd_w": (None, [C.c_int, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D]),
+        "nn_mse": (C.c_double, [C.c_long, _D, _D, _D, C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -367,3 +375,78 @@ def run_fixed(m: Model, scheme: str, uh0, k: float, nsteps: int, r0=None, psd_to
     if record:
         return un, states
     return un
+
+
+# ---- learned warm start network (nn_oracle.c) ---------------------------------
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), elementwise."""
+    x = np.asarray(x, dtype=np.float64)
+    f = x.astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    special = (u & 0x7F800000) == 0x7F800000
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    r = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(special, x, r)
+
+
+def nn_conv_fwd(x, w, bias, round_bf16=True):
+    """x (B, H, W, 32), w (9, cout, 32), bias (cout,): (z, y) for cout 32, o for 16."""
+    x, w, bias = _real(x), _real(w), _real(bias)
+    B, H, W, _ = x.shape
+    cout = w.shape[1]
+    z = np.zeros((B, H, W, 32))
+    y = np.zeros((B, H, W, 32))
+    o = np.zeros((B, H, W))
+    _load().nn_conv_fwd(B, H, W, cout, _ptr(x), _ptr(w), _ptr(bias), _ptr(z), _ptr(y), _ptr(o),
+                        int(round_bf16))
+    return (z, y) if cout == 32 else o
+
+
+def nn_conv_bwd_data(dz, w, z_prev, round_bf16=True):
+    dz, w, z_prev = _real(dz), _real(w), _real(z_prev)
+    B, H, W, _ = dz.shape
+    out = np.zeros((B, H, W, 32))
+    _load().nn_conv_bwd_data(B, H, W, w.shape[1], _ptr(dz), _ptr(w), _ptr(z_prev), _ptr(out),
+                             int(round_bf16))
+    return out
+
+
+def nn_conv_bwd_w(dz, x, cout):
+    dz, x = _real(dz), _real(x)
+    B, H, W, _ = dz.shape
+    dw = np.zeros((9, cout, 32))
+    db = np.zeros(cout)
+    _load().nn_conv_bwd_w(B, H, W, cout, _ptr(dz), _ptr(x), _ptr(dw), _ptr(db))
+    return dw, db
+
+
+def nn_mse(o, t, round_bf16=True):
+    o, t = _real(o), _real(t)
+    dz = np.zeros(o.shape + (32,))
+    loss = _load().nn_mse(o.size, _ptr(o), _ptr(t), _ptr(dz), int(round_bf16))
+    return loss, dz
+
+
+def nn_loss_and_grads(x, params, target, round_bf16=True):
+    """Whole network: params = [(w, b), ...] (hidden layers cout 32, last
+    cout 16).  Returns (loss, [(dw, db), ...], o)."""
+    acts = [bf16(x) if round_bf16 else _real(x)]
+    zs = []
+    nl = len(params)
+    for i, (w, b) in enumerate(params):
+        wq = bf16(w) if round_bf16 else w
+        if i < nl - 1:
+            z, y = nn_conv_fwd(acts[-1], wq, b, round_bf16)
+            zs.append(z)
+            acts.append(y)
+        else:
+            o = nn_conv_fwd(acts[-1], wq, b, round_bf16)
+    loss, dz = nn_mse(o, target, round_bf16)
+    grads = [None] * nl
+    for i in range(nl - 1, -1, -1):
+        w, b = params[i]
+        wq = bf16(w) if round_bf16 else w
+        grads[i] = nn_conv_bwd_w(dz, acts[i], w.shape[1])
+        if i > 0:
+            dz = nn_conv_bwd_data(dz, wq, zs[i - 1], round_bf16)
+    return loss, grads, o

@@ -140,6 +140,16 @@ _SIGS = {
     "fch_ensemble_autotune": (_I, [_V, _I]),
     "fch_ensemble_run": (_I, [_V, C.c_int64, _I, _I, C.POINTER(fch_ensemble_info)]),
     "fch_ensemble_member": (_I, [_V, _I, _V, _PD, C.POINTER(fch_member_info)]),
+    "fch_nn_conv_fwd": (_I, [_I, _I, _I, _I, _V, _V, _V, _V, _V, _V, _V]),
+    "fch_nn_conv_bwd_data": (_I, [_I, _I, _I, _I, _V, _V, _V, _V, _V, _V]),
+    "fch_nn_bwd_w_scratch_floats": (C.c_size_t, [_I, _I, _I]),
+    "fch_nn_conv_bwd_w": (_I, [_I, _I, _I, _I, _V, _V, _V, _V, _V]),
+    "fch_nn_mse": (_I, [_I, _V, _V, _V, _V, _I, _V]),
+    "fch_nn_adam": (_I, [_I, _V, _V, _V, _V, _V, _D, _D, _D, _D, _I, _V]),
+    "fch_nn_to_bf16": (_I, [_I, _V, _V, _V]),
+    "fch_nn_features": (_I, [_I, _I, _I, _V, _V, _V, _V, _V, _V, _V, _V]),
+    "fch_nn_guess": (_I, [_I, _I, _I, _V, _V, _V, _V, _V, _V, _V]),
+    "fch_nn_reduce": (_I, [_I, _I, _V, _V, _V]),
     "fch_status_string": (C.c_char_p, [_I]),
 }
 

@@ -1,0 +1,142 @@
+"""GPU tests of the learned warm start kernels: each BF16-MFMA convolution
+kernel and a full training step against the FP64 oracle with bfloat16
+rounding emulated at the same points (relative L2 per tensor)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2006_04784_amd import fch
+    fch.lib()
+    return fch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, float) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def tb(a):   # exactly representable bf16 values -> torch bf16 on the GPU
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+
+
+def tf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def P(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def test_conv_kernels(F, orc):
+    L = F.lib()
+    rng = np.random.default_rng(3)
+    B, H, W = 2, 16, 32
+    x = orc.bf16(rng.normal(size=(B, H, W, 32)))
+    w = orc.bf16(rng.normal(0, 0.1, size=(9, 32, 32)))
+    bias = rng.normal(0, 0.1, size=32).astype(np.float32).astype(np.float64)
+    z = torch.zeros((B, H, W, 32), dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros_like(z)
+    assert L.fch_nn_conv_fwd(B, H, W, 32, P(tb(x)), P(tb(w)), P(tf(bias)), P(z), P(y), None,
+                             None) == 0
+    zr, yr = orc.nn_conv_fwd(x, w, bias, True)
+    assert rel(z.float().cpu().numpy(), zr) < 2e-3
+    assert rel(y.float().cpu().numpy(), yr) < 2e-3
+    # output layer
+    w16 = orc.bf16(rng.normal(0, 0.1, size=(9, 16, 32)))
+    o = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
+    assert L.fch_nn_conv_fwd(B, H, W, 16, P(tb(x)), P(tb(w16)), P(tf(bias[:16])), None, None,
+                             P(o), None) == 0
+    assert rel(o.cpu().numpy(), orc.nn_conv_fwd(x, w16, bias[:16], True)) < 1e-5
+    # backward data, both weight shapes
+    dz = orc.bf16(rng.normal(size=(B, H, W, 32)))
+    zp = orc.bf16(rng.normal(size=(B, H, W, 32)))
+    wt = torch.zeros(9 * 32 * 32, dtype=torch.bfloat16, device="cuda")
+    for ww in (w, w16):
+        dzz = dz.copy()
+        if ww.shape[1] == 16:
+            dzz[..., 16:] = 0.0
+        out = torch.zeros((B, H, W, 32), dtype=torch.bfloat16, device="cuda")
+        assert L.fch_nn_conv_bwd_data(B, H, W, ww.shape[1], P(tb(dzz)), P(tb(ww)), P(tb(zp)),
+                                      P(out), P(wt), None) == 0
+        assert rel(out.float().cpu().numpy(), orc.nn_conv_bwd_data(dzz, ww, zp, True)) < 2e-3
+    # backward weights
+    for cout in (32, 16):
+        dzz = dz.copy()
+        dzz[..., cout:] = 0.0
+        n = int(L.fch_nn_bwd_w_scratch_floats(B, H, W))
+        scr = torch.zeros(n, dtype=torch.float32, device="cuda")
+        g = torch.zeros(9 * cout * 32 + cout, dtype=torch.float32, device="cuda")
+        assert L.fch_nn_conv_bwd_w(B, H, W, cout, P(tb(dzz)), P(tb(x)), P(g), P(scr), None) == 0
+        dw, db = orc.nn_conv_bwd_w(dzz, x, cout)
+        gg = g.cpu().numpy()
+        assert rel(gg[:9 * cout * 32], dw.ravel()) < 1e-5
+        assert rel(gg[9 * cout * 32:], db) < 1e-5
+
+
+def test_training_step_matches_oracle(F, orc):
+    from paper_2006_04784_amd import nn
+    rng = np.random.default_rng(4)
+    B, H, W = 2, 16, 32
+    net = nn.WarmStartNet(H, W, B, seed=5)
+    params = net.init_params(5)
+    params[-1] = (rng.normal(0, 0.05, size=(9, 16, 32)), rng.normal(0, 0.05, size=16))
+    params[-1][0][:, 1:, :] = 0.0
+    params[-1][1][1:] = 0.0
+    net.set_params(params)
+    un = torch.from_numpy(rng.normal(size=(B, H, W))).cuda()
+    um = un + 0.01 * torch.from_numpy(rng.normal(size=(B, H, W))).cuda()
+    up = un + 0.012 * torch.from_numpy(rng.normal(size=(B, H, W))).cuda()
+    k = torch.tensor([[2e-3, 1e-3], [1e-3, 1e-3]], dtype=torch.float64).cuda()
+    net.features(un, um, k, up)
+    x = net.x.float().cpu().numpy().astype(np.float64)
+    t = net.target.cpu().numpy().astype(np.float64)
+    # features against their definition
+    d = (un - um).cpu().numpy() * (k[:, 0] / k[:, 1]).cpu().numpy()[:, None, None]
+    s = np.sqrt((d ** 2).mean(axis=(1, 2)))
+    assert np.allclose(net.scale.cpu().numpy(), s, rtol=1e-12)
+    assert np.array_equal(x[..., 0], orc.bf16(un.cpu().numpy()))
+    assert np.allclose(t, ((up - un).cpu().numpy() - d) / s[:, None, None], rtol=1e-6, atol=1e-6)
+    net.forward(B)
+    loss = float(net.backward(B).cpu()[0])
+    q = [(orc.bf16(w), b.astype(np.float32).astype(np.float64)) for w, b in params]
+    lref, gref, oref = orc.nn_loss_and_grads(x, q, t, True)
+    assert rel(net.o.cpu().numpy(), oref) < 1e-3
+    assert abs(loss - lref) < 1e-3 * lref
+    for (gw, gb), (rw, rb) in zip(net.get_grads(), gref):
+        assert rel(gw, rw) < 1e-2
+        assert rel(gb, rb) < 1e-2
+    # Adam: the first bias-corrected step from zero moments is
+    # lr * g / (|g| + eps) against the gradient
+    before = net.P.clone()
+    net.adam(lr=1e-3, eps=1e-8)
+    delta = (net.P - before).cpu().numpy().astype(np.float64)
+    g = net.G.cpu().numpy().astype(np.float64)
+    want = -1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(delta, want, rtol=1e-3, atol=5e-7)
+    assert np.all(delta[g == 0.0] == 0.0)
+
+
+def test_learned_warm_start_gain(F):
+    """Trained on PSD step pairs of the 256^2 three-bilayer workload, the
+    network's guess needs fewer PSD iterations than the extrapolated guess on
+    held-out trajectories, at the same stopping tolerance and to the same
+    solution; the untrained network (zero output layer) is the extrapolation."""
+    from paper_2006_04784_amd import learned, nn
+    plan = F.Plan(**learned.c5_model())
+    te = [learned.psd_trajectory(plan, learned.c5_initial(200), 25)]
+    net0 = nn.WarmStartNet(256, 256, 8, seed=0)
+    ev0 = learned.evaluate(plan, net0, te)
+    assert all(r[0] == r[1] for r in ev0["per_step"])
+    ev, net, _ = learned.run_experiment(range(6), [200], nsteps=40, epochs=10, batch=8)
+    print({k: v for k, v in ev.items() if k != "per_step"}, flush=True)
+    assert ev["loss_last"] < 0.3 * ev["loss_first"]
+    assert ev["iters_learned"] < ev["iters_plain"]
+    assert ev["max_rel_diff_solutions"] < 1e-8
