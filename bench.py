@@ -39,7 +39,7 @@ def spec_bytes(N):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fch_kernels.hip", "fch_device.hpp", "fch_kernels.hpp"):
+    for f in ("fch_device.hpp", "fch_kernels_impl.hpp"):
         with open(os.path.join(ROOT, "paper_2006_04784_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -253,7 +253,7 @@ def main():
         ev, _net, _plan = learned.run_experiment(range(16), [900, 901], nsteps=80, epochs=20,
                                                  batch=16, log=None, device=dev)
         ev.pop("per_step")
-        extra["learned_warm_start"] = {k: (round(v, 4) if isinstance(v, float) else v)
+        extra["learned_warm_start"] = {k: (float("%.4g" % v) if isinstance(v, float) else v)
                                        for k, v in ev.items()}
     if args.copy_probe:
         # a plain elementwise copy of known size: 256 MiB read, 256 MiB written

@@ -126,8 +126,9 @@ fch_status fch_plan_stats(fch_plan_t plan, fch_stats* out);   /* host out */
 fch_status fch_plan_reset_stats(fch_plan_t plan);
 
 /* Kernel timing.  While enabled, every row-pass and column-pass launch is
- * bracketed by HIP events on the plan's stream (up to 16384 launches; later
- * launches are not timed).  fch_plan_profile_read waits for the stream, sums
+ * bracketed by HIP events recorded on the plan's stream (up to 16384
+ * launches; later launches are not timed); an interval includes the
+ * dispatch of its kernel.  fch_plan_profile_read waits for the stream, sums
  * the elapsed times per kernel class and clears the records.  Classes:
  * 0 row pass (pointwise chemical potential), 1 column pass (forward FFT +
  * epilogue + inverse FFT), 2 column pass (one direction only),

@@ -180,7 +180,8 @@ fch_status readback(fch_plan_s* p) {
 
 constexpr int kProfCap = 16384;
 
-// bracket the next launch with events when timing is on; returns the record
+// kernel timing: an event pair recorded on the plan's stream around the
+// next launch when timing is on
 int prof_begin(fch_plan_s* p, int kind) {
   if (!p->prof_on || p->prof_n >= kProfCap) return -1;
   const int i = p->prof_n++;
@@ -195,7 +196,7 @@ void prof_end(fch_plan_s* p, int i) {
 fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
   const int kind = (epi != fch::EPI_NONE && pro != fch::PRO_NONE) ? 1 : 2;
   const int r = prof_begin(p, kind);
-  HIPCHK(p->cv->col(epi, pro, a, p->stream));
+  HIPCHK(p->cv->col(epi, pro, a, p->stream, nullptr, nullptr));
   prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
@@ -205,7 +206,7 @@ fch_status row_mu(fch_plan_s* p, double* partial) {
   RowArgs a = row_args(p);
   a.partial = partial;
   const int r = prof_begin(p, 0);
-  HIPCHK(p->rv->row(fch::ROW_MU, a, p->stream));
+  HIPCHK(p->rv->row(fch::ROW_MU, a, p->stream, nullptr, nullptr));
   prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
@@ -518,9 +519,10 @@ fch_status fch_autotune(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
     a.s1 = prev;
     a.out = prev;
     if (hipEventRecord(ev[0], p->stream) != hipSuccess ||
-        p->rv->row(fch::ROW_MU, r, p->stream) != hipSuccess ||
+        p->rv->row(fch::ROW_MU, r, p->stream, nullptr, nullptr) != hipSuccess ||
         hipEventRecord(ev[1], p->stream) != hipSuccess ||
-        p->cv->col(fch::EPI_IMEX, fch::PRO_NEXT_EXTRAP, a, p->stream) != hipSuccess ||
+        p->cv->col(fch::EPI_IMEX, fch::PRO_NEXT_EXTRAP, a, p->stream, nullptr, nullptr) !=
+            hipSuccess ||
         hipEventRecord(ev[2], p->stream) != hipSuccess ||
         hipEventSynchronize(ev[2]) != hipSuccess) {
       st = FCH_E_HIP;
@@ -584,13 +586,13 @@ fch_status fch_forward(fch_plan_t p, const double* u, fch_c128* uh) {
   r.u_in = u;
   r.X_out = p->P0;
   int pr = prof_begin(p, 3);
-  HIPCHK(p->rv->row(fch::ROW_FWD, r, p->stream));
+  HIPCHK(p->rv->row(fch::ROW_FWD, r, p->stream, nullptr, nullptr));
   prof_end(p, pr);
   ColArgs a = col_args(p);
   a.X_in = p->P0;
   a.X_out = (cd*)uh;
   pr = prof_begin(p, 3);
-  HIPCHK(p->cv->col_fwd1(a, p->stream));
+  HIPCHK(p->cv->col_fwd1(a, p->stream, nullptr, nullptr));
   prof_end(p, pr);
   p->stats.launches += 2;
   p->stats.fft_calls += 1;
@@ -604,13 +606,13 @@ fch_status fch_inverse(fch_plan_t p, const fch_c128* uh, double* u) {
   a.X_in = (const cd*)uh;
   a.X_out = p->P0;
   int pr = prof_begin(p, 3);
-  HIPCHK(p->cv->col_inv1(a, p->stream));
+  HIPCHK(p->cv->col_inv1(a, p->stream, nullptr, nullptr));
   prof_end(p, pr);
   RowArgs r = row_args(p);
   r.X_in = p->P0;
   r.u_out = u;
   pr = prof_begin(p, 3);
-  HIPCHK(p->rv->row(fch::ROW_INV, r, p->stream));
+  HIPCHK(p->rv->row(fch::ROW_INV, r, p->stream, nullptr, nullptr));
   prof_end(p, pr);
   p->stats.launches += 2;
   p->stats.fft_calls += 1;

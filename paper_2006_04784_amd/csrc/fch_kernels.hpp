@@ -99,15 +99,17 @@ enum EnsStage { ENS_PRO = 0, ENS_IMEX = 1, ENS_AM3 = 2 };
 // column-pass variants are chosen independently.
 struct RowVT {
   int N, R, E, twl, threads;
-  hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s);
+  // e0/e1 (nullable): events attached to the dispatch (kernel execution time)
+  hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   // batched row pass (chemical-potential pieces) over members [first, first+count)
   hipError_t (*row_ens)(EnsMember* m, int first, int count, hipStream_t s);
 };
 struct ColVT {
   int N, E, twl, threads;
-  hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s);
-  hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s);
-  hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s);
+  hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s, hipEvent_t e0,
+                    hipEvent_t e1);
+  hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   hipError_t (*col_ens)(int stage, EnsMember* m, int first, int count, hipStream_t s);
 };
 

@@ -1,26 +1,40 @@
 // fch_variants.hpp -- launch wrappers of the kernel templates for one grid
 // size; each fch_kern_n<N>.hip instantiates the variants of its N.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "fch_kernels_impl.hpp"
+
+// launch, optionally with start/stop events attached to the dispatch itself
+// (kernel execution time, as a profiler's kernel trace reports it)
+#define FCH_LAUNCH(K, GRID, BLOCK, S, E0, E1, ...)                                   \
+  do {                                                                                \
+    if (E0)                                                                           \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__);            \
+    else                                                                              \
+      hipLaunchKernelGGL(K, GRID, BLOCK, 0, S, __VA_ARGS__);                          \
+  } while (0)
 
 namespace fch {
 
 template <int N, int R, int E, int TWL>
 struct RowImpl {
   static constexpr int NT = R * (N / E);
-  static hipError_t row(int mode, const RowArgs& a, hipStream_t s) {
+  static hipError_t row(int mode, const RowArgs& a, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
     const int* done = (mode == ROW_MU) ? &a.ctl->done : nullptr;
+    const int* nodone = nullptr;
     switch (mode) {
       case ROW_MU:
-        hipLaunchKernelGGL((k_row<N, R, E, ROW_MU, TWL>), dim3(N / R), dim3(NT), 0, s, a, done);
+        FCH_LAUNCH((k_row<N, R, E, ROW_MU, TWL>), dim3(N / R), dim3(NT), s, e0, e1, a, done);
         break;
       case ROW_FWD:
-        hipLaunchKernelGGL((k_row<N, R, E, ROW_FWD, TWL>), dim3(N / (2 * R)), dim3(NT), 0, s, a,
-                           nullptr);
+        FCH_LAUNCH((k_row<N, R, E, ROW_FWD, TWL>), dim3(N / (2 * R)), dim3(NT), s, e0, e1, a,
+                   nodone);
         break;
       case ROW_INV:
-        hipLaunchKernelGGL((k_row<N, R, E, ROW_INV, TWL>), dim3(N / (2 * R)), dim3(NT), 0, s, a,
-                           nullptr);
+        FCH_LAUNCH((k_row<N, R, E, ROW_INV, TWL>), dim3(N / (2 * R)), dim3(NT), s, e0, e1, a,
+                   nodone);
         break;
       default:
         return hipErrorInvalidValue;
@@ -43,14 +57,16 @@ struct ColImpl {
   static constexpr int H = N / 2 + 1;
 
   template <int EPI, int PRO>
-  static hipError_t lc(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col<N, E, EPI, PRO, TWL>), dim3(H), dim3(CT), 0, s, a, &a.ctl->done);
+  static hipError_t lc(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int* done = &a.ctl->done;
+    FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL>), dim3(H), dim3(CT), s, e0, e1, a, done);
     return hipGetLastError();
   }
 
-  static hipError_t col(int epi, int pro, const ColArgs& a, hipStream_t s) {
+  static hipError_t col(int epi, int pro, const ColArgs& a, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
 #define FCH_COL(E_, P_) \
-  if (epi == E_ && pro == P_) return lc<E_, P_>(a, s);
+  if (epi == E_ && pro == P_) return lc<E_, P_>(a, s, e0, e1);
     FCH_COL(EPI_NONE, PRO_FIELD)
     FCH_COL(EPI_NONE, PRO_EXTRAP)
     FCH_COL(EPI_NONE, PRO_PSD_INIT)
@@ -65,12 +81,12 @@ struct ColImpl {
 #undef FCH_COL
     return hipErrorInvalidValue;
   }
-  static hipError_t col_fwd1(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col1<N, E, -1, TWL>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+  static hipError_t col_fwd1(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    FCH_LAUNCH((k_col1<N, E, -1, TWL>), dim3((H + 1) / 2), dim3(CT), s, e0, e1, a);
     return hipGetLastError();
   }
-  static hipError_t col_inv1(const ColArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_col1<N, E, +1, TWL>), dim3((H + 1) / 2), dim3(CT), 0, s, a);
+  static hipError_t col_inv1(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    FCH_LAUNCH((k_col1<N, E, +1, TWL>), dim3((H + 1) / 2), dim3(CT), s, e0, e1, a);
     return hipGetLastError();
   }
   static hipError_t col_ens(int stage, EnsMember* m, int first, int count, hipStream_t s) {
