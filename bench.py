@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip SAV/PSD/adaptive/FFT extras")
     ap.add_argument("--config", type=str, default="",
                     help="row_R,row_E,row_twl,col_E,col_twl launch config instead of autotuning")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="steps per HIP-graph replay of the fused IMEX chain (0: launch each kernel)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB copy (counter calibration)")
     args = ap.parse_args()
@@ -105,7 +107,8 @@ def main():
         log("autotune launch variants")
         tuned_cfg, tuned_us = plan.autotune(a, b, k=k, reps=20)
         log("chosen %s (row %.2f us, column %.2f us)" % (tuned_cfg, tuned_us[0], tuned_us[1]))
-    log("warmup %d steps" % args.warmup)
+    plan.set_graph(args.graph)
+    log("warmup %d steps (graph replay of %d steps)" % (args.warmup, args.graph))
     plan.run(a, b, scheme="imex", nsteps=args.warmup, k=k, k_prev=k, startup=False)
     torch.cuda.synchronize()
 
@@ -304,7 +307,7 @@ def main():
                    "N": N, "scheme": "imex", "k": k,
                    "launch_config": dict(zip(("row_R", "row_E", "row_twl", "col_E", "col_twl"),
                                              plan.get_config())),
-                   "autotuned": not args.config},
+                   "autotuned": not args.config, "graph_steps": args.graph},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -136,6 +136,17 @@ fch_status fch_plan_reset_stats(fch_plan_t plan);
 typedef struct { int64_t count[4]; double ms[4]; } fch_profile;
 fch_status fch_plan_profile(fch_plan_t plan, int32_t enable);
 fch_status fch_plan_profile_read(fch_plan_t plan, fch_profile* out);
+/* Replay of the fixed-step fused BDF2-IMEX chain of fch_run (Sec. 3.4) as a
+ * HIP graph of `steps` steps (even, 2..256; 0 disables, the default).  The
+ * graph runs on an internal stream ordered after the plan's stream, and the
+ * plan's stream is ordered after it, so callers see the same stream
+ * semantics.  Enabling creates that stream and two events; fch_run
+ * instantiates one graph per (uh_n, uh_nm1) buffer pair, workspace and launch
+ * configuration on first use (the HIP runtime's graph objects are the only
+ * allocations).  Results are bit-identical to the unreplayed path: the same
+ * kernels run in the same order.  Ignored while kernel timing is on.
+ * FCH_E_INVALID for an odd or out-of-range count. */
+fch_status fch_plan_set_graph(fch_plan_t plan, int32_t steps);
 
 /* ---- transforms (pseudo-spectral discretization, Sec. 2.3 / Sec. 3) ------ */
 /* uh = DFT(u), unnormalized.  u: N*N doubles; uh: (N/2+1)*N complex. */

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <utility>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -400,8 +401,39 @@ fch_status fch_plan_profile_read(fch_plan_t p, fch_profile* out) {
   return FCH_OK;
 }
 
+namespace {
+void drop_chain(fch_plan_s* p) {
+  if (p->chain_exec) (void)hipGraphExecDestroy(p->chain_exec);
+  p->chain_exec = nullptr;
+  std::memset(p->chain_key, 0, sizeof(p->chain_key));
+}
+}  // namespace
+
+fch_status fch_plan_set_graph(fch_plan_t p, int32_t steps) {
+  if (!p || steps < 0 || steps > 256 || (steps & 1)) return FCH_E_INVALID;
+  if (steps > 0 && !p->gstream) {
+    if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess) {
+      p->gstream = nullptr;
+      return FCH_E_HIP;
+    }
+    if (hipEventCreateWithFlags(&p->gfork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->gjoin, hipEventDisableTiming) != hipSuccess)
+      return FCH_E_HIP;
+  }
+  if (steps != p->graph_steps) drop_chain(p);
+  p->graph_steps = steps;
+  return FCH_OK;
+}
+
 fch_status fch_plan_destroy(fch_plan_t p) {
   if (!p) return FCH_E_INVALID;
+  drop_chain(p);
+  if (p->gstream) {
+    (void)hipStreamSynchronize(p->gstream);
+    (void)hipStreamDestroy(p->gstream);
+  }
+  if (p->gfork) (void)hipEventDestroy(p->gfork);
+  if (p->gjoin) (void)hipEventDestroy(p->gjoin);
   if (p->prof_ev) {
     for (int i = 0; i < 2 * kProfCap; ++i) (void)hipEventDestroy(p->prof_ev[i]);
     delete[] p->prof_ev;
@@ -866,6 +898,59 @@ static fch_status sav_or_psd_step(fch_plan_t p, const fch_run_opts* o, const cd*
   return s;
 }
 
+namespace {
+// Launches graph_steps fused IMEX steps (row pass, then column pass with the
+// next step's prologue) from (cur, prev); graph_steps is even, so the buffer
+// roles are the same afterwards.  The graph is captured on the internal
+// stream on first use for this buffer pair, workspace and launch variants.
+fch_status chain_replay(fch_plan_s* p, cd* cur, cd* prev) {
+  const void* key[6] = {cur, prev, p->P0, p->rv, p->cv, (const void*)(intptr_t)p->graph_steps};
+  if (p->chain_exec && std::memcmp(key, p->chain_key, sizeof(key)) != 0) drop_chain(p);
+  if (!p->chain_exec) {
+    hipStream_t user = p->stream;
+    p->stream = p->gstream;
+    if (hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      p->stream = user;
+      return FCH_E_HIP;
+    }
+    const fch_stats saved = p->stats;
+    fch_status st = FCH_OK;
+    cd *c = cur, *pv = prev;
+    ColArgs a = col_args(p);
+    for (int i = 0; i < p->graph_steps && st == FCH_OK; ++i) {
+      st = row_mu(p, nullptr);
+      if (st != FCH_OK) break;
+      a.s0 = c;
+      a.s1 = pv;
+      a.out = pv;
+      st = col(p, fch::EPI_IMEX, fch::PRO_NEXT_EXTRAP, a);
+      std::swap(c, pv);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->gstream, &g);
+    p->stream = user;
+    p->stats = saved;
+    if (st == FCH_OK && (ec != hipSuccess || !g)) st = FCH_E_HIP;
+    if (st == FCH_OK && hipGraphInstantiate(&p->chain_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      p->chain_exec = nullptr;
+      st = FCH_E_HIP;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (st != FCH_OK) return st;
+    std::memcpy(p->chain_key, key, sizeof(key));
+  }
+  HIPCHK(hipEventRecord(p->gfork, p->stream));
+  HIPCHK(hipStreamWaitEvent(p->gstream, p->gfork, 0));
+  HIPCHK(hipGraphLaunch(p->chain_exec, p->gstream));
+  HIPCHK(hipEventRecord(p->gjoin, p->gstream));
+  HIPCHK(hipStreamWaitEvent(p->stream, p->gjoin, 0));
+  p->stats.launches += 2 * p->graph_steps;
+  p->stats.fft_calls += 4 * p->graph_steps;
+  p->stats.steps += p->graph_steps;
+  return FCH_OK;
+}
+}  // namespace
+
 fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128* uh_nm1,
                    double* rs, fch_run_info* info) {
   if (!p || !o || !uh_n || !uh_nm1 || uh_n == uh_nm1) return FCH_E_INVALID;
@@ -922,6 +1007,12 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
         a.s1 = prev;
         CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
         while (done < o->nsteps) {
+          // the last step (no next prologue) always runs outside the graph
+          if (p->graph_steps > 0 && !p->prof_on && o->nsteps - done > p->graph_steps) {
+            CHK(chain_replay(p, cur, prev));
+            done += p->graph_steps;
+            continue;
+          }
           CHK(row_mu(p, nullptr));
           const bool last = (done + 1 == o->nsteps);
           a.s0 = cur;

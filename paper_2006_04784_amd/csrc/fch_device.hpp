@@ -143,13 +143,49 @@ struct Sched {
   }
 };
 
+// Exchange point between Stockham passes.  When one wavefront owns the
+// whole sequence (WAVE), its own LDS writes are ordered before its reads by
+// the LDS pipeline; only compiler reordering has to be prevented.
+template <bool WAVE>
+__device__ __forceinline__ void pass_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Twiddles of pass P held by thread t: w[b (R-1) + r - 1] is
+// w^{(j mod Ns) r L/(Ns R)} for butterfly j = t + b T.  Issued one pass ahead
+// so that their latency overlaps the current pass and its exchange.
+template <int L, int E, int P>
+__device__ __forceinline__ void load_tw(cd (&w)[E], const cd* tw, int t) {
+  using S = Sched<L, E>;
+  if constexpr (P < S::NPASS) {
+    constexpr int R = S::radix(P);
+    constexpr int Ns = S::span(P);
+    constexpr int B = E / R;
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int jm = (t + b * S::T) & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b * (R - 1) + r - 1] = tw[jm * r * (L / (Ns * R))];
+      }
+    }
+  }
+}
+
 // One Stockham autosort pass (radix R, span Ns) over NSEQ independent
 // length-L sequences held by the same T threads.  Butterfly j reads
 // positions j + r L/R, twiddles by w^{(j mod Ns) r L/(Ns R)} and writes
-// (j div Ns) Ns R + (j mod Ns) + r Ns.  tw holds exp(-2 pi i m / L).
-template <int L, int E, int NSEQ, int DIR, int P>
+// (j div Ns) Ns R + (j mod Ns) + r Ns.  tw holds exp(-2 pi i m / L); w holds
+// this pass's twiddles (load_tw).
+template <int L, int E, int NSEQ, int DIR, int P, bool WAVE = false>
 __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ], const cd* tw,
-                                         int t) {
+                                         const cd (&w)[E], int t) {
   using S = Sched<L, E>;
   constexpr int R = S::radix(P);
   constexpr int Ns = S::span(P);
@@ -157,6 +193,8 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
   constexpr int T = S::T;
   constexpr bool FIRST = (P == 0);
   constexpr bool LAST = (P == S::NPASS - 1);
+  cd wn[E];
+  load_tw<L, E, P + 1>(wn, tw, t);
   if constexpr (!FIRST) {
 #pragma unroll
     for (int q = 0; q < NSEQ; ++q)
@@ -168,13 +206,12 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
   if constexpr (Ns > 1) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      const int jm = (t + b * T) & (Ns - 1);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cd w = tw[jm * r * (L / (Ns * R))];
-        if (DIR > 0) w.y = -w.y;
+        cd wr = w[b * (R - 1) + r - 1];
+        if (DIR > 0) wr.y = -wr.y;
 #pragma unroll
-        for (int q = 0; q < NSEQ; ++q) v[q][b * R + r] = cmul(v[q][b * R + r], w);
+        for (int q = 0; q < NSEQ; ++q) v[q][b * R + r] = cmul(v[q][b * R + r], wr);
       }
     }
   }
@@ -183,7 +220,7 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
 #pragma unroll
     for (int b = 0; b < B; ++b) dft<R, DIR>(&v[q][b * R]);
   if constexpr (!LAST) {
-    __syncthreads();
+    pass_sync<WAVE>();
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + b * T;
@@ -193,8 +230,8 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[q][lp(base + r * Ns)] = v[q][b * R + r];
     }
-    __syncthreads();
-    fft_pass<L, E, NSEQ, DIR, P + 1>(v, lds, tw, t);
+    pass_sync<WAVE>();
+    fft_pass<L, E, NSEQ, DIR, P + 1, WAVE>(v, lds, tw, wn, t);
   }
 }
 
@@ -202,9 +239,13 @@ __device__ __forceinline__ void fft_pass(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ
 // t + s*T of sequence q.  lds[q] is an LDS scratch of lp_size(L) elements per
 // sequence, indexed through lp().
 // Unnormalized in both directions.
-template <int L, int E, int NSEQ, int DIR>
+// WAVE: the T = L/E threads of each sequence form one wavefront (T == 64),
+// so the exchanges need no workgroup barrier.
+template <int L, int E, int NSEQ, int DIR, bool WAVE = false>
 __device__ __forceinline__ void fft(cd (&v)[NSEQ][E], cd* const (&lds)[NSEQ], const cd* tw, int t) {
-  fft_pass<L, E, NSEQ, DIR, 0>(v, lds, tw, t);
+  static_assert(!WAVE || L / E == 64, "a wave-local FFT needs 64 threads per sequence");
+  cd w0[E];  // the first pass (span 1) has no twiddles
+  fft_pass<L, E, NSEQ, DIR, 0, WAVE>(v, lds, tw, w0, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,11 +266,12 @@ struct Consts {
   double pars;    // L^2 / N^4: h^2 sum_x f g = pars * sum_half w Re(f g*)
 };
 
-__device__ __forceinline__ void well(const Consts& c, double u, double& W, double& W1,
-                                     double& W2) {
+template <bool Q>
+__device__ __forceinline__ void well_t(const Consts& c, double u, double& W, double& W1,
+                                       double& W2) {
   const double dm = u - c.bm, dp = u - c.bp;
   double A = 0.5 * dm * dm, A1 = dm, A2 = 1.0;
-  if (c.q != 0.0) {
+  if constexpr (Q) {
     const double z = dm * c.inv_eps;
     const double e = exp(-fabs(z));
     const double den = 1.0 / (1.0 + e * e);
@@ -244,6 +286,16 @@ __device__ __forceinline__ void well(const Consts& c, double u, double& W, doubl
   W = A * B;
   W1 = A1 * B + A * B1;
   W2 = A2 * B + 2.0 * A1 * B1 + A;
+}
+
+// Q = (q != 0) is uniform; callers that evaluate many points hoist the test
+// out of their loop (well_t) so that the points' chains interleave.
+__device__ __forceinline__ void well(const Consts& c, double u, double& W, double& W1,
+                                     double& W2) {
+  if (c.q != 0.0)
+    well_t<true>(c, u, W, W1, W2);
+  else
+    well_t<false>(c, u, W, W1, W2);
 }
 
 // Workgroup index remap so that consecutive logical tiles land on the same

@@ -19,6 +19,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fch_kernels.hpp"
 
 namespace fch {
@@ -30,24 +32,32 @@ __device__ __forceinline__ double wavek2(const Consts& c, int kx, int ky) {
   return c.kscale * (double)(kx * kx + kyi * kyi);
 }
 
-// deterministic tree reduction of K values over NT threads; thread 0 writes
+// deterministic reduction of K values over NT threads (a fixed butterfly
+// inside each wavefront, then the wavefront sums in order); thread 0 writes
 template <int NT, int K>
 __device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, double* out) {
+  constexpr int NW = (NT + 63) / 64;
   const int tid = threadIdx.x;
+  double w[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) red[k * NT + tid] = v[k];
-  __syncthreads();
+  for (int k = 0; k < K; ++k) {
+    w[k] = v[k];
 #pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) red[k * NT + tid] += red[k * NT + tid + s];
-    }
-    __syncthreads();
+    for (int off = (NT < 64 ? NT : 64) / 2; off >= 1; off >>= 1) w[k] += __shfl_xor(w[k], off, 64);
   }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * NW + (tid >> 6)] = w[k];
+  }
+  __syncthreads();
   if (tid == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = red[k * NT];
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) s += red[k * NW + i];
+      out[k] = s;
+    }
   }
 }
 
@@ -68,7 +78,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   constexpr int ZS = ZS0 + (((8 / R) - ZS0 % 8) % 8 + 8) % 8;
   __shared__ cd Zs[R * ZS];
   __shared__ cd twl[TWL ? N : 1];
-  __shared__ double red[2 * NT];
+  __shared__ double red[2 * ((NT + 63) / 64)];
   if (done && *done) return;
 
   const int tid = threadIdx.x;
@@ -83,6 +93,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   if constexpr (TWL) {
     for (int i = tid; i < N; i += NT) twl[i] = a.tw[i];
     tw = twl;
+    __syncthreads();  // the FFT exchanges below may be wave-local
   }
 
   cd v[1][E];
@@ -126,7 +137,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < E; ++s) v[0][s] = Zs[seq * ZS + lp(t + s * T)];
-    fft<N, E, 1, +1>(v, base, tw, t);
+    fft<N, E, 1, +1, (T == 64)>(v, base, tw, t);
   }
 
   if constexpr (MODE == ROW_INV) {
@@ -144,19 +155,28 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   if constexpr (MODE == ROW_MU) {
     const Consts& c = a.c;
     bool bad = false;
+    // the q test is hoisted out of the point loop: one branch-free body per
+    // case, so the E points' well evaluations interleave
+    auto points = [&](auto qc) {
+      constexpr bool Q = decltype(qc)::value;
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const double u = v[0][s].x * c.invN2;
-      const double lap = v[0][s].y * c.invN2;
-      double W, W1, W2;
-      well(c, u, W, W1, W2);
-      const double om = c.eps2 * lap - W1;
-      const double p = -W2 * om - c.eta2 * W1;
-      acc[0] += -c.eps2 * lap * (W1 + c.zeta * u) + 0.5 * W1 * W1 - c.eta2 * W;  // G (eq. e:G-def)
-      acc[1] += 0.5 * om * om - c.eta2 * W;                                       // energy density
-      bad |= !(isfinite(u) && isfinite(lap));
-      v[0][s] = cd{om, p};
-    }
+      for (int s = 0; s < E; ++s) {
+        const double u = v[0][s].x * c.invN2;
+        const double lap = v[0][s].y * c.invN2;
+        double W, W1, W2;
+        well_t<Q>(c, u, W, W1, W2);
+        const double om = c.eps2 * lap - W1;
+        const double p = -W2 * om - c.eta2 * W1;
+        acc[0] += -c.eps2 * lap * (W1 + c.zeta * u) + 0.5 * W1 * W1 - c.eta2 * W;  // G (eq. e:G-def)
+        acc[1] += 0.5 * om * om - c.eta2 * W;                                       // energy density
+        bad |= !(isfinite(u) && isfinite(lap));
+        v[0][s] = cd{om, p};
+      }
+    };
+    if (c.q != 0.0)
+      points(std::integral_constant<bool, true>{});
+    else
+      points(std::integral_constant<bool, false>{});
     if (bad) a.ctl->nonfinite = 1;
   } else {  // ROW_FWD: two physical rows as one complex sequence
     const double* ua = a.u_in + (size_t)(y0 + seq) * N;
@@ -165,8 +185,8 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
     for (int s = 0; s < E; ++s) v[0][s] = cd{ua[t + s * T], ub[t + s * T]};
   }
 
-  fft<N, E, 1, -1>(v, base, tw, t);
-  __syncthreads();
+  fft<N, E, 1, -1, (T == 64)>(v, base, tw, t);
+  pass_sync<(T == 64)>();
 #pragma unroll
   for (int s = 0; s < E; ++s) Zs[seq * ZS + lp(t + s * T)] = v[0][s];
   __syncthreads();
@@ -233,7 +253,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
   constexpr int M = N / 2;
   __shared__ cd buf[2][lp_size(N)];
   __shared__ cd twl[TWL ? N : 1];
-  __shared__ double red[2 * T];
+  __shared__ double red[2 * ((T + 63) / 64)];
   if (done && *done) return;
 
   const Consts& c = a.c;
@@ -256,14 +276,19 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
   const StepCtl* ctl = a.ctl;
 
   if constexpr (EPI != EPI_NONE) {
-    // state values of this column are loaded before the FFT so that their
-    // latency overlaps it
+    // the FFT inputs are requested first; the state values of this column
+    // are requested after them, before the FFT, so that they arrive while it
+    // runs (vector loads complete in issue order)
     cd pre0[E], pre1[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       const size_t g = col + t + s * T;
       v[0][s] = a.P0[g];
       v[1][s] = a.P1[g];
+    }
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const size_t g = col + t + s * T;
       if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
         pre0[s] = a.s0[g];
         pre1[s] = a.s1[g];

@@ -27,6 +27,12 @@ struct fch_plan_s {
   int prof_n;
   hipEvent_t* prof_ev;    // 2 per record
   int* prof_kind;
+  // HIP-graph replay of the fixed-step fused IMEX chain (fch_plan_set_graph)
+  int graph_steps;
+  hipStream_t gstream;
+  hipEvent_t gfork, gjoin;
+  hipGraphExec_t chain_exec;
+  const void* chain_key[6];
 };
 
 

@@ -117,6 +117,7 @@ _SIGS = {
     "fch_plan_stats": (_I, [_V, C.POINTER(fch_stats)]),
     "fch_plan_reset_stats": (_I, [_V]),
     "fch_plan_profile": (_I, [_V, _I]),
+    "fch_plan_set_graph": (_I, [_V, _I]),
     "fch_plan_profile_read": (_I, [_V, C.POINTER(fch_profile)]),
     "fch_forward": (_I, [_V, _V, _V]),
     "fch_inverse": (_I, [_V, _V, _V]),
@@ -301,6 +302,11 @@ class Plan:
 
     def reset_stats(self):
         _check(lib().fch_plan_reset_stats(self.h))
+
+    def set_graph(self, steps):
+        """HIP-graph replay of the fixed-step fused IMEX chain, `steps` steps
+        per replay (even; 0 disables)."""
+        _check(lib().fch_plan_set_graph(self.h, int(steps)))
 
     def profile(self, enable=True):
         _check(lib().fch_plan_profile(self.h, int(enable)))

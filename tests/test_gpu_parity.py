@@ -139,6 +139,53 @@ def test_imex_full_size_fused_chain(F, orc):
     assert rel(host(a), ref) < 1e-10
 
 
+def test_graph_replay_is_bit_identical(F, orc):
+    """fch_plan_set_graph: the replayed fused chain equals the launched one
+    bit for bit, including a remainder shorter than one replay and a second
+    buffer pair (a new graph), and stays on the oracle."""
+    log("imex graph replay c1")
+    plan, m, uh0 = _c1(orc, F)
+    with pytest.raises(RuntimeError):
+        plan.set_graph(3)
+    ref = orc.run_fixed(m, "imex", uh0, 1e-3, 37)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.run(a, b, scheme="imex", nsteps=37, k=1e-3)
+    plan.set_graph(8)
+    for rep in range(2):
+        c, d = dev(uh0), torch.zeros_like(dev(uh0))
+        info = plan.run(c, d, scheme="imex", nsteps=37, k=1e-3)
+        assert info["accepted"] == 37
+        assert torch.equal(c, a) and torch.equal(d, b), rep
+    assert rel(host(c), ref) < 1e-8
+    # continuing without startup on the same pair reuses the graph
+    plan.run(a, b, scheme="imex", nsteps=20, k=1e-3, k_prev=1e-3, startup=False)
+    plan.set_graph(0)
+    plan.run(c, d, scheme="imex", nsteps=20, k=1e-3, k_prev=1e-3, startup=False)
+    assert torch.equal(c, a) and torch.equal(d, b)
+
+
+def test_graph_replay_full_size(F, orc):
+    """1024^2 with graph replay as the benchmark runs it: equal to the
+    launched chain bit for bit and to the oracle after 4 steps."""
+    log("imex 1024^2 graph replay")
+    kw, u0 = inputs.workload("m1")
+    kw = dict(kw, zeta=1.1, D0=kw["L"] ** 2 * 1.05)
+    plan, m = pair(F, orc, **kw)
+    uh0 = orc.r2c(u0)
+    ref = orc.run_fixed(m, "imex", uh0, 1e-3, 4)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.set_graph(2)
+    plan.run(a, b, scheme="imex", nsteps=4, k=1e-3)
+    assert rel(host(a), ref) < 1e-10
+    plan.set_graph(16)
+    plan.run(a, b, scheme="imex", nsteps=40, k=1e-3, k_prev=1e-3, startup=False)
+    plan.set_graph(0)
+    c, d = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.run(c, d, scheme="imex", nsteps=4, k=1e-3)
+    plan.run(c, d, scheme="imex", nsteps=40, k=1e-3, k_prev=1e-3, startup=False)
+    assert torch.equal(c, a) and torch.equal(d, b)
+
+
 # ---- SAV --------------------------------------------------------------------
 def test_sav_step_and_r(F, orc):
     log("sav step c1")
