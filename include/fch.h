@@ -153,6 +153,20 @@ fch_status fch_plan_set_graph(fch_plan_t plan, int32_t steps);
 fch_status fch_forward(fch_plan_t plan, const double* u, fch_c128* uh);
 /* u = real part of IDFT(Hermitian extension of uh) / N^2. */
 fch_status fch_inverse(fch_plan_t plan, const fch_c128* uh, double* u);
+/* The same transforms over `batch` fields (1..65535) stored back to back:
+ * u holds batch*N*N doubles, uh batch*(N/2+1)*N complex values, field b at
+ * offset b*N*N and b*(N/2+1)*N.  Field b of the result equals fch_forward /
+ * fch_inverse of field b bit for bit.  fch_forward_batch needs no workspace:
+ * the row pass writes uh and the column pass transforms it in place.
+ * fch_inverse_batch leaves uh unchanged and stages the column-inverted
+ * spectra in ws, caller-owned device memory of at least
+ * fch_inverse_batch_ws_bytes(plan, batch) = batch*16*N*(N/2+1) bytes
+ * (FCH_E_INVALID if smaller).  Neither needs fch_plan_set_workspace.
+ * u and uh must not overlap, nor ws either of them. */
+fch_status fch_forward_batch(fch_plan_t plan, int32_t batch, const double* u, fch_c128* uh);
+size_t     fch_inverse_batch_ws_bytes(fch_plan_t plan, int32_t batch);
+fch_status fch_inverse_batch(fch_plan_t plan, int32_t batch, const fch_c128* uh, double* u,
+                             void* ws, size_t ws_bytes);
 
 /* ---- chemical potential (eq. FCH) ---------------------------------------- */
 /* muh = half spectrum of mu(u) = (eps^2 Lap - W''(u)) omega + eps^2 eta1 Lap u

@@ -651,6 +651,45 @@ fch_status fch_inverse(fch_plan_t p, const fch_c128* uh, double* u) {
   return FCH_OK;
 }
 
+fch_status fch_forward_batch(fch_plan_t p, int32_t batch, const double* u, fch_c128* uh) {
+  if (!p || !u || !uh || batch < 1 || batch > 65535) return FCH_E_INVALID;
+  const size_t ps = (size_t)p->N * p->N, ss = (size_t)p->N * p->H;
+  RowArgs r = row_args(p);
+  r.u_in = u;
+  r.X_out = (cd*)uh;
+  HIPCHK(p->rv->row_batch(fch::ROW_FWD, r, batch, ps, ss, p->stream));
+  ColArgs a = col_args(p);
+  a.X_in = (const cd*)uh;
+  a.X_out = (cd*)uh;
+  HIPCHK(p->cv->col1_batch(-1, a, batch, ss, p->stream));
+  p->stats.launches += 2;
+  p->stats.fft_calls += batch;
+  return FCH_OK;
+}
+
+size_t fch_inverse_batch_ws_bytes(fch_plan_t p, int32_t batch) {
+  if (!p || batch < 1) return 0;
+  return (size_t)batch * p->H * p->N * sizeof(cd);
+}
+
+fch_status fch_inverse_batch(fch_plan_t p, int32_t batch, const fch_c128* uh, double* u,
+                             void* ws, size_t ws_bytes) {
+  if (!p || !u || !uh || !ws || batch < 1 || batch > 65535) return FCH_E_INVALID;
+  if (ws_bytes < fch_inverse_batch_ws_bytes(p, batch)) return FCH_E_INVALID;
+  const size_t ps = (size_t)p->N * p->N, ss = (size_t)p->N * p->H;
+  ColArgs a = col_args(p);
+  a.X_in = (const cd*)uh;
+  a.X_out = (cd*)ws;
+  HIPCHK(p->cv->col1_batch(+1, a, batch, ss, p->stream));
+  RowArgs r = row_args(p);
+  r.X_in = (const cd*)ws;
+  r.u_out = u;
+  HIPCHK(p->rv->row_batch(fch::ROW_INV, r, batch, ps, ss, p->stream));
+  p->stats.launches += 2;
+  p->stats.fft_calls += batch;
+  return FCH_OK;
+}
+
 // ---- chemical potential ---------------------------------------------------
 fch_status fch_chem_potential(fch_plan_t p, const fch_c128* uh, fch_c128* muh, double* energy) {
   if (!p || !uh || !muh || (const void*)uh == (const void*)muh) return FCH_E_INVALID;

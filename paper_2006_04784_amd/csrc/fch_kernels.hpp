@@ -103,6 +103,9 @@ struct RowVT {
   hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   // batched row pass (chemical-potential pieces) over members [first, first+count)
   hipError_t (*row_ens)(EnsMember* m, int first, int count, hipStream_t s);
+  // ROW_FWD / ROW_INV over `batch` fields stored back to back
+  hipError_t (*row_batch)(int mode, const RowArgs& a, int batch, size_t pstride, size_t sstride,
+                          hipStream_t s);
 };
 struct ColVT {
   int N, E, twl, threads;
@@ -111,6 +114,8 @@ struct ColVT {
   hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   hipError_t (*col_ens)(int stage, EnsMember* m, int first, int count, hipStream_t s);
+  // single-field column transforms (dir -1 forward, +1 inverse) over `batch` fields
+  hipError_t (*col1_batch)(int dir, const ColArgs& a, int batch, size_t sstride, hipStream_t s);
 };
 
 // registry: the first entry of each list is the default for N

@@ -520,7 +520,7 @@ __global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
 // single-field column transforms (boundary fch_forward / fch_inverse):
 // two columns per workgroup, one sequence each
 template <int N, int E, int DIR, int TWL>
-__global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
+__device__ __forceinline__ void col1_body(const ColArgs& a) {
   constexpr int T = N / E;
   constexpr int H = N / 2 + 1;
   __shared__ cd buf[2][lp_size(N)];
@@ -552,6 +552,35 @@ __global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
       for (int s = 0; s < E; ++s) a.X_out[(size_t)kx * N + t + s * T] = v[q][s];
     }
   }
+}
+
+template <int N, int E, int DIR, int TWL>
+__global__ __launch_bounds__(N / E) void k_col1(ColArgs a) {
+  col1_body<N, E, DIR, TWL>(a);
+}
+
+// ---- batched single-field transforms (field = blockIdx.y) --------------------
+// Fields are stored back to back: physical fields pstride doubles apart, half
+// spectra sstride complex values apart.  Each field runs the single-field body.
+template <int N, int R, int E, int MODE, int TWL>
+__global__ __launch_bounds__(R*(N / E)) void k_row_b(RowArgs a, size_t pstride, size_t sstride) {
+  const size_t b = blockIdx.y;
+  if constexpr (MODE == ROW_FWD) {
+    a.u_in += b * pstride;
+    a.X_out += b * sstride;
+  } else {
+    a.X_in += b * sstride;
+    a.u_out += b * pstride;
+  }
+  row_body<N, R, E, MODE, TWL>(a, nullptr);
+}
+
+template <int N, int E, int DIR, int TWL>
+__global__ __launch_bounds__(N / E) void k_col1_b(ColArgs a, size_t sstride) {
+  const size_t b = blockIdx.y;
+  a.X_in += b * sstride;
+  a.X_out += b * sstride;
+  col1_body<N, E, DIR, TWL>(a);
 }
 
 }  // namespace fch

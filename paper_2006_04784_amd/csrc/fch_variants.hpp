@@ -45,8 +45,21 @@ struct RowImpl {
     hipLaunchKernelGGL((k_row_ens<N, R, E, TWL>), dim3(N / R, count), dim3(NT), 0, s, m, first);
     return hipGetLastError();
   }
+  static hipError_t row_batch(int mode, const RowArgs& a, int batch, size_t pstride,
+                              size_t sstride, hipStream_t s) {
+    const dim3 grid(N / (2 * R), batch);
+    if (mode == ROW_FWD)
+      hipLaunchKernelGGL((k_row_b<N, R, E, ROW_FWD, TWL>), grid, dim3(NT), 0, s, a, pstride,
+                         sstride);
+    else if (mode == ROW_INV)
+      hipLaunchKernelGGL((k_row_b<N, R, E, ROW_INV, TWL>), grid, dim3(NT), 0, s, a, pstride,
+                         sstride);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   static const RowVT* table() {
-    static const RowVT vt = {N, R, E, TWL, NT, &row, &row_ens};
+    static const RowVT vt = {N, R, E, TWL, NT, &row, &row_ens, &row_batch};
     return &vt;
   }
 };
@@ -106,8 +119,17 @@ struct ColImpl {
     }
     return hipGetLastError();
   }
+  static hipError_t col1_batch(int dir, const ColArgs& a, int batch, size_t sstride,
+                               hipStream_t s) {
+    const dim3 grid((H + 1) / 2, batch);
+    if (dir < 0)
+      hipLaunchKernelGGL((k_col1_b<N, E, -1, TWL>), grid, dim3(CT), 0, s, a, sstride);
+    else
+      hipLaunchKernelGGL((k_col1_b<N, E, +1, TWL>), grid, dim3(CT), 0, s, a, sstride);
+    return hipGetLastError();
+  }
   static const ColVT* table() {
-    static const ColVT vt = {N, E, TWL, CT, &col, &col_fwd1, &col_inv1, &col_ens};
+    static const ColVT vt = {N, E, TWL, CT, &col, &col_fwd1, &col_inv1, &col_ens, &col1_batch};
     return &vt;
   }
 };

@@ -117,6 +117,9 @@ _SIGS = {
     "fch_plan_stats": (_I, [_V, C.POINTER(fch_stats)]),
     "fch_plan_reset_stats": (_I, [_V]),
     "fch_plan_profile": (_I, [_V, _I]),
+    "fch_forward_batch": (_I, [_V, _I, _V, _V]),
+    "fch_inverse_batch_ws_bytes": (C.c_size_t, [_V, _I]),
+    "fch_inverse_batch": (_I, [_V, _I, _V, _V, _V, C.c_size_t]),
     "fch_plan_set_graph": (_I, [_V, _I]),
     "fch_plan_profile_read": (_I, [_V, C.POINTER(fch_profile)]),
     "fch_forward": (_I, [_V, _V, _V]),
@@ -333,6 +336,44 @@ class Plan:
         out = self.phys() if out is None else out
         self._sync_stream()
         _check(lib().fch_inverse(self.h, _p(uh), _p(out)))
+        return out
+
+    def forward_batch(self, u, out=None):
+        """u: contiguous float64 (B, N, N) -> (B, N/2+1, N) complex128 half spectra."""
+        if u.dtype != torch.float64 or u.dim() != 3 or tuple(u.shape[1:]) != (self.N, self.N) \
+                or not u.is_contiguous() or u.device != self.device:
+            raise ValueError("expected contiguous float64 (B, N, N) on %s" % self.device)
+        B = int(u.shape[0])
+        if out is None:
+            out = torch.empty((B, self.H, self.N), dtype=torch.complex128, device=self.device)
+        elif out.dtype != torch.complex128 or tuple(out.shape) != (B, self.H, self.N) or \
+                not out.is_contiguous() or out.device != self.device:
+            raise ValueError("expected contiguous complex128 (B, %d, %d)" % (self.H, self.N))
+        self._sync_stream()
+        _check(lib().fch_forward_batch(self.h, B, _p(u), _p(out)))
+        return out
+
+    def lib_inverse_batch_ws_bytes(self, batch):
+        return int(lib().fch_inverse_batch_ws_bytes(self.h, int(batch)))
+
+    def inverse_batch(self, uh, out=None, ws=None):
+        """uh: contiguous complex128 (B, N/2+1, N) -> (B, N, N) float64.  ws: optional
+        device workspace (uint8 tensor) of fch_inverse_batch_ws_bytes bytes."""
+        if uh.dtype != torch.complex128 or uh.dim() != 3 or tuple(uh.shape[1:]) != (self.H, self.N) \
+                or not uh.is_contiguous() or uh.device != self.device:
+            raise ValueError("expected contiguous complex128 (B, %d, %d)" % (self.H, self.N))
+        B = int(uh.shape[0])
+        nb = int(lib().fch_inverse_batch_ws_bytes(self.h, B))
+        if ws is None:
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = torch.empty((B, self.N, self.N), dtype=torch.float64, device=self.device)
+        elif out.dtype != torch.float64 or tuple(out.shape) != (B, self.N, self.N) or \
+                not out.is_contiguous() or out.device != self.device:
+            raise ValueError("expected contiguous float64 (B, N, N)")
+        self._sync_stream()
+        _check(lib().fch_inverse_batch(self.h, B, _p(uh), _p(out), _p(ws),
+                                       ws.numel() * ws.element_size()))
         return out
 
     def chem_potential(self, uh, out=None, energy=False):
