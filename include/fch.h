@@ -229,6 +229,42 @@ fch_status fch_adapt_dt(fch_plan_t plan, const fch_c128* uh_trial, const fch_c12
 /* F(u) = Lap mu(u) as a half spectrum (device out). */
 fch_status fch_rhs(fch_plan_t plan, const fch_c128* uh, fch_c128* Fh);
 
+/* ---- the steps with device-resident scalars (graph-capturable) ------------
+ * Same operations as fch_step_imex / fch_step_sav / fch_step_psd /
+ * fch_adapt_dt (same kernels; results bit-identical for the same values),
+ * but every per-step scalar is read from device memory when the launched
+ * kernels run, every scalar result is written to device memory, and nothing
+ * allocates, synchronizes or copies to the host.  A sequence of these calls
+ * can therefore be captured into a HIP graph on the plan's stream and replayed
+ * after writing new values into the scalar buffers.
+ *   k_dev[2]      = (k_{n+1}, k_n), doubles; k_n <= 0 selects the first-order
+ *                   startup step (eq. BDF2Coef with u^{n-1} unused, but uh_nm1
+ *                   must still point at a finite field, e.g. uh_n).
+ *   r_dev[2]      = (r^n, r^{n-1}) (SAV, eq. 4.8); r_np1_dev: r^{n+1} out.
+ *   iters_dev     = PSD iterations taken (int32, out).
+ *   out_dev[3]    = (accept as 1.0 / 0.0, k_next, err) (adaptivity, out).
+ *   status_dev    = int32 out (nullable): 0 ok, FCH_E_INVALID (k not positive
+ *                   and finite, k_n <= 0 for fch_adapt_dt_dev, untabulated q
+ *                   for the lambda table), FCH_E_NOCONV (PSD limit reached),
+ *                   FCH_E_NONFINITE.
+ * All pointers are device pointers.  The host return value covers only the
+ * host-side checks (null pointers, aliasing, options).  fch_step_psd_dev
+ * launches opts->max_iter (or fixed_iters) iterations; once converged the
+ * remaining launches return at once. */
+fch_status fch_step_imex_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                             const double* k_dev, fch_c128* uh_np1, int32_t* status_dev);
+fch_status fch_step_sav_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                            const double* r_dev, const double* k_dev, fch_c128* uh_np1,
+                            double* r_np1_dev, int32_t* status_dev);
+fch_status fch_step_psd_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                            const double* k_dev, const fch_c128* guess,
+                            const fch_psd_opts* opts, fch_c128* uh_np1, int32_t* iters_dev,
+                            int32_t* status_dev);
+fch_status fch_adapt_dt_dev(fch_plan_t plan, const fch_c128* uh_trial, const fch_c128* uh_n,
+                            const fch_c128* F_n, const fch_c128* F_nm1, const double* k_dev,
+                            const fch_adapt_opts* opts, fch_c128* F_trial, double* out_dev,
+                            int32_t* status_dev);
+
 /* ---- trajectories -------------------------------------------------------- */
 /* Runs a scheme on the device state.  On entry uh_n holds u^n and uh_nm1
  * u^{n-1} (ignored when opts->startup = 1: a first-order step of size

@@ -10,6 +10,7 @@
 #include <new>
 
 #include "fch.h"
+#include "fch_coef.hpp"
 #include "fch_kernels.hpp"
 #include "fch_plan.hpp"
 
@@ -97,51 +98,9 @@ StepCtl ctl_zero() {
   return v;
 }
 
-// eq. BDF2Coef; k_n <= 0 selects the first-order startup step (u* = u^n)
-void set_bdf2(StepCtl& v, double k_np1, double k_n) {
-  v.k_np1 = k_np1;
-  v.k_n = k_n;
-  if (k_n <= 0.0) {
-    v.a = 1.0 / k_np1;
-    v.b = -1.0 / k_np1;
-    v.c = 0.0;
-    v.gamma = 0.0;
-  } else {
-    v.a = 1.0 / k_np1 + 1.0 / (k_np1 + k_n);
-    v.b = -1.0 / k_np1 - 1.0 / k_n;
-    v.c = 1.0 / k_n - 1.0 / (k_np1 + k_n);
-    v.gamma = k_np1 / k_n;
-  }
-}
-
-// eq. Predictor: AM3 weights of F(u~), F^n, F^{n-1}
-void set_am3(StepCtl& v, double k_np1, double k_n) {
-  const double g = k_np1 / k_n;
-  v.w1 = k_np1 / 6.0 * (3.0 + 2.0 * g) / (1.0 + g);
-  v.w2 = k_np1 / 6.0 * (3.0 + g);
-  v.w3 = -k_np1 / 6.0 * g * g / (1.0 + g);
-}
-
-// Table SearchSize: lambda(q, k) linear in k between the printed columns,
-// constant outside; q must be one of the tabulated rows
-double lambda_table(double q, double k) {
-  static const double ks[10] = {1e-6, 1e-5, 5e-5, 1e-4, 5e-4, 1e-3, 5e-3, 0.01, 0.02, 0.03};
-  static const double qs[3] = {0.0, 0.2, 0.5};
-  static const double lam[3][10] = {
-      {1.0, 1.07, 1.11, 1.14, 1.24, 1.34, 1.60, 1.738, 1.804, 1.855},
-      {1.0, 1.04, 1.15, 1.28, 1.50, 1.70, 1.87, 1.92, 1.95, 1.97},
-      {1.0, 1.20, 1.32, 1.45, 1.72, 1.83, 1.965, 1.97, 1.985, 1.99}};
-  int row = -1;
-  for (int i = 0; i < 3; ++i)
-    if (std::fabs(q - qs[i]) < 1e-12) row = i;
-  if (row < 0) return -1.0;
-  if (k <= ks[0]) return lam[row][0];
-  if (k >= ks[9]) return lam[row][9];
-  int j = 0;
-  while (k > ks[j + 1]) ++j;
-  const double t = (k - ks[j]) / (ks[j + 1] - ks[j]);
-  return lam[row][j] + t * (lam[row][j + 1] - lam[row][j]);
-}
+using fch::set_bdf2;
+using fch::set_am3;
+using fch::lambda_table;
 
 RowArgs row_args(fch_plan_s* p) {
   RowArgs a;
@@ -894,6 +853,136 @@ fch_status fch_adapt_dt(fch_plan_t p, const fch_c128* uh_trial, const fch_c128* 
   if (k_next) *k_next = p->hctl->k_next;
   if (err) *err = p->hctl->err;
   return status_from_ctl(p);
+}
+
+// ---- steps with device-resident scalars (graph-capturable) ----------------
+namespace {
+fch_status ctl_dev(fch_plan_s* p, const StepCtl& v, const double* k_dev, const double* r_dev,
+                   int flags) {
+  HIPCHK(fch::launch_ctl_dev(p->ctl, v, k_dev, r_dev, p->prm.q, flags, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+fch_status ctl_out(fch_plan_s* p, int what, double* d_out, int32_t* i_out, int32_t* status) {
+  if (!d_out && !i_out && !status) return FCH_OK;
+  HIPCHK(fch::launch_ctl_out(p->ctl, what, d_out, i_out, status, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+fch_status check_step_dev(fch_plan_s* p, const fch_c128* un, const fch_c128* um,
+                          const double* k_dev, const fch_c128* out) {
+  if (!p || !un || !um || !k_dev || !out) return FCH_E_INVALID;
+  if ((const void*)out == (const void*)un) return FCH_E_INVALID;
+  return need_ws(p);
+}
+}  // namespace
+
+fch_status fch_step_imex_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                             const double* k_dev, fch_c128* uh_np1, int32_t* status_dev) {
+  CHK(check_step_dev(p, uh_n, uh_nm1, k_dev, uh_np1));
+  CHK(ctl_dev(p, ctl_zero(), k_dev, nullptr, 0));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh_n;
+  a.s1 = (const cd*)uh_nm1;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+  CHK(row_mu(p, nullptr));
+  a.out = (cd*)uh_np1;
+  CHK(col(p, fch::EPI_IMEX, fch::PRO_NONE, a));
+  p->stats.fft_calls += 4;
+  p->stats.steps += 1;
+  return ctl_out(p, fch::OUT_STATUS, nullptr, nullptr, status_dev);
+}
+
+fch_status fch_step_sav_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                            const double* r_dev, const double* k_dev, fch_c128* uh_np1,
+                            double* r_np1_dev, int32_t* status_dev) {
+  CHK(check_step_dev(p, uh_n, uh_nm1, k_dev, uh_np1));
+  if (!r_dev || !r_np1_dev) return FCH_E_INVALID;
+  CHK(ctl_dev(p, ctl_zero(), k_dev, r_dev, fch::CTL_SAV));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh_n;
+  a.s1 = (const cd*)uh_nm1;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+  CHK(row_mu(p, p->rpart));
+  CHK(finalize(p, fch::FIN_SAV_S, true, false));
+  a.out = (cd*)uh_np1;
+  a.aux = p->aux;
+  a.partial = p->cpart;
+  CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, a));
+  CHK(finalize(p, fch::FIN_SAV_R, false, true));
+  HIPCHK(fch::launch_axpy_r((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->stream));
+  p->stats.launches += 1;
+  p->stats.fft_calls += 4;
+  p->stats.steps += 1;
+  return ctl_out(p, fch::OUT_SAV, r_np1_dev, nullptr, status_dev);
+}
+
+fch_status fch_step_psd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                            const double* k_dev, const fch_c128* guess,
+                            const fch_psd_opts* opts, fch_c128* uh_np1, int32_t* iters_dev,
+                            int32_t* status_dev) {
+  CHK(check_step_dev(p, uh_n, uh_nm1, k_dev, uh_np1));
+  if (!opts || opts->max_iter < 1 || !(opts->tol > 0.0 || opts->fixed_iters > 0))
+    return FCH_E_INVALID;
+  if (guess && (const void*)guess == (const void*)uh_np1) return FCH_E_INVALID;
+  int flags = 0;
+  StepCtl v = ctl_zero();
+  if (opts->lambda > 0.0) {
+    v.lambda = opts->lambda;
+  } else {
+    if (!(lambda_table(p->prm.q, 1e-3) > 0.0)) return FCH_E_INVALID;
+    flags |= fch::CTL_LAMBDA;
+  }
+  v.tol = opts->tol;
+  v.max_iter = opts->max_iter;
+  v.fixed_iters = opts->fixed_iters;
+  CHK(ctl_dev(p, v, k_dev, nullptr, flags));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh_n;
+  a.s1 = (const cd*)uh_nm1;
+  a.guess = (const cd*)guess;
+  a.out = (cd*)uh_np1;
+  a.aux = p->aux;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_PSD_INIT, a));
+  a.partial = p->cpart;
+  // every iteration up to the limit is launched; after the device flag is
+  // set (converged, limit, non-finite) the remaining launches return at once
+  const int limit = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
+  for (int i = 0; i < limit; ++i) {
+    CHK(row_mu(p, nullptr));
+    CHK(col(p, fch::EPI_PSD, fch::PRO_NEXT_FIELD, a));
+    CHK(finalize(p, fch::FIN_PSD, false, true));
+  }
+  p->stats.steps += 1;
+  return ctl_out(p, fch::OUT_PSD, nullptr, iters_dev, status_dev);
+}
+
+fch_status fch_adapt_dt_dev(fch_plan_t p, const fch_c128* uh_trial, const fch_c128* uh_n,
+                            const fch_c128* F_n, const fch_c128* F_nm1, const double* k_dev,
+                            const fch_adapt_opts* opts, fch_c128* F_trial, double* out_dev,
+                            int32_t* status_dev) {
+  if (!p || !uh_trial || !uh_n || !F_n || !F_nm1 || !F_trial || !k_dev || !out_dev)
+    return FCH_E_INVALID;
+  const void* outs = F_trial;
+  if (outs == uh_trial || outs == uh_n || outs == F_n || outs == F_nm1) return FCH_E_INVALID;
+  CHK(check_adapt(opts));
+  CHK(need_ws(p));
+  StepCtl v = ctl_zero();
+  set_adapt(v, opts);
+  CHK(ctl_dev(p, v, k_dev, nullptr, fch::CTL_AM3));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh_trial;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+  CHK(row_mu(p, nullptr));
+  a.s1 = (const cd*)uh_n;
+  a.f_n = (const cd*)F_n;
+  a.f_nm1 = (const cd*)F_nm1;
+  a.out = (cd*)F_trial;
+  a.partial = p->cpart;
+  CHK(col(p, fch::EPI_AM3, fch::PRO_NONE, a));
+  CHK(finalize(p, fch::FIN_AM3, false, true));
+  p->stats.fft_calls += 4;
+  return ctl_out(p, fch::OUT_ADAPT, out_dev, nullptr, status_dev);
 }
 
 // ---- trajectories ---------------------------------------------------------

@@ -1,0 +1,75 @@
+// fch_coef.hpp -- per-step scalars of the schemes, shared by the host-side
+// orchestration and the device-side controllers (one definition, so a step
+// driven from the host and one driven from device memory use the same
+// arithmetic).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fch_kernels.hpp"
+
+namespace fch {
+
+// eq. BDF2Coef; k_n <= 0 selects the first-order startup step (u* = u^n)
+__host__ __device__ inline void set_bdf2(StepCtl& v, double k_np1, double k_n) {
+  v.k_np1 = k_np1;
+  v.k_n = k_n;
+  if (k_n <= 0.0) {
+    v.a = 1.0 / k_np1;
+    v.b = -1.0 / k_np1;
+    v.c = 0.0;
+    v.gamma = 0.0;
+  } else {
+    v.a = 1.0 / k_np1 + 1.0 / (k_np1 + k_n);
+    v.b = -1.0 / k_np1 - 1.0 / k_n;
+    v.c = 1.0 / k_n - 1.0 / (k_np1 + k_n);
+    v.gamma = k_np1 / k_n;
+  }
+}
+
+// eq. Predictor: AM3 weights of F(u~), F^n, F^{n-1}
+__host__ __device__ inline void set_am3(StepCtl& v, double k_np1, double k_n) {
+  const double g = k_np1 / k_n;
+  v.w1 = k_np1 / 6.0 * (3.0 + 2.0 * g) / (1.0 + g);
+  v.w2 = k_np1 / 6.0 * (3.0 + g);
+  v.w3 = -k_np1 / 6.0 * g * g / (1.0 + g);
+}
+
+// Table SearchSize: lambda(q, k) linear in k between the printed columns,
+// constant outside; -1 when q is not one of the tabulated rows
+__host__ __device__ inline double lambda_table(double q, double k) {
+  const double ks[10] = {1e-6, 1e-5, 5e-5, 1e-4, 5e-4, 1e-3, 5e-3, 0.01, 0.02, 0.03};
+  const double qs[3] = {0.0, 0.2, 0.5};
+  const double lam[3][10] = {{1.0, 1.07, 1.11, 1.14, 1.24, 1.34, 1.60, 1.738, 1.804, 1.855},
+                             {1.0, 1.04, 1.15, 1.28, 1.50, 1.70, 1.87, 1.92, 1.95, 1.97},
+                             {1.0, 1.20, 1.32, 1.45, 1.72, 1.83, 1.965, 1.97, 1.985, 1.99}};
+  int row = -1;
+  for (int i = 0; i < 3; ++i)
+    if (fabs(q - qs[i]) < 1e-12) row = i;
+  if (row < 0) return -1.0;
+  if (k <= ks[0]) return lam[row][0];
+  if (k >= ks[9]) return lam[row][9];
+  int j = 0;
+  while (k > ks[j + 1]) ++j;
+  const double t = (k - ks[j]) / (ks[j + 1] - ks[j]);
+  return lam[row][j] + t * (lam[row][j + 1] - lam[row][j]);
+}
+
+// Sec. 3.2 Steps 3-4: from the relative AM3 error e of the trial step
+// k_np1, the acceptance and the next trial step (rho_s (sigma/e)^{1/3} k,
+// capped, clamped to [k_min, k_max]); returns accept
+__host__ __device__ inline int am3_decide(StepCtl& v, double e) {
+  const double kt = v.k_np1;
+  const double ee = e > 1e-300 ? e : 1e-300;
+  double kn = v.rho_s * cbrt(v.sigma_tol / ee) * kt;
+  if (v.cap > 0.0 && kn > v.cap * kt) kn = v.cap * kt;
+  if (kn > v.k_max) kn = v.k_max;
+  if (kn < v.k_min) kn = v.k_min;
+  v.err = e;
+  v.k_next = kn;
+  v.accept = (e <= v.sigma_tol) || (kt <= v.k_min);
+  return v.accept;
+}
+
+}  // namespace fch

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "fch.h"
+#include "fch_coef.hpp"
 #include "fch_kernels.hpp"
 #include "fch_plan.hpp"
 
@@ -266,16 +267,8 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   // Step 0: the first trial step equals the last step
   double kt = k1;
   if (kt > m.t_end - m.t) kt = m.t_end - m.t;
-  v.k_n = k1;
-  v.k_np1 = kt;
-  v.a = 1.0 / kt + 1.0 / (kt + k1);
-  v.b = -1.0 / kt - 1.0 / k1;
-  v.c = 1.0 / k1 - 1.0 / (kt + k1);
-  const double g = kt / k1;
-  v.gamma = g;
-  v.w1 = kt / 6.0 * (3.0 + 2.0 * g) / (1.0 + g);
-  v.w2 = kt / 6.0 * (3.0 + g);
-  v.w3 = -kt / 6.0 * g * g / (1.0 + g);
+  fch::set_bdf2(v, kt, k1);
+  fch::set_am3(v, kt, k1);
   v.done = (m.t >= m.t_end * (1.0 - 1e-14) || m.accepted >= m.max_accepted) ? 1 : 0;
   HCHK(hipStreamSynchronize(p->stream));
   HCHK(hipMemcpy(m.klog, &k1, sizeof(double), hipMemcpyHostToDevice));

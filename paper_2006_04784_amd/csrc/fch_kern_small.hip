@@ -4,6 +4,7 @@
 // energy), and the SAV combine u^{n+1} = p + r q.
 #include <hip/hip_runtime.h>
 
+#include "fch_coef.hpp"
 #include "fch_kernels_impl.hpp"
 
 namespace fch {
@@ -82,14 +83,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
     }
     case FIN_AM3: {
       const double e = sqrt(c0 / c1);
-      const double ee = e > 1e-300 ? e : 1e-300;
-      double kn = ctl->rho_s * cbrt(ctl->sigma_tol / ee) * ctl->k_np1;
-      if (ctl->cap > 0.0 && kn > ctl->cap * ctl->k_np1) kn = ctl->cap * ctl->k_np1;
-      if (kn > ctl->k_max) kn = ctl->k_max;
-      if (kn < ctl->k_min) kn = ctl->k_min;
-      ctl->err = e;
-      ctl->k_next = kn;
-      ctl->accept = (e <= ctl->sigma_tol) || (ctl->k_np1 <= ctl->k_min);
+      am3_decide(*ctl, e);
       if (!isfinite(e)) ctl->nonfinite = 1;
       break;
     }
@@ -124,15 +118,8 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
   StepCtl& ctl = m->ctl;
   const double kt = ctl.k_np1;
   const double e = sqrt(c0 / c1);
-  const double ee = e > 1e-300 ? e : 1e-300;
-  double kn = ctl.rho_s * cbrt(ctl.sigma_tol / ee) * kt;
-  if (ctl.cap > 0.0 && kn > ctl.cap * kt) kn = ctl.cap * kt;
-  if (kn > ctl.k_max) kn = ctl.k_max;
-  if (kn < ctl.k_min) kn = ctl.k_min;
-  const int accept = (e <= ctl.sigma_tol) || (kt <= ctl.k_min);
-  ctl.err = e;
-  ctl.k_next = kn;
-  ctl.accept = accept;
+  const int accept = am3_decide(ctl, e);
+  const double kn = ctl.k_next;
   if (!isfinite(e)) {
     ctl.nonfinite = 1;
     ctl.done = 1;
@@ -161,19 +148,72 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
   double k1 = kn;
   if (k1 > m->t_end - m->t) k1 = m->t_end - m->t;
   const double k0 = ctl.k_n;
-  ctl.k_np1 = k1;
-  ctl.a = 1.0 / k1 + 1.0 / (k1 + k0);
-  ctl.b = -1.0 / k1 - 1.0 / k0;
-  ctl.c = 1.0 / k0 - 1.0 / (k1 + k0);
-  const double g = k1 / k0;
-  ctl.gamma = g;
-  ctl.w1 = k1 / 6.0 * (3.0 + 2.0 * g) / (1.0 + g);
-  ctl.w2 = k1 / 6.0 * (3.0 + g);
-  ctl.w3 = -k1 / 6.0 * g * g / (1.0 + g);
+  set_bdf2(ctl, k1, k0);
+  set_am3(ctl, k1, k0);
 }
 
 hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_ens_control, dim3(count), dim3(256), 0, s, m, first);
+  return hipGetLastError();
+}
+
+// Control block of one step whose step sizes (and SAV scalars) live in device
+// memory: v carries the constant fields (tolerances, step-control options,
+// iteration limits, a fixed lambda); k_dev = (k_{n+1}, k_n) and r_dev =
+// (r^n, r^{n-1}) are read when the step runs.  An unusable k (or an
+// untabulated q when lambda comes from Table SearchSize) marks the block
+// invalid; the PSD kernels then do nothing.
+__global__ void k_ctl_dev(StepCtl* ctl, StepCtl v, const double* k_dev, const double* r_dev,
+                          double q, int flags) {
+  const double k1 = k_dev[0], k0 = k_dev[1];
+  set_bdf2(v, k1, k0);
+  if (flags & CTL_AM3) set_am3(v, k1, k0);
+  if (flags & CTL_SAV) {
+    v.r_n = r_dev[0];
+    v.r_nm1 = (k0 > 0.0) ? r_dev[1] : 0.0;
+  }
+  if (flags & CTL_LAMBDA) v.lambda = lambda_table(q, k1);
+  bool bad = !(k1 > 0.0) || !isfinite(k1) || !isfinite(k0);
+  if (flags & CTL_AM3) bad = bad || !(k0 > 0.0);
+  if (flags & CTL_LAMBDA) bad = bad || !(v.lambda > 0.0);
+  if (flags & CTL_SAV) bad = bad || !isfinite(v.r_n) || !isfinite(v.r_nm1);
+  if (bad) {
+    v.invalid = 1;
+    v.done = 4;
+  }
+  *ctl = v;
+}
+
+// Scalar results and status of the last step, written to caller memory:
+// SAV r^{n+1}; PSD iterations; adaptivity (accept, k_next, err).  status:
+// 0 ok, -1 invalid scalars, -5 PSD not converged, -6 non-finite values.
+__global__ void k_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_out, int* status) {
+  const StepCtl& c = *ctl;
+  int st = 0;
+  if (c.invalid)
+    st = -1;
+  else if (c.nonfinite || (what == OUT_PSD && c.done == 3))
+    st = -6;
+  else if (what == OUT_PSD && c.done == 2)
+    st = -5;
+  if (what == OUT_SAV && d_out) d_out[0] = c.r_np1;
+  if (what == OUT_PSD && i_out) i_out[0] = c.iters;
+  if (what == OUT_ADAPT && d_out) {
+    d_out[0] = c.accept ? 1.0 : 0.0;
+    d_out[1] = c.k_next;
+    d_out[2] = c.err;
+  }
+  if (status) *status = st;
+}
+
+hipError_t launch_ctl_dev(StepCtl* ctl, const StepCtl& v, const double* k_dev,
+                          const double* r_dev, double q, int flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_dev, dim3(1), dim3(1), 0, s, ctl, v, k_dev, r_dev, q, flags);
+  return hipGetLastError();
+}
+hipError_t launch_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_out, int* status,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_out, dim3(1), dim3(1), 0, s, ctl, what, d_out, i_out, status);
   return hipGetLastError();
 }
 

@@ -125,6 +125,13 @@ int col_variant_count(int N);
 const ColVT* col_variant(int N, int i);
 
 hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s);
+// device-scalar steps: flags of k_ctl_dev, result kinds of k_ctl_out
+enum CtlFlags { CTL_AM3 = 1, CTL_SAV = 2, CTL_LAMBDA = 4 };
+enum CtlOut { OUT_STATUS = 0, OUT_SAV = 1, OUT_PSD = 2, OUT_ADAPT = 3 };
+hipError_t launch_ctl_dev(StepCtl* ctl, const StepCtl& v, const double* k_dev,
+                          const double* r_dev, double q, int flags, hipStream_t s);
+hipError_t launch_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_out, int* status,
+                          hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s);
 // per-member AM3 decision, slot rotation and next-attempt scalars

@@ -120,6 +120,10 @@ _SIGS = {
     "fch_forward_batch": (_I, [_V, _I, _V, _V]),
     "fch_inverse_batch_ws_bytes": (C.c_size_t, [_V, _I]),
     "fch_inverse_batch": (_I, [_V, _I, _V, _V, _V, C.c_size_t]),
+    "fch_step_imex_dev": (_I, [_V, _V, _V, _V, _V, _V]),
+    "fch_step_sav_dev": (_I, [_V, _V, _V, _V, _V, _V, _V, _V]),
+    "fch_step_psd_dev": (_I, [_V, _V, _V, _V, _V, _V, _V, _V, _V]),
+    "fch_adapt_dt_dev": (_I, [_V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
     "fch_plan_set_graph": (_I, [_V, _I]),
     "fch_plan_profile_read": (_I, [_V, C.POINTER(fch_profile)]),
     "fch_forward": (_I, [_V, _V, _V]),
@@ -439,6 +443,61 @@ class Plan:
                                   k_n, C.byref(o), _p(out), C.byref(acc), C.byref(kn),
                                   C.byref(err)))
         return out, bool(acc.value), kn.value, err.value
+
+    # -- device-scalar (graph-capturable) steps: k_dev etc. are device tensors
+    def _chk_dev(self, t, n, dtype):
+        if t is None or t.dtype != dtype or t.numel() < n or not t.is_contiguous() or \
+                t.device != self.device:
+            raise ValueError("expected a contiguous %s device tensor of >= %d values" % (dtype, n))
+
+    def step_imex_dev(self, uh_n, uh_nm1, k_dev, out, status_dev=None):
+        self._chk_spec(uh_n, uh_nm1, out)
+        self._chk_dev(k_dev, 2, torch.float64)
+        if status_dev is not None:
+            self._chk_dev(status_dev, 1, torch.int32)
+        self._sync_stream()
+        _check(lib().fch_step_imex_dev(self.h, _p(uh_n), _p(uh_nm1), _p(k_dev), _p(out),
+                                       _p(status_dev)))
+        return out
+
+    def step_sav_dev(self, uh_n, uh_nm1, r_dev, k_dev, out, r_np1_dev, status_dev=None):
+        self._chk_spec(uh_n, uh_nm1, out)
+        self._chk_dev(k_dev, 2, torch.float64)
+        self._chk_dev(r_dev, 2, torch.float64)
+        self._chk_dev(r_np1_dev, 1, torch.float64)
+        if status_dev is not None:
+            self._chk_dev(status_dev, 1, torch.int32)
+        self._sync_stream()
+        _check(lib().fch_step_sav_dev(self.h, _p(uh_n), _p(uh_nm1), _p(r_dev), _p(k_dev),
+                                      _p(out), _p(r_np1_dev), _p(status_dev)))
+        return out
+
+    def step_psd_dev(self, uh_n, uh_nm1, k_dev, out, iters_dev, status_dev=None, guess=None,
+                     tol=1e-10, max_iter=1000, lam=0.0, fixed_iters=0):
+        self._chk_spec(uh_n, uh_nm1, out, guess)
+        self._chk_dev(k_dev, 2, torch.float64)
+        self._chk_dev(iters_dev, 1, torch.int32)
+        if status_dev is not None:
+            self._chk_dev(status_dev, 1, torch.int32)
+        o = fch_psd_opts(tol, max_iter, lam, fixed_iters)
+        self._sync_stream()
+        _check(lib().fch_step_psd_dev(self.h, _p(uh_n), _p(uh_nm1), _p(k_dev), _p(guess),
+                                      C.byref(o), _p(out), _p(iters_dev), _p(status_dev)))
+        return out
+
+    def adapt_dt_dev(self, uh_trial, uh_n, F_n, F_nm1, k_dev, out, out_dev, status_dev=None,
+                     opts: AdaptOpts = None):
+        self._chk_spec(uh_trial, uh_n, F_n, F_nm1, out)
+        self._chk_dev(k_dev, 2, torch.float64)
+        self._chk_dev(out_dev, 3, torch.float64)
+        if status_dev is not None:
+            self._chk_dev(status_dev, 1, torch.int32)
+        o = (opts or AdaptOpts()).c()
+        self._sync_stream()
+        _check(lib().fch_adapt_dt_dev(self.h, _p(uh_trial), _p(uh_n), _p(F_n), _p(F_nm1),
+                                      _p(k_dev), C.byref(o), _p(out), _p(out_dev),
+                                      _p(status_dev)))
+        return out
 
     def run(self, uh_n, uh_nm1, scheme="imex", adaptive=False, startup=True, nsteps=0, k=1e-3,
             k_prev=0.0, k_first=0.0, t_end=0.0, adapt: AdaptOpts = None, psd_tol=1e-10,

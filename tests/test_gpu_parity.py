@@ -453,3 +453,90 @@ def test_autotune_picks_a_compiled_variant(F, orc):
     assert torch.equal(a, a0) and torch.equal(b, b0)     # inputs untouched
     out = plan.step_imex(a, b, 1e-3, 1e-3)
     assert rel(host(out), orc.imex_step(m, u1, uh0, 1e-3, 1e-3)) < 1e-10
+
+
+# ---- device-scalar (graph-capturable) steps ---------------------------------
+def test_dev_steps_equal_host_steps(F, orc):
+    """fch_step_imex_dev / _sav_dev / _psd_dev / fch_adapt_dt_dev read their
+    scalars from device memory and equal the host-scalar calls bit for bit."""
+    log("device-scalar steps c1")
+    plan, m, uh0 = _c1(orc, F)
+    k = 1e-3
+    d = lambda *v: torch.tensor(v, dtype=torch.float64, device="cuda")
+    st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    a0 = dev(uh0)
+    # IMEX: startup, then a ratio change
+    u1 = plan.step_imex(a0, None, k, -1.0)
+    u1d = plan.step_imex_dev(a0, a0, d(k, -1.0), plan.spec(), st)
+    assert torch.equal(u1, u1d) and int(st.item()) == 0
+    u2 = plan.step_imex(u1, a0, 1.7 * k, k)
+    u2d = plan.step_imex_dev(u1, a0, d(1.7 * k, k), plan.spec(), st)
+    assert torch.equal(u2, u2d) and int(st.item()) == 0
+    # SAV
+    r0 = plan.sav_r(a0)
+    s1, r1 = plan.step_sav(u1, a0, r0, r0, 1.7 * k, k)
+    rn = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s1d = plan.step_sav_dev(u1, a0, d(r0, r0), d(1.7 * k, k), plan.spec(), rn, st)
+    assert torch.equal(s1, s1d) and float(rn.item()) == r1 and int(st.item()) == 0
+    # PSD (lambda from the table, and a fixed lambda)
+    for lam in (0.0, 1.2):
+        p1, info = plan.step_psd(u1, a0, 1.7 * k, k, tol=1e-10, lam=lam)
+        it = torch.zeros(1, dtype=torch.int32, device="cuda")
+        p1d = plan.step_psd_dev(u1, a0, d(1.7 * k, k), plan.spec(), it, st, tol=1e-10,
+                                max_iter=200, lam=lam)
+        assert torch.equal(p1, p1d) and int(it.item()) == info["iters"] and int(st.item()) == 0
+    # adaptivity
+    Fn, Fm = plan.rhs(u1), plan.rhs(a0)
+    Ft, acc, kn, err = plan.adapt_dt(u2, u1, Fn, Fm, 1.7 * k, k)
+    out = torch.zeros(3, dtype=torch.float64, device="cuda")
+    Ftd = plan.adapt_dt_dev(u2, u1, Fn, Fm, d(1.7 * k, k), plan.spec(), out, st)
+    o = out.cpu().numpy()
+    assert torch.equal(Ft, Ftd) and o[0] == float(acc) and o[1] == kn and o[2] == err
+    assert int(st.item()) == 0
+    # invalid scalars are reported on the device
+    plan.step_imex_dev(u1, a0, d(-1.0, k), plan.spec(), st)
+    assert int(st.item()) == -1
+    it = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    plan.step_psd_dev(u1, a0, d(float("nan"), k), plan.spec(), it, st, max_iter=5)
+    assert int(st.item()) == -1 and int(it.item()) == 0
+    plan.adapt_dt_dev(u2, u1, Fn, Fm, d(1.7 * k, 0.0), plan.spec(), out, st)
+    assert int(st.item()) == -1
+    # a PSD limit that is too small reports non-convergence
+    plan.step_psd_dev(u1, a0, d(1.7 * k, k), plan.spec(), it, st, tol=1e-14, max_iter=2)
+    assert int(st.item()) == -5 and int(it.item()) == 2
+
+
+def test_dev_steps_in_a_captured_graph(F, orc):
+    """Two device-scalar IMEX steps captured in a HIP graph (torch capture on
+    the plan's stream), replayed with new inputs and step sizes written
+    between replays: every replay equals the eager host-scalar steps."""
+    log("device-scalar steps under graph capture")
+    plan, m, uh0 = _c1(orc, F)
+    k = 1e-3
+    a0 = dev(uh0)
+    u1 = plan.step_imex(a0, None, k, -1.0)
+    x_nm1, x_n = a0.clone(), u1.clone()
+    y1, y2 = plan.spec(), plan.spec()
+    kd1 = torch.tensor([k, k], dtype=torch.float64, device="cuda")
+    kd2 = torch.tensor([k, k], dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    # one eager call before capture
+    plan.step_imex_dev(x_n, x_nm1, kd1, y1, st)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.step_imex_dev(x_n, x_nm1, kd1, y1, st)
+        plan.step_imex_dev(y1, x_n, kd2, y2, st)
+    cases = [(a0, u1, 1.3 * k, k, 0.8 * k), (u1, plan.step_imex(u1, a0, k, k), k, k, 2.0 * k),
+             (a0, u1, 0.5 * k, k, 0.5 * k)]
+    for rep, (um, un, k1, k0, k2) in enumerate(cases):
+        x_nm1.copy_(um)
+        x_n.copy_(un)
+        kd1.copy_(torch.tensor([k1, k0], dtype=torch.float64))
+        kd2.copy_(torch.tensor([k2, k1], dtype=torch.float64))
+        g.replay()
+        torch.cuda.synchronize()
+        e1 = plan.step_imex(un, um, k1, k0)
+        e2 = plan.step_imex(e1, un, k2, k1)
+        assert torch.equal(y1, e1) and torch.equal(y2, e2), rep
+        assert int(st.item()) == 0
