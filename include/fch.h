@@ -330,6 +330,12 @@ fch_status fch_ensemble_autotune(fch_ensemble_t ens, int32_t reps);
 /* Runs attempts until every member finished or max_attempts attempts ran. */
 fch_status fch_ensemble_run(fch_ensemble_t ens, int64_t max_attempts, int32_t sync_every,
                             int32_t use_graph, fch_ensemble_info* info);
+/* Queues `attempts` attempts of all members (captured graph replays when
+ * use_graph) after the work already on the ensemble's stream, and orders that
+ * stream after them; no synchronization, no host read-back.  Members that
+ * finished skip their work on the device.  Status: fch_ensemble_member or a
+ * later fch_ensemble_run. */
+fch_status fch_ensemble_step(fch_ensemble_t ens, int32_t attempts, int32_t use_graph);
 /* Status of member i (host out); uh (device out, nullable) receives its last
  * accepted state; klog (host out, nullable, max_steps doubles) its accepted
  * step sizes.  Synchronizes. */

@@ -56,6 +56,7 @@ struct fch_ensemble_s {
   hipStream_t user_stream = nullptr;  // caller's stream: loads, and the start of a run
   hipEvent_t fork = nullptr;
   hipEvent_t start = nullptr;
+  hipEvent_t finish = nullptr;  // end of the attempts queued by fch_ensemble_step
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 };
@@ -174,6 +175,7 @@ fch_status fch_ensemble_create(const fch_params* members, int32_t count,
   }
   if (st == FCH_OK && (hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) != hipSuccess ||
                        hipEventCreateWithFlags(&e->start, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&e->finish, hipEventDisableTiming) != hipSuccess ||
                        hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess ||
                        hipHostMalloc((void**)&e->pinned, sizeof(EnsMember) * count,
                                      hipHostMallocDefault) != hipSuccess))
@@ -203,6 +205,7 @@ fch_status fch_ensemble_destroy(fch_ensemble_t e) {
   }
   if (e->fork) (void)hipEventDestroy(e->fork);
   if (e->start) (void)hipEventDestroy(e->start);
+  if (e->finish) (void)hipEventDestroy(e->finish);
   if (e->stream) (void)hipStreamDestroy(e->stream);
   if (e->pinned) (void)hipHostFree(e->pinned);
   delete e;
@@ -289,27 +292,57 @@ fch_status fch_ensemble_autotune(fch_ensemble_t e, int32_t reps) {
   return FCH_OK;
 }
 
-fch_status fch_ensemble_run(fch_ensemble_t e, int64_t max_attempts, int32_t sync_every,
-                            int32_t use_graph, fch_ensemble_info* info) {
-  if (!e || max_attempts < 1 || sync_every < 1) return FCH_E_INVALID;
+namespace {
+// captures one attempt of all members into a graph on first use
+fch_status ensure_graph(fch_ensemble_s* e) {
+  if (e->gexec) return FCH_OK;
+  HCHK(hipStreamBeginCapture(e->stream, hipStreamCaptureModeGlobal));
+  fch_status st = enqueue_attempt(e);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(e->stream, &g);
+  if (st != FCH_OK || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != FCH_OK ? st : FCH_E_HIP;
+  }
+  e->graph = g;
+  if (hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    drop_graph(e);
+    return FCH_E_HIP;
+  }
+  return FCH_OK;
+}
+
+fch_status check_runnable(fch_ensemble_s* e) {
   if (!e->ws) return FCH_E_NOMEM;
   for (int k = 0; k < e->count; ++k)
     if (!e->loaded[k]) return FCH_E_INVALID;
-  if (use_graph && !e->gexec) {
-    HCHK(hipStreamBeginCapture(e->stream, hipStreamCaptureModeGlobal));
-    fch_status st = enqueue_attempt(e);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(e->stream, &g);
-    if (st != FCH_OK || ec != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return st != FCH_OK ? st : FCH_E_HIP;
-    }
-    e->graph = g;
-    if (hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-      drop_graph(e);
-      return FCH_E_HIP;
+  return FCH_OK;
+}
+}  // namespace
+
+fch_status fch_ensemble_step(fch_ensemble_t e, int32_t attempts, int32_t use_graph) {
+  if (!e || attempts < 1) return FCH_E_INVALID;
+  SCHK(check_runnable(e));
+  if (use_graph) SCHK(ensure_graph(e));
+  HCHK(hipEventRecord(e->start, e->user_stream));
+  HCHK(hipStreamWaitEvent(e->stream, e->start, 0));
+  for (int32_t i = 0; i < attempts; ++i) {
+    if (use_graph) {
+      HCHK(hipGraphLaunch(e->gexec, e->stream));
+    } else {
+      SCHK(enqueue_attempt(e));
     }
   }
+  HCHK(hipEventRecord(e->finish, e->stream));
+  HCHK(hipStreamWaitEvent(e->user_stream, e->finish, 0));
+  return FCH_OK;
+}
+
+fch_status fch_ensemble_run(fch_ensemble_t e, int64_t max_attempts, int32_t sync_every,
+                            int32_t use_graph, fch_ensemble_info* info) {
+  if (!e || max_attempts < 1 || sync_every < 1) return FCH_E_INVALID;
+  SCHK(check_runnable(e));
+  if (use_graph) SCHK(ensure_graph(e));
   // order after the caller's stream
   HCHK(hipEventRecord(e->start, e->user_stream));
   HCHK(hipStreamWaitEvent(e->stream, e->start, 0));

@@ -147,6 +147,7 @@ _SIGS = {
     "fch_ensemble_load": (_I, [_V, _I, _V]),
     "fch_ensemble_autotune": (_I, [_V, _I]),
     "fch_ensemble_run": (_I, [_V, C.c_int64, _I, _I, C.POINTER(fch_ensemble_info)]),
+    "fch_ensemble_step": (_I, [_V, _I, _I]),
     "fch_ensemble_member": (_I, [_V, _I, _V, _PD, C.POINTER(fch_member_info)]),
     "fch_nn_conv_fwd": (_I, [_I, _I, _I, _I, _V, _V, _V, _V, _V, _V, _V]),
     "fch_nn_conv_bwd_data": (_I, [_I, _I, _I, _I, _V, _V, _V, _V, _V, _V]),
@@ -573,6 +574,11 @@ class Ensemble:
     def autotune(self, reps=10):
         self._sync_stream()
         _check(lib().fch_ensemble_autotune(self.h, reps))
+
+    def step(self, attempts=1, use_graph=True):
+        """Queues attempts on the device without waiting (fch_ensemble_step)."""
+        self._sync_stream()
+        _check(lib().fch_ensemble_step(self.h, int(attempts), int(use_graph)))
 
     def run(self, max_attempts=100000, sync_every=50, use_graph=True):
         info = fch_ensemble_info()

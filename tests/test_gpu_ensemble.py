@@ -119,3 +119,22 @@ def test_mixed_sizes_autotuned(F):
     for i, m in enumerate(mem):
         uh, klog, mi = ens.member(i)
         assert torch.isfinite(uh).all() and mi["accepted"] == 20
+
+
+def test_ensemble_step_queues_without_waiting(F):
+    """fch_ensemble_step: attempts queued in chunks (graph and eager) reach
+    the same member states, bit for bit, as one fch_ensemble_run."""
+    log("ensemble step chunks")
+    mem = members_small()
+    ref = build(F, mem)
+    ref.run(max_attempts=1000, sync_every=50, use_graph=True)
+    for use_graph in (True, False):
+        ens = build(F, mem)
+        for _ in range(40):   # more attempts than any member needs: finished ones idle
+            ens.step(attempts=5, use_graph=use_graph)
+        info = ens.run(max_attempts=1, sync_every=1, use_graph=use_graph)
+        for i in range(len(mem)):
+            a, ka, ma = ens.member(i)
+            b, kb, mb = ref.member(i)
+            assert ma["done"] and ma["accepted"] == mb["accepted"], (use_graph, i)
+            assert torch.equal(a, b) and np.array_equal(ka, kb), (use_graph, i)
