@@ -4,4 +4,4 @@
 #include "fch_variants.hpp"
 
 FCH_VARIANTS(16, FCH_LIST(RowImpl<16, 2, 4, 1>::table(), RowImpl<16, 1, 4, 1>::table()),
-             FCH_LIST(ColImpl<16, 4, 0>::table(), ColImpl<16, 4, 1>::table(), ColImpl<16, 16, 0>::table()))
+             FCH_LIST(ColImpl<16, 4, 0>::table(), ColImpl<16, 4, 1>::table()))

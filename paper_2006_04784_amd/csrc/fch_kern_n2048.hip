@@ -4,4 +4,4 @@
 #include "fch_variants.hpp"
 
 FCH_VARIANTS(2048, FCH_LIST(RowImpl<2048, 2, 8, 0>::table(), RowImpl<2048, 2, 16, 1>::table(), RowImpl<2048, 2, 16, 0>::table(), RowImpl<2048, 1, 16, 0>::table(), RowImpl<2048, 1, 8, 0>::table()),
-             FCH_LIST(ColImpl<2048, 8, 0>::table(), ColImpl<2048, 4, 0>::table(), ColImpl<2048, 8, 1>::table(), ColImpl<2048, 16, 0>::table()))
+             FCH_LIST(ColImpl<2048, 8, 0>::table(), ColImpl<2048, 4, 0>::table(), ColImpl<2048, 8, 1>::table()))

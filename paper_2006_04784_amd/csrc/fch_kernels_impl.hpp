@@ -222,13 +222,14 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
 // ===========================================================================
 
 // Columns kx = 0 and kx = N/2 of the half spectrum of a real field obey
-// U(ky) = conj U(N - ky).  Rounding in the column FFTs breaks this slightly;
-// the explicit linear terms of the schemes act on that non-real component
-// while the pointwise terms (computed from real fields) never see it, so it
-// would grow from step to step.  Every state written by a column pass is
-// therefore projected: U(ky) <- (U(ky) + conj U(N - ky)) / 2, exchanging
-// partners through LDS.  Call only where kx is 0 or N/2 (uniform per group).
-// (the first NF of the NV register fields are projected)
+// U(ky) = conj U(N - ky).  Rounding breaks this slightly; the explicit linear
+// terms of the schemes act on that non-real component while the pointwise
+// terms (computed from real fields) never see it, so it would grow from step
+// to step.  The single-field column transforms project their output:
+// U(ky) <- (U(ky) + conj U(N - ky)) / 2, exchanging partners through LDS.
+// Call only where kx is 0 or N/2 (uniform per group).  (The first NF of the
+// NV register fields are projected.)  The column pass of the schemes keeps
+// these columns exactly Hermitian by construction instead (col_body).
 template <int N, int E, int NF, int NV>
 __device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd* const (&lds)[2], int t) {
   constexpr int T = N / E;
@@ -247,6 +248,173 @@ __device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd* const (&lds)[2
     }
   __syncthreads();
 }
+
+// ---- per-wavenumber algebra of the column pass --------------------------------
+// State values read at one wavenumber before the forward FFT: u^n, u^{n-1}
+// (IMEX, SAV), the PSD iterate and b u^n + c u^{n-1} (PSD), or the field U
+// whose (U, Lap U) fed the evaluation (MU, F, AM3).
+template <int EPI>
+__device__ __forceinline__ void load_pre(const ColArgs& a, size_t g, cd& p0, cd& p1) {
+  if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
+    p0 = a.s0[g];
+    p1 = a.s1[g];
+  } else if constexpr (EPI == EPI_PSD) {
+    p0 = a.out[g];
+    p1 = a.aux[g];
+  } else {
+    p0 = a.s0[g];
+    p1 = cd{0.0, 0.0};
+  }
+}
+
+// Epilogue at one wavenumber from the forward-transformed omega^, p^:
+// mu^ = -eps^2 |k|^2 omega^ + p^ - eps^2 eta1 |k|^2 U^ (eq. FCH with Lap ->
+// -|k|^2), then the scheme's diagonal algebra.  o0: the output (u^{n+1},
+// mu^, F^, the next PSD iterate, F(u~)); o1: SAV q^ or PSD d^; Ua: the field
+// the partial sums need (U, or X for SAV); un, um: u^n, u^{n-1}.
+template <int EPI>
+__device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, double k2,
+                                          double wgt, cd om, cd pp, cd p0, cd p1, cd& o0,
+                                          cd& o1, cd& Ua, cd& un, cd& um, double (&acc)[2]) {
+  const double e2k2 = c.eps2 * k2;
+  cd U;
+  un = cd{0.0, 0.0};
+  um = cd{0.0, 0.0};
+  if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
+    un = p0;
+    um = p1;
+    U = cadd(un, cscale(csub(un, um), ctl->gamma));
+  } else {
+    U = p0;
+  }
+  Ua = U;
+  o1 = cd{0.0, 0.0};
+  const cd mu = {-e2k2 * om.x + pp.x - e2k2 * c.eta1 * U.x,
+                 -e2k2 * om.y + pp.y - e2k2 * c.eta1 * U.y};
+  if constexpr (EPI == EPI_MU) {
+    o0 = mu;
+    acc[0] += wgt * k2 * cnorm2(U);
+  } else if constexpr (EPI == EPI_F) {
+    o0 = cscale(mu, -k2);
+  } else if constexpr (EPI == EPI_IMEX) {
+    const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
+    const cd Nh = csub(mu, cscale(U, Lk));
+    const double inv = 1.0 / (ctl->a + k2 * Lk);
+    o0 = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * Nh.x) * inv,
+            (-ctl->b * un.y - ctl->c * um.y - k2 * Nh.y) * inv};
+  } else if constexpr (EPI == EPI_SAV) {
+    const double lsav = e2k2 * e2k2 - e2k2 * (c.eta1 + 2.0 * c.zeta);
+    const double inv_s = 1.0 / ctl->s_star;
+    const cd X = cscale(csub(mu, cscale(U, lsav)), inv_s);
+    const double L0 = e2k2 * e2k2 + c.beta1 * c.alpha * e2k2 + c.beta2 * c.alpha * c.alpha;
+    const double L1 = -e2k2 * (c.eta1 + 2.0 * c.zeta) - c.beta1 * c.alpha * e2k2 -
+                      c.beta2 * c.alpha * c.alpha;
+    const double inv = 1.0 / (ctl->a + k2 * L0);
+    o0 = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * L1 * U.x) * inv,
+            (-ctl->b * un.y - ctl->c * um.y - k2 * L1 * U.y) * inv};
+    o1 = cscale(X, -k2 * inv);
+    Ua = X;  // the SAV sums need X
+  } else if constexpr (EPI == EPI_PSD) {
+    const cd G = p1;
+    cd d = {0.0, 0.0};
+    if (k2 != 0.0) {
+      const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
+      const double inv = -1.0 / (k2 * Lk + ctl->a);
+      d = cd{(k2 * mu.x + ctl->a * U.x + G.x) * inv, (k2 * mu.y + ctl->a * U.y + G.y) * inv};
+    }
+    o0 = cadd(U, cscale(d, ctl->lambda));
+    o1 = d;
+  } else if constexpr (EPI == EPI_AM3) {
+    o0 = cscale(mu, -k2);
+  }
+}
+
+// After the epilogue: the stores, the Parseval partial sums and the field
+// handed to the next prologue (unext).
+template <int EPI, int PRO>
+__device__ __forceinline__ void post_point(const ColArgs& a, const StepCtl* ctl, size_t g,
+                                           double wgt, cd o0, cd o1, cd Ua, cd un, cd um,
+                                           cd& unext, double (&acc)[2]) {
+  a.out[g] = o0;
+  if constexpr (EPI == EPI_MU || EPI == EPI_F) {
+    unext = Ua;
+  } else if constexpr (EPI == EPI_IMEX) {
+    if constexpr (PRO == PRO_NEXT_EXTRAP)
+      unext = cadd(o0, cscale(csub(o0, un), ctl->gamma));
+    else
+      unext = o0;
+  } else if constexpr (EPI == EPI_SAV) {
+    a.aux[g] = o1;
+    const cd rp = {ctl->a * o0.x + ctl->b * un.x + ctl->c * um.x,
+                   ctl->a * o0.y + ctl->b * un.y + ctl->c * um.y};
+    acc[0] += wgt * cdotr(Ua, rp);
+    acc[1] += wgt * cdotr(Ua, o1);
+  } else if constexpr (EPI == EPI_PSD) {
+    acc[0] += wgt * cnorm2(o1);
+    acc[1] += wgt * cnorm2(o0);
+    unext = o0;
+  } else if constexpr (EPI == EPI_AM3) {
+    const cd u_n = a.s1[g], fn = a.f_n[g], fm = a.f_nm1[g];
+    const cd up = {u_n.x + ctl->w1 * o0.x + ctl->w2 * fn.x + ctl->w3 * fm.x,
+                   u_n.y + ctl->w1 * o0.y + ctl->w2 * fn.y + ctl->w3 * fm.y};
+    acc[0] += wgt * cnorm2(csub(Ua, up));
+    acc[1] += wgt * cnorm2(up);
+  }
+}
+
+// State values the prologue reads at one wavenumber (PRO_FIELD: U; EXTRAP and
+// PSD_INIT: u^n, u^{n-1} and, for PSD_INIT, the guess).
+template <int PRO>
+__device__ __forceinline__ void load_pro(const ColArgs& a, size_t g, cd& s0v, cd& s1v, cd& gv) {
+  s0v = a.s0[g];
+  s1v = cd{0.0, 0.0};
+  gv = cd{0.0, 0.0};
+  if constexpr (PRO == PRO_EXTRAP || PRO == PRO_PSD_INIT) s1v = a.s1[g];
+  if constexpr (PRO == PRO_PSD_INIT) {
+    if (a.guess) gv = a.guess[g];
+  }
+}
+
+// Prologue at one wavenumber: U whose (U, Lap U) the next evaluation needs:
+// the field, the extrapolation u^n + gamma (u^n - u^{n-1}) (eq. Richardson),
+// or the PSD initial iterate (guess, keeping the mean of u^n; PSD_INIT also
+// writes b u^n + c u^{n-1} and the iterate).  PRO_NEXT_*: unext.
+template <int PRO>
+__device__ __forceinline__ cd pro_point(const ColArgs& a, const StepCtl* ctl, size_t g,
+                                        bool mean_mode, cd s0v, cd s1v, cd gv, cd unext) {
+  if constexpr (PRO == PRO_FIELD) {
+    return s0v;
+  } else if constexpr (PRO == PRO_EXTRAP) {
+    return cadd(s0v, cscale(csub(s0v, s1v), ctl->gamma));
+  } else if constexpr (PRO == PRO_PSD_INIT) {
+    a.aux[g] = cd{ctl->b * s0v.x + ctl->c * s1v.x, ctl->b * s0v.y + ctl->c * s1v.y};
+    cd U;
+    if (a.guess)
+      U = mean_mode ? s0v : gv;  // keep the mass of u^n
+    else
+      U = cadd(s0v, cscale(csub(s0v, s1v), ctl->gamma));
+    a.out[g] = U;
+    return U;
+  } else {
+    return unext;
+  }
+}
+
+// Hermitian part of a column of a real field's half spectrum at ky, from its
+// values at ky and N - ky (exactly conjugate at the two points)
+__device__ __forceinline__ cd herm(cd x, cd xr) {
+  return cd{0.5 * (x.x + xr.x), 0.5 * (x.y - xr.y)};
+}
+
+// N/2 workgroups.  Workgroup kx > 0 transforms column kx.  Workgroup 0
+// transforms the two self-conjugate columns kx = 0 and N/2 together: the
+// row-transformed fields are real there, so each field's two columns pack
+// into one complex sequence z = X_0 + i X_{N/2}, and after the FFT
+// X^_0(k) = (Z(k) + conj Z(-k))/2, X^_{N/2}(k) = (Z(k) - conj Z(-k))/(2i).
+// The state values its epilogue reads are replaced by their Hermitian parts,
+// so every state it writes is exactly the spectrum of a real field (a
+// non-Hermitian component of these columns would be amplified by the
+// explicit terms of the schemes); the inverse transforms pack the same way.
 template <int N, int E, int EPI, int PRO, int TWL>
 __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
   constexpr int T = N / E;
@@ -259,8 +427,10 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
   const Consts& c = a.c;
   const int t = threadIdx.x;
   const int kx = blockIdx.x;
+  const bool sc = (kx == 0);  // the self-conjugate pair kx = 0, N/2
   const size_t col = (size_t)kx * N;
-  const double wgt = (kx == 0 || kx == M) ? 1.0 : 2.0;  // Parseval weight of the half spectrum
+  constexpr size_t colM = (size_t)M * N;
+  const double wgt = sc ? 1.0 : 2.0;  // Parseval weight of the half spectrum
 
   const cd* tw = a.tw;
   if constexpr (TWL) {
@@ -271,176 +441,193 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
 
   cd v[2][E];
   cd* const base[2] = {buf[0], buf[1]};
-  cd unext[E];  // field handed to the prologue by the epilogue
+  // PRO_NEXT_*: the epilogue hands the next evaluation's field to the
+  // prologue by writing (U, -|k|^2 U) (packed for the self-conjugate pair)
+  // straight into v[.][s], whose FFT output it has just consumed
+  constexpr bool NEXT = (PRO == PRO_NEXT_EXTRAP || PRO == PRO_NEXT_FIELD);
   double acc[2] = {0.0, 0.0};
   const StepCtl* ctl = a.ctl;
 
   if constexpr (EPI != EPI_NONE) {
-    // the FFT inputs are requested first; the state values of this column
-    // are requested after them, before the FFT, so that they arrive while it
-    // runs (vector loads complete in issue order)
-    cd pre0[E], pre1[E];
+    // the FFT inputs are requested first; the state values after them,
+    // before the FFT, so that they arrive while it runs.  Workgroup 0 reads
+    // both of its columns here: every state value it uses is read before it
+    // writes any output (outputs may alias u^{n-1} or, for PSD, the iterate).
+    cd pre0[E], pre1[E], preM0[E], preM1[E];
+    if (sc) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const size_t g = col + t + s * T;
-      v[0][s] = a.P0[g];
-      v[1][s] = a.P1[g];
-    }
+      for (int s = 0; s < E; ++s) {
+        const int ky = t + s * T;
+        const cd a0 = a.P0[ky], aM = a.P0[colM + ky];
+        const cd b0 = a.P1[ky], bM = a.P1[colM + ky];
+        v[0][s] = cd{a0.x - aM.y, a0.y + aM.x};
+        v[1][s] = cd{b0.x - bM.y, b0.y + bM.x};
+      }
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const size_t g = col + t + s * T;
-      if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
-        pre0[s] = a.s0[g];
-        pre1[s] = a.s1[g];
-      } else if constexpr (EPI == EPI_PSD) {
-        pre0[s] = a.out[g];
-        pre1[s] = a.aux[g];
-      } else {
-        pre0[s] = a.s0[g];
+      for (int s = 0; s < E; ++s) load_pre<EPI>(a, colM + t + s * T, preM0[s], preM1[s]);
+    } else {
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        const size_t g = col + t + s * T;
+        v[0][s] = a.P0[g];
+        v[1][s] = a.P1[g];
       }
     }
+#pragma unroll
+    for (int s = 0; s < E; ++s) load_pre<EPI>(a, col + t + s * T, pre0[s], pre1[s]);
     fft<N, E, 2, -1>(v, base, tw, t);
 
-    // epilogue values: o[0] the state / output, o[1] the SAV q; Ua holds the
-    // field U and un (u^n) where later terms need them
-    cd o[2][E];
-    cd Ua[E], una[E], uma[E];
+    if (!sc) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const int ky = t + s * T;
-      const size_t g = col + ky;
-      const double k2 = wavek2(c, kx, ky);
-      const cd om = v[0][s], pp = v[1][s];
-      const double e2k2 = c.eps2 * k2;
-      // field U whose (U, Lap U) fed this evaluation
-      cd U;
-      cd un = {0, 0}, um = {0, 0};
-      if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
-        un = pre0[s];
-        um = pre1[s];
-        U = cadd(un, cscale(csub(un, um), ctl->gamma));
-      } else {
-        U = pre0[s];
-      }
-      Ua[s] = U;
-      una[s] = un;
-      uma[s] = um;
-      // mu = -eps^2 |k|^2 omega + p - eps^2 eta1 |k|^2 U
-      const cd mu = {-e2k2 * om.x + pp.x - e2k2 * c.eta1 * U.x,
-                     -e2k2 * om.y + pp.y - e2k2 * c.eta1 * U.y};
-      if constexpr (EPI == EPI_MU) {
-        o[0][s] = mu;
-        acc[0] += wgt * k2 * cnorm2(U);
-      } else if constexpr (EPI == EPI_F) {
-        o[0][s] = cscale(mu, -k2);
-      } else if constexpr (EPI == EPI_IMEX) {
-        const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
-        const cd Nh = csub(mu, cscale(U, Lk));
-        const double inv = 1.0 / (ctl->a + k2 * Lk);
-        o[0][s] = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * Nh.x) * inv,
-                     (-ctl->b * un.y - ctl->c * um.y - k2 * Nh.y) * inv};
-      } else if constexpr (EPI == EPI_SAV) {
-        const double lsav = e2k2 * e2k2 - e2k2 * (c.eta1 + 2.0 * c.zeta);
-        const double inv_s = 1.0 / ctl->s_star;
-        const cd X = cscale(csub(mu, cscale(U, lsav)), inv_s);
-        const double L0 = e2k2 * e2k2 + c.beta1 * c.alpha * e2k2 + c.beta2 * c.alpha * c.alpha;
-        const double L1 = -e2k2 * (c.eta1 + 2.0 * c.zeta) - c.beta1 * c.alpha * e2k2 -
-                          c.beta2 * c.alpha * c.alpha;
-        const double inv = 1.0 / (ctl->a + k2 * L0);
-        o[0][s] = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * L1 * U.x) * inv,
-                     (-ctl->b * un.y - ctl->c * um.y - k2 * L1 * U.y) * inv};
-        o[1][s] = cscale(X, -k2 * inv);
-        Ua[s] = X;  // the SAV sums need X
-      } else if constexpr (EPI == EPI_PSD) {
-        const cd G = pre1[s];
-        cd d = {0.0, 0.0};
-        if (k2 != 0.0) {
-          const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
-          const double inv = -1.0 / (k2 * Lk + ctl->a);
-          d = cd{(k2 * mu.x + ctl->a * U.x + G.x) * inv, (k2 * mu.y + ctl->a * U.y + G.y) * inv};
+      for (int s = 0; s < E; ++s) {
+        const int ky = t + s * T;
+        const double k2 = wavek2(c, kx, ky);
+        cd o0, o1, Ua, un, um, U;
+        epi_point<EPI>(c, ctl, k2, wgt, v[0][s], v[1][s], pre0[s], pre1[s], o0, o1, Ua, un, um,
+                       acc);
+        post_point<EPI, PRO>(a, ctl, col + ky, wgt, o0, o1, Ua, un, um, U, acc);
+        if constexpr (NEXT) {
+          v[0][s] = U;
+          v[1][s] = cscale(U, -k2);
         }
-        o[0][s] = cadd(U, cscale(d, ctl->lambda));
-        o[1][s] = d;
-      } else if constexpr (EPI == EPI_AM3) {
-        o[0][s] = cscale(mu, -k2);
       }
-    }
-    // states written by this pass are spectra of real fields (see hermitian_fix)
-    if constexpr (EPI == EPI_IMEX || EPI == EPI_PSD) {
-      if (kx == 0 || kx == M) hermitian_fix<N, E, 1, 2>(o, base, t);
-    } else if constexpr (EPI == EPI_SAV) {
-      if (kx == 0 || kx == M) hermitian_fix<N, E, 2, 2>(o, base, t);
-    }
+    } else {
+      // separate the two columns; Z(-k) comes from the thread holding N - ky:
+      // omega^, p^ of column 0 are (Z + conj Z(-k))/2, of column N/2
+      // (Z - conj Z(-k))/(2i)
+      constexpr bool P1 = (EPI == EPI_IMEX || EPI == EPI_SAV || EPI == EPI_PSD);
+      cd sep[4][E];  // omega^_0, p^_0, omega^_{N/2}, p^_{N/2}
+      __syncthreads();
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const size_t g = col + t + s * T;
-      a.out[g] = o[0][s];
-      if constexpr (EPI == EPI_MU || EPI == EPI_F) {
-        unext[s] = Ua[s];
-      } else if constexpr (EPI == EPI_IMEX) {
-        if constexpr (PRO == PRO_NEXT_EXTRAP)
-          unext[s] = cadd(o[0][s], cscale(csub(o[0][s], una[s]), ctl->gamma));
-        else
-          unext[s] = o[0][s];
-      } else if constexpr (EPI == EPI_SAV) {
-        a.aux[g] = o[1][s];
-        const cd p = o[0][s], un = una[s], um = uma[s];
-        const cd rp = {ctl->a * p.x + ctl->b * un.x + ctl->c * um.x,
-                       ctl->a * p.y + ctl->b * un.y + ctl->c * um.y};
-        acc[0] += wgt * cdotr(Ua[s], rp);
-        acc[1] += wgt * cdotr(Ua[s], o[1][s]);
-      } else if constexpr (EPI == EPI_PSD) {
-        acc[0] += wgt * cnorm2(o[1][s]);
-        acc[1] += wgt * cnorm2(o[0][s]);
-        unext[s] = o[0][s];
-      } else if constexpr (EPI == EPI_AM3) {
-        const cd F = o[0][s];
-        const cd u_n = a.s1[g], fn = a.f_n[g], fm = a.f_nm1[g];
-        const cd up = {u_n.x + ctl->w1 * F.x + ctl->w2 * fn.x + ctl->w3 * fm.x,
-                       u_n.y + ctl->w1 * F.y + ctl->w2 * fn.y + ctl->w3 * fm.y};
-        acc[0] += wgt * cnorm2(csub(Ua[s], up));
-        acc[1] += wgt * cnorm2(up);
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < E; ++s) base[q][lp(t + s * T)] = v[q][s];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          const cd z = v[q][s], zr = base[q][lp((N - (t + s * T)) & (N - 1))];
+          sep[q][s] = herm(z, zr);
+          sep[2 + q][s] = cd{0.5 * (z.y + zr.y), -0.5 * (z.x - zr.x)};
+        }
+      // the state values of each column are replaced by their Hermitian
+      // parts through the same exchange; then that column's epilogue
+      cd U0[E];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        cd(&p0)[E] = h ? preM0 : pre0;
+        cd(&p1)[E] = h ? preM1 : pre1;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          base[0][lp(t + s * T)] = p0[s];
+          if constexpr (P1) base[1][lp(t + s * T)] = p1[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          const int kr = (N - (t + s * T)) & (N - 1);
+          p0[s] = herm(p0[s], base[0][lp(kr)]);
+          if constexpr (P1) p1[s] = herm(p1[s], base[1][lp(kr)]);
+        }
+        const int kxh = h ? M : 0;
+        const size_t colh = h ? colM : 0;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          const int ky = t + s * T;
+          const double k2 = wavek2(c, kxh, ky);
+          cd o0, o1, Ua, un, um, U;
+          epi_point<EPI>(c, ctl, k2, 1.0, sep[2 * h][s], sep[2 * h + 1][s], p0[s], p1[s], o0, o1,
+                         Ua, un, um, acc);
+          post_point<EPI, PRO>(a, ctl, colh + ky, 1.0, o0, o1, Ua, un, um, U, acc);
+          if constexpr (NEXT) {
+            if (h == 0) {
+              U0[s] = U;
+            } else {
+              const double k20 = wavek2(c, 0, ky);
+              v[0][s] = cd{U0[s].x - U.y, U0[s].y + U.x};
+              v[1][s] = cd{-k20 * U0[s].x + k2 * U.y, -k20 * U0[s].y - k2 * U.x};
+            }
+          }
+        }
       }
     }
   }
 
   if constexpr (PRO != PRO_NONE) {
+    if constexpr (!NEXT) {
+      // each point is read and written by the same thread; workgroup 0 then
+      // replaces U of columns 0 and N/2 by its Hermitian part (U is linear in
+      // the state with real coefficients, so this equals projecting the
+      // state) and packs their inverse transforms as the real and the
+      // imaginary part of one sequence
+      if (!sc) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const int ky = t + s * T;
-      const size_t g = col + ky;
-      const double k2 = wavek2(c, kx, ky);
-      cd U;
-      if constexpr (PRO == PRO_FIELD) {
-        U = a.s0[g];
-      } else if constexpr (PRO == PRO_EXTRAP) {
-        const cd un = a.s0[g], um = a.s1[g];
-        U = cadd(un, cscale(csub(un, um), ctl->gamma));
-      } else if constexpr (PRO == PRO_PSD_INIT) {
-        const cd un = a.s0[g], um = a.s1[g];
-        a.aux[g] = cd{ctl->b * un.x + ctl->c * um.x, ctl->b * un.y + ctl->c * um.y};
-        if (a.guess) {
-          U = (kx == 0 && ky == 0) ? un : a.guess[g];  // keep the mass of u^n
-        } else {
-          U = cadd(un, cscale(csub(un, um), ctl->gamma));
+        for (int s = 0; s < E; ++s) {
+          const int ky = t + s * T;
+          cd s0v, s1v, gv;
+          load_pro<PRO>(a, col + ky, s0v, s1v, gv);
+          const cd U = pro_point<PRO>(a, ctl, col + ky, false, s0v, s1v, gv, cd{0.0, 0.0});
+          v[0][s] = U;
+          v[1][s] = cscale(U, -wavek2(c, kx, ky));
         }
-        a.out[g] = U;
       } else {
-        U = unext[s];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          const int ky = t + s * T;
+          cd s0v, s1v, gv;
+          load_pro<PRO>(a, ky, s0v, s1v, gv);
+          v[0][s] = pro_point<PRO>(a, ctl, ky, ky == 0, s0v, s1v, gv, cd{0.0, 0.0});
+          load_pro<PRO>(a, colM + ky, s0v, s1v, gv);
+          v[1][s] = pro_point<PRO>(a, ctl, colM + ky, false, s0v, s1v, gv, cd{0.0, 0.0});
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int s = 0; s < E; ++s) base[q][lp(t + s * T)] = v[q][s];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+          const int ky = t + s * T;
+          const int kr = (N - ky) & (N - 1);
+          const cd U = herm(v[0][s], base[0][lp(kr)]), UM = herm(v[1][s], base[1][lp(kr)]);
+          const double k2 = wavek2(c, 0, ky), k2M = wavek2(c, M, ky);
+          v[0][s] = cd{U.x - UM.y, U.y + UM.x};
+          v[1][s] = cd{-k2 * U.x + k2M * UM.y, -k2 * U.y - k2M * UM.x};
+        }
       }
-      v[0][s] = U;
-      v[1][s] = cscale(U, -k2);
     }
     fft<N, E, 2, +1>(v, base, tw, t);
+    if (!sc) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-      a.P0[col + t + s * T] = v[0][s];
-      a.P1[col + t + s * T] = v[1][s];
+      for (int s = 0; s < E; ++s) {
+        a.P0[col + t + s * T] = v[0][s];
+        a.P1[col + t + s * T] = v[1][s];
+      }
+    } else {
+      // the inverse transforms of the two real columns are the real and the
+      // imaginary part (the row pass reads real parts at kx = 0, N/2)
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        const int ky = t + s * T;
+        a.P0[ky] = cd{v[0][s].x, 0.0};
+        a.P0[colM + ky] = cd{v[0][s].y, 0.0};
+        a.P1[ky] = cd{v[1][s].x, 0.0};
+        a.P1[colM + ky] = cd{v[1][s].y, 0.0};
+      }
     }
   }
 
   if constexpr (EPI == EPI_MU || EPI == EPI_SAV || EPI == EPI_PSD || EPI == EPI_AM3) {
-    if (a.partial) block_reduce<T, 2>(acc, red, a.partial + 2 * kx);
+    if (a.partial) {
+      block_reduce<T, 2>(acc, red, a.partial + 2 * kx);
+      if (sc && t == 0) {  // the sums of column N/2 are in workgroup 0's
+        a.partial[2 * M] = 0.0;
+        a.partial[2 * M + 1] = 0.0;
+      }
+    }
   }
 }
 

@@ -72,7 +72,7 @@ struct ColImpl {
   template <int EPI, int PRO>
   static hipError_t lc(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const int* done = &a.ctl->done;
-    FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL>), dim3(H), dim3(CT), s, e0, e1, a, done);
+    FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL>), dim3(N / 2), dim3(CT), s, e0, e1, a, done);
     return hipGetLastError();
   }
 
@@ -103,7 +103,7 @@ struct ColImpl {
     return hipGetLastError();
   }
   static hipError_t col_ens(int stage, EnsMember* m, int first, int count, hipStream_t s) {
-    const dim3 grid(H, count);
+    const dim3 grid(N / 2, count);  // workgroup 0 takes both self-conjugate columns
     switch (stage) {
       case ENS_PRO:
         hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_PRO>), grid, dim3(CT), 0, s, m, first);

@@ -540,3 +540,54 @@ def test_dev_steps_in_a_captured_graph(F, orc):
         e2 = plan.step_imex(e1, un, k2, k1)
         assert torch.equal(y1, e1) and torch.equal(y2, e2), rep
         assert int(st.item()) == 0
+
+
+def test_output_aliasing_u_nm1_is_exact(F, orc):
+    """IMEX, SAV and PSD with uh_np1 == uh_nm1 equal the non-aliased call bit
+    for bit: every value a column workgroup reads (including the mirrored
+    values of the self-conjugate columns kx = 0, N/2) is read before any
+    output of that workgroup is written."""
+    log("aliasing u^{n+1} = u^{n-1}")
+    plan, m, uh0 = _c1(orc, F)
+    k = 1e-3
+    a0 = dev(uh0)
+    u1 = plan.step_imex(a0, None, k, -1.0)
+    ref = plan.step_imex(u1, a0, 1.3 * k, k)
+    b = a0.clone()
+    plan.step_imex(u1, b, 1.3 * k, k, out=b)
+    assert torch.equal(b, ref)
+    r0 = plan.sav_r(a0)
+    ref, rr = plan.step_sav(u1, a0, r0, r0, 1.3 * k, k)
+    b = a0.clone()
+    _, rb = plan.step_sav(u1, b, r0, r0, 1.3 * k, k, out=b)
+    assert torch.equal(b, ref) and rb == rr
+    ref, st = plan.step_psd(u1, a0, 1.3 * k, k, tol=1e-10)
+    b = a0.clone()
+    _, st2 = plan.step_psd(u1, b, 1.3 * k, k, tol=1e-10, out=b)
+    assert torch.equal(b, ref) and st2["iters"] == st["iters"]
+
+
+def test_self_conjugate_columns_stay_exactly_hermitian(F, orc):
+    """A state whose kx = 0 and N/2 columns are perturbed off Hermitian
+    symmetry is stepped: the column pass uses their Hermitian parts, so every
+    state it writes has U(ky) == conj U(N - ky) bit for bit in those columns,
+    and the trajectory equals the oracle's from the projected start."""
+    log("self-conjugate columns")
+    plan, m, uh0 = _c1(orc, F)
+    N = uh0.shape[0]
+    rng = np.random.default_rng(5)
+    bad = uh0.copy()
+    for kx in (0, N // 2):
+        bad[:, kx] += 1e-3 * (rng.normal(size=N) + 1j * rng.normal(size=N)) * np.abs(uh0[:, kx]).max()
+    proj = bad.copy()
+    for kx in (0, N // 2):
+        col = bad[:, kx]
+        proj[:, kx] = 0.5 * (col + np.conj(col[(-np.arange(N)) % N]))
+    ref = orc.run_fixed(m, "imex", proj, 1e-3, 30)
+    a, b = dev(bad), torch.zeros_like(dev(bad))
+    plan.run(a, b, scheme="imex", nsteps=30, k=1e-3)
+    h = host(a)
+    for kx in (0, N // 2):
+        col = h[:, kx]
+        assert np.array_equal(col, np.conj(col[(-np.arange(N)) % N])), kx
+    assert rel(h, ref) < 1e-8
