@@ -39,7 +39,7 @@ def spec_bytes(N):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fch_device.hpp", "fch_kernels_impl.hpp"):
+    for f in ("fch_device.hpp", "fch_kernels_impl.hpp", "fch_coef.hpp"):
         with open(os.path.join(ROOT, "paper_2006_04784_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -172,6 +172,14 @@ fch_status row_mu(fch_plan_s* p, double* partial) {
   return FCH_OK;
 }
 
+// n PSD iterations (Sec. 3.3) after `done_before` iterations of the solve:
+// each is a row pass (chemical-potential pieces of the iterate) and a column
+// pass (step, partial sums, next iterate's inverse transform).  From the
+// second iteration on, the row pass first evaluates the previous iteration's
+// stopping test; the last one is evaluated by one finalize launch.  Once the
+// test has stopped the solve, the remaining launches return at once.
+fch_status psd_iterations(fch_plan_s* p, const ColArgs& a, int done_before, int n);
+
 fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
   FinArgs f;
   std::memset(&f, 0, sizeof(f));
@@ -192,6 +200,24 @@ fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
     fch_status s_ = (x);               \
     if (s_ != FCH_OK) return s_;       \
   } while (0)
+
+fch_status psd_iterations(fch_plan_s* p, const ColArgs& a, int done_before, int n) {
+  for (int i = 0; i < n; ++i) {
+    RowArgs r = row_args(p);
+    if (i > 0) {
+      r.psd_part = p->cpart;
+      r.psd_ncol = p->H;
+      r.psd_iter = done_before + i;
+    }
+    const int pr = prof_begin(p, 0);
+    HIPCHK(p->rv->row(fch::ROW_MU, r, p->stream, nullptr, nullptr));
+    prof_end(p, pr);
+    p->stats.launches += 1;
+    CHK(col(p, fch::EPI_PSD, fch::PRO_NEXT_FIELD, a));
+  }
+  if (n > 0) CHK(finalize(p, fch::FIN_PSD, false, true));
+  return FCH_OK;
+}
 
 
 // one chemical-potential evaluation of the field already column-inverted in
@@ -780,11 +806,7 @@ fch_status fch_step_psd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   int chunk = p->psd_hint > 0 ? p->psd_hint : 4;
   for (;;) {
     const int n = (chunk < limit - queued) ? chunk : (limit - queued);
-    for (int i = 0; i < n; ++i) {
-      CHK(row_mu(p, nullptr));
-      CHK(col(p, fch::EPI_PSD, fch::PRO_NEXT_FIELD, a));
-      CHK(finalize(p, fch::FIN_PSD, false, true));
-    }
+    CHK(psd_iterations(p, a, queued, n));
     queued += n;
     CHK(readback(p));
     if (p->hctl->done || queued >= limit) break;
@@ -948,11 +970,7 @@ fch_status fch_step_psd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   // every iteration up to the limit is launched; after the device flag is
   // set (converged, limit, non-finite) the remaining launches return at once
   const int limit = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
-  for (int i = 0; i < limit; ++i) {
-    CHK(row_mu(p, nullptr));
-    CHK(col(p, fch::EPI_PSD, fch::PRO_NEXT_FIELD, a));
-    CHK(finalize(p, fch::FIN_PSD, false, true));
-  }
+  CHK(psd_iterations(p, a, 0, limit));
   p->stats.steps += 1;
   return ctl_out(p, fch::OUT_PSD, nullptr, iters_dev, status_dev);
 }

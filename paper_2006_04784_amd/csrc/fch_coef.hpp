@@ -72,4 +72,15 @@ __host__ __device__ inline int am3_decide(StepCtl& v, double e) {
   return v.accept;
 }
 
+// Sec. 3.3 stopping test after `iters` iterations whose last step ratio is
+// ||d|| / ||u_{s+1}||: 0 continue, 1 converged (or the fixed count reached),
+// 2 iteration limit, 3 non-finite
+__host__ __device__ inline int psd_done_code(const StepCtl& v, double ratio, int iters) {
+  if (!isfinite(ratio)) return 3;
+  if (v.fixed_iters > 0) return iters >= v.fixed_iters ? 1 : 0;
+  if (ratio < v.tol) return 1;
+  if (iters >= v.max_iter) return 2;
+  return 0;
+}
+
 }  // namespace fch

@@ -37,8 +37,13 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
     r1 = sum_strided(a.rpart, a.nrow, 2, 1, red);
   }
   if (a.cpart) {
-    c0 = sum_strided(a.cpart, a.ncol, 2, 0, red);
-    c1 = sum_strided(a.cpart, a.ncol, 2, 1, red);
+    if (a.mode == FIN_PSD) {
+      // the same summation as the stopping test folded into the row pass
+      fixed_sum2<256>(a.cpart, a.ncol, c0, c1);
+    } else {
+      c0 = sum_strided(a.cpart, a.ncol, 2, 0, red);
+      c1 = sum_strided(a.cpart, a.ncol, 2, 1, red);
+    }
   }
   if (threadIdx.x != 0) return;
   switch (a.mode) {
@@ -67,18 +72,12 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
     }
     case FIN_PSD: {
       const double ratio = sqrt(c0 / c1);
+      const int it = ctl->iters + 1;
+      const int code = psd_done_code(*ctl, ratio, it);
       ctl->ratio = ratio;
-      ctl->iters += 1;
-      if (!isfinite(ratio)) {
-        ctl->nonfinite = 1;
-        ctl->done = 3;
-      } else if (ctl->fixed_iters > 0) {
-        if (ctl->iters >= ctl->fixed_iters) ctl->done = 1;
-      } else if (ratio < ctl->tol) {
-        ctl->done = 1;
-      } else if (ctl->iters >= ctl->max_iter) {
-        ctl->done = 2;
-      }
+      ctl->iters = it;
+      if (code) ctl->done = code;
+      if (code == 3) ctl->nonfinite = 1;
       break;
     }
     case FIN_AM3: {

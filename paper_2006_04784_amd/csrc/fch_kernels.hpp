@@ -42,6 +42,12 @@ struct RowArgs {
   double* partial;     // ROW_MU: 2 per workgroup (E_1 density, energy density), nullable
   StepCtl* ctl;
   const cd* tw;        // exp(-2 pi i m / N), m < N
+  // ROW_MU inside a PSD solve (nullable): the column partial sums of the
+  // previous iteration (psd_ncol pairs), whose stopping test every workgroup
+  // evaluates first; psd_iter = the number of iterations that test completes
+  const double* psd_part;
+  int psd_ncol;
+  int psd_iter;
 };
 
 struct ColArgs {

@@ -21,6 +21,7 @@
 
 #include <type_traits>
 
+#include "fch_coef.hpp"
 #include "fch_kernels.hpp"
 
 namespace fch {
@@ -61,6 +62,82 @@ __device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, 
   }
 }
 
+// Sums of the two interleaved partial-sum columns p[2i], p[2i+1], i < n, in
+// one fixed order whatever the caller's workgroup size: 64 lanes take
+// i = l, l+64, ... each, then a fixed XOR butterfly.  Called by the threads
+// 0..NT-1 of a workgroup; with NT >= 64 the first wavefront computes it,
+// with fewer threads thread 0 reproduces the same additions.  Valid in
+// thread 0.
+template <int NT>
+__device__ __forceinline__ void fixed_sum2(const double* p, int n, double& s0, double& s1) {
+  if constexpr (NT >= 64) {
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x;
+      double a = 0.0, b = 0.0;
+      for (int i = l; i < n; i += 64) {
+        a += p[2 * i];
+        b += p[2 * i + 1];
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+      }
+      s0 = a;
+      s1 = b;
+    }
+  } else {
+    if (threadIdx.x == 0) {
+      double a[64], b[64];
+      for (int l = 0; l < 64; ++l) {
+        a[l] = 0.0;
+        b[l] = 0.0;
+        for (int i = l; i < n; i += 64) {
+          a[l] += p[2 * i];
+          b[l] += p[2 * i + 1];
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        double na[64], nb[64];
+        for (int l = 0; l < 64; ++l) {
+          na[l] = a[l] + a[l ^ off];
+          nb[l] = b[l] + b[l ^ off];
+        }
+        for (int l = 0; l < 64; ++l) {
+          a[l] = na[l];
+          b[l] = nb[l];
+        }
+      }
+      s0 = a[0];
+      s1 = b[0];
+    }
+  }
+}
+
+// Stopping test of a PSD iteration (Sec. 3.3) from its column partial sums
+// (sum |d|^2, sum |u_{s+1}|^2): every workgroup of the next row pass computes
+// the same verdict; workgroup 0 records it.  Returns the done code in all
+// threads.
+template <int NT>
+__device__ __forceinline__ int psd_check(const RowArgs& a) {
+  __shared__ int verdict;
+  double c0 = 0.0, c1 = 0.0;
+  fixed_sum2<NT>(a.psd_part, a.psd_ncol, c0, c1);
+  if (threadIdx.x == 0) {
+    const double ratio = sqrt(c0 / c1);
+    const int code = psd_done_code(*a.ctl, ratio, a.psd_iter);
+    verdict = code;
+    if (blockIdx.x == 0) {
+      a.ctl->ratio = ratio;
+      a.ctl->iters = a.psd_iter;
+      if (code) a.ctl->done = code;
+      if (code == 3) a.ctl->nonfinite = 1;
+    }
+  }
+  __syncthreads();
+  return verdict;
+}
+
 // ===========================================================================
 // Row pass
 // ===========================================================================
@@ -80,6 +157,9 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   __shared__ cd twl[TWL ? N : 1];
   __shared__ double red[2 * ((NT + 63) / 64)];
   if (done && *done) return;
+  if constexpr (MODE == ROW_MU) {
+    if (a.psd_part && psd_check<NT>(a)) return;
+  }
 
   const int tid = threadIdx.x;
   const int seq = tid / T;
@@ -674,6 +754,9 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
   a.partial = nullptr;
   a.ctl = &m->ctl;
   a.tw = m->tw;
+  a.psd_part = nullptr;
+  a.psd_ncol = 0;
+  a.psd_iter = 0;
   row_body<N, R, E, ROW_MU, TWL>(a, &m->ctl.done);
 }
 
