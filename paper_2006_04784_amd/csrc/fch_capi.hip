@@ -759,13 +759,14 @@ fch_status fch_step_sav(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   a.s1 = um;
   CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
   CHK(row_mu(p, p->rpart));
-  CHK(finalize(p, fch::FIN_SAV_S, true, false));
   a.out = (cd*)uh_np1;
   a.aux = p->aux;
   a.partial = p->cpart;
+  a.sav_rpart = p->rpart;
+  a.sav_nrow = p->N / p->rv->R;
   CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, a));
-  CHK(finalize(p, fch::FIN_SAV_R, false, true));
-  HIPCHK(fch::launch_axpy_r((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->stream));
+  HIPCHK(fch::launch_sav_combine((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->cpart, p->H,
+                                 p->c.pars, p->stream));
   p->stats.launches += 1;
   p->stats.fft_calls += 4;
   p->stats.steps += 1;
@@ -926,13 +927,14 @@ fch_status fch_step_sav_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   a.s1 = (const cd*)uh_nm1;
   CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
   CHK(row_mu(p, p->rpart));
-  CHK(finalize(p, fch::FIN_SAV_S, true, false));
   a.out = (cd*)uh_np1;
   a.aux = p->aux;
   a.partial = p->cpart;
+  a.sav_rpart = p->rpart;
+  a.sav_nrow = p->N / p->rv->R;
   CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, a));
-  CHK(finalize(p, fch::FIN_SAV_R, false, true));
-  HIPCHK(fch::launch_axpy_r((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->stream));
+  HIPCHK(fch::launch_sav_combine((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->cpart, p->H,
+                                 p->c.pars, p->stream));
   p->stats.launches += 1;
   p->stats.fft_calls += 4;
   p->stats.steps += 1;

@@ -72,6 +72,24 @@ __host__ __device__ inline int am3_decide(StepCtl& v, double e) {
   return v.accept;
 }
 
+// SAV auxiliary scalar at the extrapolated state (eqs. 4.5-4.6):
+// s* = sqrt(E_1(u*) + D0).  Returns 0, 1 (non-finite) or 2 (E_1 + D0 <= 0);
+// s is 1 when unusable.
+__host__ __device__ inline int sav_sstar(double E1, double D0, double& s) {
+  const double s2 = E1 + D0;
+  s = 1.0;
+  if (!isfinite(s2)) return 1;
+  if (!(s2 > 0.0)) return 2;
+  s = sqrt(s2);
+  return 0;
+}
+
+// SAV scalar solve (eq. 4.8) from g_p = (X, a p + b u^n + c u^{n-1}) and
+// g_q = (X, q): r^{n+1} = (-b r^n - c r^{n-1} + g_p / 2) / (a - a g_q / 2)
+__host__ __device__ inline double sav_r_solve(const StepCtl& v, double gp, double gq) {
+  return (-v.b * v.r_n - v.c * v.r_nm1 + 0.5 * gp) / (v.a - 0.5 * v.a * gq);
+}
+
 // Sec. 3.3 stopping test after `iters` iterations whose last step ratio is
 // ||d|| / ||u_{s+1}||: 0 continue, 1 converged (or the fixed count reached),
 // 2 iteration limit, 3 non-finite

@@ -49,25 +49,12 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   switch (a.mode) {
     case FIN_SAV_S: {
       const double E1 = c.h2 * r0;
-      const double s2 = E1 + c.D0;
+      double sst;
+      const int st = sav_sstar(E1, c.D0, sst);
       ctl->E1 = E1;
-      if (!isfinite(s2)) {
-        ctl->nonfinite = 1;
-        ctl->s_star = 1.0;
-      } else if (!(s2 > 0.0)) {
-        ctl->invalid = 1;
-        ctl->s_star = 1.0;
-      } else {
-        ctl->s_star = sqrt(s2);
-      }
-      break;
-    }
-    case FIN_SAV_R: {
-      const double gp = c.pars * c0, gq = c.pars * c1;
-      const double r = (-ctl->b * ctl->r_n - ctl->c * ctl->r_nm1 + 0.5 * gp) /
-                       (ctl->a - 0.5 * ctl->a * gq);
-      ctl->r_np1 = r;
-      if (!isfinite(r)) ctl->nonfinite = 1;
+      ctl->s_star = sst;
+      if (st == 1) ctl->nonfinite = 1;
+      if (st == 2) ctl->invalid = 1;
       break;
     }
     case FIN_PSD: {
@@ -94,8 +81,23 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   }
 }
 
-__global__ void k_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n) {
-  const double r = ctl->r_np1;
+// u^{n+1} = p + r^{n+1} q (eq. 4.8).  Every workgroup solves for r^{n+1} from
+// the column partial sums (g_p, g_q) in the same order; workgroup 0 records it.
+__global__ __launch_bounds__(256) void k_sav_combine(cd* out, const cd* q, StepCtl* ctl, size_t n,
+                                                     const double* cpart, int ncol, double pars) {
+  __shared__ double rs;
+  double c0 = 0.0, c1 = 0.0;
+  fixed_sum2<256>(cpart, ncol, c0, c1);
+  if (threadIdx.x == 0) {
+    const double r = sav_r_solve(*ctl, pars * c0, pars * c1);
+    rs = r;
+    if (blockIdx.x == 0) {
+      ctl->r_np1 = r;
+      if (!isfinite(r)) ctl->nonfinite = 1;
+    }
+  }
+  __syncthreads();
+  const double r = rs;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
     const cd o = out[i], qq = q[i];
@@ -224,10 +226,12 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s) {
+hipError_t launch_sav_combine(cd* out, const cd* q, StepCtl* ctl, size_t n, const double* cpart,
+                              int ncol, double pars, hipStream_t s) {
   size_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_axpy_r, dim3((unsigned)blocks), dim3(256), 0, s, out, q, ctl, n);
+  if (blocks > 512) blocks = 512;  // each workgroup also reads the 2 ncol partial sums
+  hipLaunchKernelGGL(k_sav_combine, dim3((unsigned)blocks), dim3(256), 0, s, out, q, ctl, n, cpart,
+                     ncol, pars);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ struct StepCtl {
 enum RowMode { ROW_MU = 0, ROW_FWD = 1, ROW_INV = 2 };
 enum Epi { EPI_NONE = 0, EPI_MU, EPI_F, EPI_IMEX, EPI_SAV, EPI_PSD, EPI_AM3 };
 enum Pro { PRO_NONE = 0, PRO_FIELD, PRO_EXTRAP, PRO_PSD_INIT, PRO_NEXT_EXTRAP, PRO_NEXT_FIELD };
-enum FinMode { FIN_SAV_S = 0, FIN_SAV_R, FIN_PSD, FIN_AM3, FIN_ENERGY };
+enum FinMode { FIN_SAV_S = 0, FIN_PSD, FIN_AM3, FIN_ENERGY };
 
 struct RowArgs {
   Consts c;
@@ -66,6 +66,10 @@ struct ColArgs {
   double* partial;  // 2 per column
   StepCtl* ctl;
   const cd* tw;
+  // EPI_SAV (nullable): the row partial sums (E_1 densities, sav_nrow pairs)
+  // from which every workgroup forms s*; otherwise ctl->s_star is used
+  const double* sav_rpart;
+  int sav_nrow;
 };
 
 struct FinArgs {
@@ -139,7 +143,9 @@ hipError_t launch_ctl_dev(StepCtl* ctl, const StepCtl& v, const double* k_dev,
 hipError_t launch_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_out, int* status,
                           hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
-hipError_t launch_axpy_r(cd* out, const cd* q, const StepCtl* ctl, size_t n, hipStream_t s);
+// SAV combine u^{n+1} = p + r^{n+1} q, the r-solve done in every workgroup
+hipError_t launch_sav_combine(cd* out, const cd* q, StepCtl* ctl, size_t n, const double* cpart,
+                              int ncol, double pars, hipStream_t s);
 // per-member AM3 decision, slot rotation and next-attempt scalars
 hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s);
 

@@ -353,9 +353,10 @@ __device__ __forceinline__ void load_pre(const ColArgs& a, size_t g, cd& p0, cd&
 // mu^, F^, the next PSD iterate, F(u~)); o1: SAV q^ or PSD d^; Ua: the field
 // the partial sums need (U, or X for SAV); un, um: u^n, u^{n-1}.
 template <int EPI>
-__device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, double k2,
-                                          double wgt, cd om, cd pp, cd p0, cd p1, cd& o0,
-                                          cd& o1, cd& Ua, cd& un, cd& um, double (&acc)[2]) {
+__device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, double sstar,
+                                          double k2, double wgt, cd om, cd pp, cd p0, cd p1,
+                                          cd& o0, cd& o1, cd& Ua, cd& un, cd& um,
+                                          double (&acc)[2]) {
   const double e2k2 = c.eps2 * k2;
   cd U;
   un = cd{0.0, 0.0};
@@ -384,7 +385,7 @@ __device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, d
             (-ctl->b * un.y - ctl->c * um.y - k2 * Nh.y) * inv};
   } else if constexpr (EPI == EPI_SAV) {
     const double lsav = e2k2 * e2k2 - e2k2 * (c.eta1 + 2.0 * c.zeta);
-    const double inv_s = 1.0 / ctl->s_star;
+    const double inv_s = 1.0 / sstar;
     const cd X = cscale(csub(mu, cscale(U, lsav)), inv_s);
     const double L0 = e2k2 * e2k2 + c.beta1 * c.alpha * e2k2 + c.beta2 * c.alpha * c.alpha;
     const double L1 = -e2k2 * (c.eta1 + 2.0 * c.zeta) - c.beta1 * c.alpha * e2k2 -
@@ -519,6 +520,33 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
     tw = twl;
   }
 
+  // SAV: s* = sqrt(E_1(u*) + D0) from the row pass's partial sums, formed
+  // by every workgroup in the same order (workgroup 0 records it)
+  double sstar = 0.0;
+  if constexpr (EPI == EPI_SAV) {
+    __shared__ double sh_s;
+    if (a.sav_rpart) {
+      double r0 = 0.0, r1 = 0.0;
+      fixed_sum2<T>(a.sav_rpart, a.sav_nrow, r0, r1);
+      if (t == 0) {
+        const double E1 = c.h2 * r0;
+        double sst;
+        const int st = sav_sstar(E1, c.D0, sst);
+        sh_s = sst;
+        if (blockIdx.x == 0) {
+          a.ctl->E1 = E1;
+          a.ctl->s_star = sst;
+          if (st == 1) a.ctl->nonfinite = 1;
+          if (st == 2) a.ctl->invalid = 1;
+        }
+      }
+      __syncthreads();
+      sstar = sh_s;
+    } else {
+      sstar = a.ctl->s_star;
+    }
+  }
+
   cd v[2][E];
   cd* const base[2] = {buf[0], buf[1]};
   // PRO_NEXT_*: the epilogue hands the next evaluation's field to the
@@ -563,8 +591,8 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
         const int ky = t + s * T;
         const double k2 = wavek2(c, kx, ky);
         cd o0, o1, Ua, un, um, U;
-        epi_point<EPI>(c, ctl, k2, wgt, v[0][s], v[1][s], pre0[s], pre1[s], o0, o1, Ua, un, um,
-                       acc);
+        epi_point<EPI>(c, ctl, sstar, k2, wgt, v[0][s], v[1][s], pre0[s], pre1[s], o0, o1, Ua, un,
+                       um, acc);
         post_point<EPI, PRO>(a, ctl, col + ky, wgt, o0, o1, Ua, un, um, U, acc);
         if constexpr (NEXT) {
           v[0][s] = U;
@@ -618,8 +646,8 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
           const int ky = t + s * T;
           const double k2 = wavek2(c, kxh, ky);
           cd o0, o1, Ua, un, um, U;
-          epi_point<EPI>(c, ctl, k2, 1.0, sep[2 * h][s], sep[2 * h + 1][s], p0[s], p1[s], o0, o1,
-                         Ua, un, um, acc);
+          epi_point<EPI>(c, ctl, sstar, k2, 1.0, sep[2 * h][s], sep[2 * h + 1][s], p0[s], p1[s],
+                         o0, o1, Ua, un, um, acc);
           post_point<EPI, PRO>(a, ctl, colh + ky, 1.0, o0, o1, Ua, un, um, U, acc);
           if constexpr (NEXT) {
             if (h == 0) {
@@ -738,6 +766,8 @@ __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
   a.partial = nullptr;
   a.ctl = const_cast<StepCtl*>(&m->ctl);
   a.tw = m->tw;
+  a.sav_rpart = nullptr;
+  a.sav_nrow = 0;
 }
 
 template <int N, int R, int E, int TWL>
