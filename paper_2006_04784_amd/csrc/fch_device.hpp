@@ -266,6 +266,9 @@ struct Consts {
   double pars;    // L^2 / N^4: h^2 sum_x f g = pars * sum_half w Re(f g*)
 };
 
+// W, W', W'' at u.  Q = (q != 0) is a template argument so that a caller
+// evaluating many points tests the uniform q once, outside its point loop,
+// and the points' chains interleave.
 template <bool Q>
 __device__ __forceinline__ void well_t(const Consts& c, double u, double& W, double& W1,
                                        double& W2) {
@@ -286,16 +289,6 @@ __device__ __forceinline__ void well_t(const Consts& c, double u, double& W, dou
   W = A * B;
   W1 = A1 * B + A * B1;
   W2 = A2 * B + 2.0 * A1 * B1 + A;
-}
-
-// Q = (q != 0) is uniform; callers that evaluate many points hoist the test
-// out of their loop (well_t) so that the points' chains interleave.
-__device__ __forceinline__ void well(const Consts& c, double u, double& W, double& W1,
-                                     double& W2) {
-  if (c.q != 0.0)
-    well_t<true>(c, u, W, W1, W2);
-  else
-    well_t<false>(c, u, W, W1, W2);
 }
 
 // Workgroup index remap so that consecutive logical tiles land on the same

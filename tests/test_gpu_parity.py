@@ -591,3 +591,55 @@ def test_self_conjugate_columns_stay_exactly_hermitian(F, orc):
         col = h[:, kx]
         assert np.array_equal(col, np.conj(col[(-np.arange(N)) % N])), kx
     assert rel(h, ref) < 1e-8
+
+
+def test_constant_state_is_a_fixed_point(F, orc):
+    """Degenerate input: a spatially constant u has Lap u = 0 and a constant
+    chemical potential, so F(u) = Lap mu = 0 and every scheme keeps it (the
+    mean to rounding, every other mode at rounding level); the oracle agrees."""
+    log("constant state")
+    kw = model_kw(64, 4 * np.pi)
+    plan, m = pair(F, orc, **kw)
+    u = np.full((64, 64), -0.3)
+    uh = orc.r2c(u)
+    a = dev(uh)
+    k = 1e-3
+    mean = abs(uh[0, 0])
+
+    def check(out, what):
+        h = host(out)
+        assert abs(h[0, 0] - uh[0, 0]) <= 1e-14 * mean, what
+        rest = h.copy()
+        rest[0, 0] = 0.0
+        assert np.abs(rest).max() <= 1e-12 * mean, what
+
+    check(plan.step_imex(a, None, k, -1.0), "imex startup")
+    check(plan.step_imex(a, a, 1.5 * k, k), "imex")
+    r0 = plan.sav_r(a)
+    out, r1 = plan.step_sav(a, a, r0, r0, k, k)
+    check(out, "sav")
+    assert abs(r1 - r0) <= 1e-12 * abs(r0)
+    out, st = plan.step_psd(a, a, k, k, tol=1e-10)
+    check(out, "psd")
+    assert st["iters"] <= 2
+    F0 = plan.rhs(a)
+    assert float(F0.abs().max()) <= 1e-10 * mean
+    x, y = a.clone(), a.clone()
+    info = plan.run(x, y, scheme="imex", adaptive=True, startup=True, t_end=0.05, k_first=1e-4)
+    check(x, "adaptive")
+    assert info["accepted"] >= 2
+    ref = orc.imex_step(m, uh, uh, 1.5 * k, k)
+    assert np.abs(ref - uh).max() <= 1e-12 * mean
+
+
+def test_batch_limits(F, orc):
+    plan = F.Plan(**model_kw(16, 2 * np.pi))
+    lib = F.lib()
+    U = torch.zeros((1, 16, 16), dtype=torch.float64, device="cuda")
+    Uh = torch.zeros((1, 9, 16), dtype=torch.complex128, device="cuda")
+    import ctypes as C
+    for b in (0, 65536, -1):
+        assert lib.fch_forward_batch(plan.h, b, C.c_void_p(U.data_ptr()),
+                                     C.c_void_p(Uh.data_ptr())) == F.FCH_E_INVALID
+    assert lib.fch_inverse_batch_ws_bytes(plan.h, 0) == 0
+    assert lib.fch_inverse_batch_ws_bytes(plan.h, 3) == 3 * 16 * 9 * 16
