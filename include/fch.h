@@ -382,10 +382,13 @@ fch_status fch_nn_to_bf16(int32_t n, const float* p, void* p_bf16, void* stream)
 /* Features of B samples of physical fields (f64 [B][H][W]); k: [B][2] = (k_{n+1},
  * k_n).  d = (u^n - u^{n-1}) k_{n+1}/k_n, scale s = RMS(d) (f64 [B] out),
  * x = [u^n, d/s, (log10 k_{n+1} + 3)/2, 0, ...] (bf16), and the target
- * (u^{n+1} - u^n - d)/s (f32, only when u_np1 and target are non-NULL). */
+ * (u^{n+1} - u^n - d)/s (f32, only when u_np1 and target are non-NULL).
+ * work: device scratch of fch_nn_features_work_doubles(B) doubles (partial
+ * sums of the scale). */
+int32_t    fch_nn_features_work_doubles(int32_t B);
 fch_status fch_nn_features(int32_t B, int32_t H, int32_t W, const double* u_n, const double* u_nm1,
                            const double* u_np1, const double* k, void* x, float* target,
-                           double* scale, void* stream);
+                           double* scale, double* work, void* stream);
 /* g = u^n + d + s * o (physical f64 [B][H][W]). */
 fch_status fch_nn_guess(int32_t B, int32_t H, int32_t W, const double* u_n, const double* u_nm1,
                         const double* k, const double* scale, const float* o, double* g,

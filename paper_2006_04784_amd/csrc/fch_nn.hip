@@ -132,25 +132,33 @@ __global__ void k_flip_weights(int cout, const u16* __restrict__ w, u16* __restr
   wt[i] = (co < cout) ? w[((8 - t) * cout + co) * C + ci] : (u16)0;
 }
 
-// Weight and bias gradients.  A workgroup owns ROWS image rows of one
-// sample and walks them in 32-pixel chunks: per chunk it stages dz^T and
-// three column-shifted copies of the input (rows r-1..r+1) channel-major in
-// LDS, then each wave accumulates its taps' 32x32 blocks with MFMA (K = 32
-// pixels).  Per-workgroup partials are reduced in a fixed order afterwards.
+// Weight and bias gradients dW[t][co][ci] = sum_p dz[p][co] x[p + t][ci],
+// db[co] = sum_p dz[p][co]: a reduction over pixels, which the MFMA takes as
+// its K dimension.  A workgroup owns WROWS output rows of one sample and
+// walks them in 32-pixel chunks.  Per chunk it stages, channel-major in LDS,
+// the WROWS + 2 input rows it needs (34 pixels with the periodic halo) and
+// the WROWS dz rows, each from 16-byte global loads written as pixel pairs.
+// The three horizontal tap shifts read the same input lines at offsets 0, 1,
+// 2 pixels: two aligned 16-byte reads and a byte-align for the odd shift.
+// Wave w owns taps w, w+4, w+8 over all rows, so its accumulators need no
+// cross-wave sum.  Per-workgroup partials are reduced in a fixed order.
 constexpr int WROWS = 8;
+constexpr int LP = 40;  // u16 per staged line: 34 pixels + pad (80 B, 16-B aligned)
 template <int COUT>
 __global__ __launch_bounds__(256) void k_conv_bwd_w(int H, int W, const u16* __restrict__ dz,
                                                     const u16* __restrict__ x,
                                                     float* __restrict__ part) {
   constexpr int MT = COUT / 16;
-  __shared__ u16 dzT[COUT][32 + 8];
-  __shared__ u16 xT[3][3][C][32 + 8];  // [dx][row][ci][px]
+  constexpr int XR = WROWS + 2;
+  __shared__ __attribute__((aligned(16))) u16 xT[XR][C][LP];
+  __shared__ __attribute__((aligned(16))) u16 dzT[WROWS][COUT][LP];
+  __shared__ float dbs[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kb = lane >> 4;
   const int bands = H / WROWS;
   const int b = blockIdx.x / bands, r0 = (blockIdx.x % bands) * WROWS;
-  const u16* dzb = dz + (size_t)b * H * W * C;
-  const u16* xb = x + (size_t)b * H * W * C;
+  const uint4* dzb = (const uint4*)(dz + (size_t)b * H * W * C);
+  const uint4* xb = (const uint4*)(x + (size_t)b * H * W * C);
   f32x4 acc[3][MT][2];
 #pragma unroll
   for (int s = 0; s < 3; ++s)
@@ -158,40 +166,78 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(int H, int W, const u16* __r
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int n = 0; n < 2; ++n) acc[s][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // bias: thread (co, row) sums its row's 32 pixels per chunk
+  constexpr int DBT = COUT * WROWS;  // threads that take part (<= 256)
   float dbacc = 0.f;
-  for (int r = r0; r < r0 + WROWS; ++r) {
-    for (int c0 = 0; c0 < W; c0 += 32) {
-      __syncthreads();
-      for (int i = tid; i < 32 * COUT; i += 256) {
-        const int px = i / COUT, co = i % COUT;
-        dzT[co][px] = dzb[((size_t)r * W + c0 + px) * C + co];
+  for (int c0 = 0; c0 < W; c0 += 32) {
+    __syncthreads();
+    // input lines: rows r0-1 .. r0+WROWS, pixels c0-1 .. c0+32 as pairs
+    for (int i = tid; i < XR * 17 * (C / 8); i += 256) {
+      const int q = i % (C / 8), pr = (i / (C / 8)) % 17, rr = i / ((C / 8) * 17);
+      const int gr = (r0 + rr - 1 + H) % H;
+      const int g0 = (c0 + 2 * pr - 1 + W) % W, g1 = (c0 + 2 * pr + W) % W;
+      const uint4 v0 = xb[((size_t)gr * W + g0) * (C / 8) + q];
+      const uint4 v1 = xb[((size_t)gr * W + g1) * (C / 8) + q];
+      const uint32_t a0[4] = {v0.x, v0.y, v0.z, v0.w}, a1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        // channels q*8 + 2j (low halves) and q*8 + 2j + 1 (high halves)
+        *(uint32_t*)&xT[rr][q * 8 + 2 * j][2 * pr] = (a0[j] & 0xffffu) | (a1[j] << 16);
+        *(uint32_t*)&xT[rr][q * 8 + 2 * j + 1][2 * pr] = (a0[j] >> 16) | (a1[j] & 0xffff0000u);
       }
-      for (int i = tid; i < 3 * 3 * 32 * C; i += 256) {
-        const int ci = i % C, px = (i / C) % 32, rr = (i / (C * 32)) % 3, dxi = i / (C * 32 * 3);
-        const int gr = (r + rr - 1 + H) % H, gc = (c0 + px + dxi - 1 + W) % W;
-        xT[dxi][rr][ci][px] = xb[((size_t)gr * W + gc) * C + ci];
+    }
+    // dz lines: rows r0 .. r0+WROWS-1, pixels c0 .. c0+31 as pairs
+    for (int i = tid; i < WROWS * 16 * (COUT / 8); i += 256) {
+      const int q = i % (COUT / 8), pr = (i / (COUT / 8)) % 16, rr = i / ((COUT / 8) * 16);
+      const size_t p0 = (size_t)(r0 + rr) * W + c0 + 2 * pr;
+      const uint4 v0 = dzb[p0 * (C / 8) + q];
+      const uint4 v1 = dzb[(p0 + 1) * (C / 8) + q];
+      const uint32_t a0[4] = {v0.x, v0.y, v0.z, v0.w}, a1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        *(uint32_t*)&dzT[rr][q * 8 + 2 * j][2 * pr] = (a0[j] & 0xffffu) | (a1[j] << 16);
+        *(uint32_t*)&dzT[rr][q * 8 + 2 * j + 1][2 * pr] = (a0[j] >> 16) | (a1[j] & 0xffff0000u);
       }
-      __syncthreads();
-      if (tid < COUT) {
-        float sacc = 0.f;
-        for (int px = 0; px < 32; ++px) sacc += bf2f(dzT[tid][px]);
-        dbacc += sacc;
-      }
+    }
+    __syncthreads();
+    if (tid < DBT) {
+      const int co = tid % COUT, rr = tid / COUT;
+      float sacc = 0.f;
+      for (int px = 0; px < 32; ++px) sacc += bf2f(dzT[rr][co][px]);
+      dbacc += sacc;
+    }
+#pragma unroll 1
+    for (int rr = 0; rr < WROWS; ++rr) {
+      Chunk a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) a[m].u = *(const uint4*)&dzT[rr][m * 16 + li][kb * 8];
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int t = wave + 4 * s;
         if (t < 9) {
-          const int dy = t / 3 - 1, dx = t % 3 - 1;
+          const int dy = t / 3 - 1, sh = t % 3;  // line offset (pixels) = dx + 1
 #pragma unroll
-          for (int m = 0; m < MT; ++m) {
-            Chunk a;
-            a.u = *(const uint4*)&dzT[m * 16 + li][kb * 8];
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-              Chunk bb;
-              bb.u = *(const uint4*)&xT[dx + 1][dy + 1][n * 16 + li][kb * 8];
-              acc[s][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, bb.v, acc[s][m][n], 0, 0, 0);
+          for (int n = 0; n < 2; ++n) {
+            const u16* line = &xT[rr + dy + 1][n * 16 + li][kb * 8];
+            const uint4 lo = *(const uint4*)line;
+            Chunk bb;
+            if (sh == 0) {
+              bb.u = lo;
+            } else {
+              const uint4 hi = *(const uint4*)(line + 8);
+              if (sh == 2) {
+                bb.u = uint4{lo.y, lo.z, lo.w, hi.x};
+              } else {
+                bb.u = uint4{__builtin_amdgcn_alignbyte(lo.y, lo.x, 2),
+                             __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
+                             __builtin_amdgcn_alignbyte(lo.w, lo.z, 2),
+                             __builtin_amdgcn_alignbyte(hi.x, lo.w, 2)};
+              }
             }
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+              acc[s][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m].v, bb.v, acc[s][m][n], 0,
+                                                                    0, 0);
           }
         }
       }
@@ -214,16 +260,44 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(int H, int W, const u16* __r
           }
     }
   }
-  if (tid < COUT) pw[9 * COUT * C + tid] = dbacc;
+  dbs[tid] = (tid < DBT) ? dbacc : 0.f;
+  __syncthreads();
+  if (tid < COUT) {
+    float sdb = 0.f;
+    for (int rr = 0; rr < WROWS; ++rr) sdb += dbs[rr * COUT + tid];
+    pw[9 * COUT * C + tid] = sdb;
+  }
 }
 
-// fixed-order sum of the per-workgroup partials
+// fixed-order sum of nparts partial vectors (one thread per element)
 __global__ void k_reduce_parts(int nparts, int len, const float* __restrict__ part,
                                float* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
   float s = 0.f;
   for (int k = 0; k < nparts; ++k) s += part[(size_t)k * len + i];
+  out[i] = s;
+}
+
+// fixed-order sum of the per-workgroup partials, in two stages: RG groups of
+// consecutive partials, then the groups in order
+constexpr int RG = 16;
+__global__ void k_reduce_stage1(int nparts, int len, const float* __restrict__ part,
+                                float* __restrict__ tmp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (i >= len) return;
+  const int per = (nparts + RG - 1) / RG;
+  const int k0 = g * per, k1 = min(nparts, k0 + per);
+  float s = 0.f;
+  for (int k = k0; k < k1; ++k) s += part[(size_t)k * len + i];
+  tmp[(size_t)g * len + i] = s;
+}
+__global__ void k_reduce_stage2(int len, const float* __restrict__ tmp, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.f;
+  for (int g = 0; g < RG; ++g) s += tmp[(size_t)g * len + i];
   out[i] = s;
 }
 
@@ -277,23 +351,26 @@ __global__ void k_to_bf16(int n, const float* __restrict__ p, u16* __restrict__ 
   if (i < n) pb[i] = f2bf(p[i]);
 }
 
-// Features of one sample: d = (u^n - u^{n-1}) k_{n+1}/k_n, s = RMS(d),
-// x = [u^n, d/s, (log10 k_{n+1} + 3)/2, 0...] as bf16, and the target
-// (u^{n+1} - u^n - d)/s when u^{n+1} is given.  One workgroup per sample
-// computes s deterministically first.
-__global__ __launch_bounds__(256) void k_features(int HW, const double* __restrict__ un,
-                                                  const double* __restrict__ um,
-                                                  const double* __restrict__ unp1,
-                                                  const double* __restrict__ kk, u16* __restrict__ x,
-                                                  float* __restrict__ tgt,
-                                                  double* __restrict__ scale) {
+// Features of B samples, over the whole grid: d = (u^n - u^{n-1}) k_{n+1}/k_n,
+// s = RMS(d), x = [u^n, d/s, (log10 k_{n+1} + 3)/2, 0...] as bf16, and the
+// target (u^{n+1} - u^n - d)/s when u^{n+1} is given.  First kernel: partial
+// sums of d^2 over FEAT_BLK chunks of each sample; second: every block forms
+// s from its sample's partials in the same order (block 0 records it) and
+// writes its chunk.
+constexpr int FEAT_BLK = 64;
+__global__ __launch_bounds__(256) void k_feat_part(int HW, const double* __restrict__ un,
+                                                   const double* __restrict__ um,
+                                                   const double* __restrict__ kk,
+                                                   double* __restrict__ work) {
   __shared__ double red[256];
-  const int b = blockIdx.x;
+  const int b = blockIdx.y;
   const double r = kk[2 * b] / kk[2 * b + 1];
   const double* a = un + (size_t)b * HW;
   const double* p = um + (size_t)b * HW;
+  const int chunk = (HW + FEAT_BLK - 1) / FEAT_BLK;
+  const int lo = blockIdx.x * chunk, hi = min(HW, lo + chunk);
   double s2 = 0.0;
-  for (int i = threadIdx.x; i < HW; i += 256) {
+  for (int i = lo + threadIdx.x; i < hi; i += 256) {
     const double d = (a[i] - p[i]) * r;
     s2 += d * d;
   }
@@ -303,23 +380,45 @@ __global__ __launch_bounds__(256) void k_features(int HW, const double* __restri
     if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  double s = sqrt(red[0] / HW);
-  if (!(s > 1e-300)) s = 1e-300;
-  if (threadIdx.x == 0) scale[b] = s;
+  if (threadIdx.x == 0) work[b * FEAT_BLK + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_feat_write(int HW, const double* __restrict__ un,
+                                                    const double* __restrict__ um,
+                                                    const double* __restrict__ unp1,
+                                                    const double* __restrict__ kk,
+                                                    const double* __restrict__ work,
+                                                    u16* __restrict__ x, float* __restrict__ tgt,
+                                                    double* __restrict__ scale) {
+  __shared__ double sh;
+  const int b = blockIdx.y;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < FEAT_BLK; ++i) t += work[b * FEAT_BLK + i];
+    double s = sqrt(t / HW);
+    if (!(s > 1e-300)) s = 1e-300;
+    sh = s;
+    if (blockIdx.x == 0) scale[b] = s;
+  }
+  __syncthreads();
+  const double s = sh;
+  const double r = kk[2 * b] / kk[2 * b + 1];
   const float lk = (float)((log10(kk[2 * b]) + 3.0) * 0.5);
   const u16 lkb = f2bf(lk);
-  for (int i = threadIdx.x; i < HW; i += 256) {
-    const double d = (a[i] - p[i]) * r;
-    uint4* row = (uint4*)(x + ((size_t)b * HW + i) * C);
+  const size_t base = (size_t)b * HW;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < HW; i += gridDim.x * 256) {
+    const double a = un[base + i];
+    const double d = (a - um[base + i]) * r;
+    uint4* row = (uint4*)(x + (base + i) * C);
     uint4 first = {0, 0, 0, 0};
-    first.x = (uint32_t)f2bf((float)a[i]) | ((uint32_t)f2bf((float)(d / s)) << 16);
+    first.x = (uint32_t)f2bf((float)a) | ((uint32_t)f2bf((float)(d / s)) << 16);
     first.y = lkb;
     const uint4 zero = {0, 0, 0, 0};
     row[0] = first;
     row[1] = zero;
     row[2] = zero;
     row[3] = zero;
-    if (unp1 && tgt) tgt[(size_t)b * HW + i] = (float)((unp1[(size_t)b * HW + i] - a[i] - d) / s);
+    if (unp1 && tgt) tgt[base + i] = (float)((unp1[base + i] - a - d) / s);
   }
 }
 
@@ -377,12 +476,13 @@ fch_status fch_nn_conv_bwd_data(int32_t B, int32_t H, int32_t W, int32_t cout, c
 }
 
 size_t fch_nn_bwd_w_scratch_floats(int32_t B, int32_t H, int32_t W) {
-  return (size_t)B * (H / WROWS) * (9 * C * C + C);
+  // per-workgroup partials, then the RG group sums of the reduction
+  return (size_t)(B * (H / WROWS) + RG) * (9 * C * C + C);
 }
 
 fch_status fch_nn_conv_bwd_w(int32_t B, int32_t H, int32_t W, int32_t cout, const void* dz,
                              const void* x, float* dw_db, float* scratch, void* stream) {
-  if (!ok_dims(B, H, W) || !dz || !x || !dw_db || !scratch) return FCH_E_INVALID;
+  if (!ok_dims(B, H, W) || H % WROWS || !dz || !x || !dw_db || !scratch) return FCH_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   const int nwg = B * (H / WROWS);
   const int len = 9 * cout * C + cout;
@@ -395,8 +495,10 @@ fch_status fch_nn_conv_bwd_w(int32_t B, int32_t H, int32_t W, int32_t cout, cons
   } else {
     return FCH_E_INVALID;
   }
-  hipLaunchKernelGGL(k_reduce_parts, dim3((len + 255) / 256), dim3(256), 0, s, nwg, len, scratch,
-                     dw_db);
+  float* tmp = scratch + (size_t)nwg * len;
+  hipLaunchKernelGGL(k_reduce_stage1, dim3((len + 255) / 256, RG), dim3(256), 0, s, nwg, len,
+                     scratch, tmp);
+  hipLaunchKernelGGL(k_reduce_stage2, dim3((len + 255) / 256), dim3(256), 0, s, len, tmp, dw_db);
   return hipGetLastError() == hipSuccess ? FCH_OK : FCH_E_HIP;
 }
 
@@ -432,12 +534,17 @@ fch_status fch_nn_to_bf16(int32_t n, const float* p, void* p_bf16, void* stream)
   return hipGetLastError() == hipSuccess ? FCH_OK : FCH_E_HIP;
 }
 
+int32_t fch_nn_features_work_doubles(int32_t B) { return B > 0 ? B * FEAT_BLK : 0; }
+
 fch_status fch_nn_features(int32_t B, int32_t H, int32_t W, const double* u_n, const double* u_nm1,
                            const double* u_np1, const double* k, void* x, float* target,
-                           double* scale, void* stream) {
-  if (!ok_dims(B, H, W) || !u_n || !u_nm1 || !k || !x || !scale) return FCH_E_INVALID;
-  hipLaunchKernelGGL(k_features, dim3(B), dim3(256), 0, (hipStream_t)stream, H * W, u_n, u_nm1,
-                     u_np1, k, (u16*)x, target, scale);
+                           double* scale, double* work, void* stream) {
+  if (!ok_dims(B, H, W) || !u_n || !u_nm1 || !k || !x || !scale || !work) return FCH_E_INVALID;
+  const hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_feat_part, dim3(FEAT_BLK, B), dim3(256), 0, st, H * W, u_n, u_nm1, k, work);
+  const int nblk = (H * W + 255) / 256 < 128 ? (H * W + 255) / 256 : 128;
+  hipLaunchKernelGGL(k_feat_write, dim3(nblk, B), dim3(256), 0, st, H * W, u_n, u_nm1, u_np1, k,
+                     work, (u16*)x, target, scale);
   return hipGetLastError() == hipSuccess ? FCH_OK : FCH_E_HIP;
 }
 

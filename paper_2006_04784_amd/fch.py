@@ -156,7 +156,8 @@ _SIGS = {
     "fch_nn_mse": (_I, [_I, _V, _V, _V, _V, _I, _V]),
     "fch_nn_adam": (_I, [_I, _V, _V, _V, _V, _V, _D, _D, _D, _D, _I, _V]),
     "fch_nn_to_bf16": (_I, [_I, _V, _V, _V]),
-    "fch_nn_features": (_I, [_I, _I, _I, _V, _V, _V, _V, _V, _V, _V, _V]),
+    "fch_nn_features_work_doubles": (_I, [_I]),
+    "fch_nn_features": (_I, [_I, _I, _I, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
     "fch_nn_guess": (_I, [_I, _I, _I, _V, _V, _V, _V, _V, _V, _V]),
     "fch_nn_reduce": (_I, [_I, _I, _V, _V, _V]),
     "fch_status_string": (C.c_char_p, [_I]),

@@ -59,6 +59,8 @@ class WarmStartNet:
         self.target = torch.zeros((batch, H, W), **f32)
         self.scale = torch.zeros(batch, dtype=torch.float64, device=self.dev)
         self.kk = torch.zeros((batch, 2), dtype=torch.float64, device=self.dev)
+        self.fwork = torch.zeros(int(fch.lib().fch_nn_features_work_doubles(batch)),
+                                 dtype=torch.float64, device=self.dev)
         L = fch.lib()
         self.scratch = torch.zeros(int(L.fch_nn_bwd_w_scratch_floats(batch, H, W)), **f32)
         self.nblocks = 256
@@ -167,7 +169,7 @@ class WarmStartNet:
         _chk(fch.lib().fch_nn_features(nb, self.H, self.W, _p(u_n), _p(u_nm1), _p(u_np1),
                                        _p(self.kk), _p(self.x),
                                        _p(self.target) if u_np1 is not None else None,
-                                       _p(self.scale), self._stream()))
+                                       _p(self.scale), _p(self.fwork), self._stream()))
         return nb
 
     def guess(self, u_n, u_nm1, k, out=None):
