@@ -27,10 +27,14 @@ def c5_initial(seed):
                                     r_range=(0.5, 1.5))
 
 
-def psd_trajectory(plan, u0, nsteps, sigma_tol=1e-5, k_max=0.05, tol=1e-10, k_first=1e-6):
+def psd_trajectory(plan, u0, nsteps, sigma_tol=1e-5, k_max=0.05, tol=1e-10, k_first=1e-6,
+                   max_iter=2000):
     """Adaptive BDF2-PSD run (Sec. 3.2 step control, Sec. 3.3 solver) from the
     physical state u0 (numpy).  Returns the accepted physical states
-    (torch float64, (nsteps+1, N, N)) and step sizes (numpy, k[i] = t_i - t_{i-1})."""
+    (torch float64, (nsteps+1, N, N)) and step sizes (numpy, k[i] = t_i - t_{i-1}).
+    A solve that does not reach the tolerance within max_iter iterations (at
+    the largest steps of this stiff workload) counts as a rejected attempt
+    and halves the trial step."""
     dev = plan.device
     opts = fch.AdaptOpts(sigma_tol=sigma_tol, k_max=k_max)
     cur = plan.forward(torch.from_numpy(u0).to(dev))
@@ -44,7 +48,11 @@ def psd_trajectory(plan, u0, nsteps, sigma_tol=1e-5, k_max=0.05, tol=1e-10, k_fi
     attempts = 0
     while len(states) <= nsteps and attempts < 20 * nsteps:
         attempts += 1
-        trial, _ = plan.step_psd(cur, prev, kt, kn, tol=tol)
+        trial, st = plan.step_psd(cur, prev, kt, kn, tol=tol, max_iter=max_iter,
+                                  raise_noconv=False)
+        if st["status"] == fch.FCH_E_NOCONV:
+            kt *= 0.5
+            continue
         Ft, acc, knext, err = plan.adapt_dt(trial, cur, Fn, Fm, kt, kn, opts)
         if acc:
             prev, cur = cur, trial
@@ -108,13 +116,14 @@ def evaluate(plan, net: WarmStartNet, trajs, tol=1e-10):
             uhm = plan.forward(S[n - 1].contiguous())
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sol_plain, st_plain = plan.step_psd(uhn, uhm, k1, k0, tol=tol)
+            sol_plain, st_plain = plan.step_psd(uhn, uhm, k1, k0, tol=tol, max_iter=4000)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             k = torch.tensor([[k1, k0]], dtype=torch.float64, device=dev)
             g = net.guess(S[n:n + 1].contiguous(), S[n - 1:n].contiguous(), k)
             gh = plan.forward(g[0].contiguous())
-            sol_learn, st_learn = plan.step_psd(uhn, uhm, k1, k0, guess=gh, tol=tol)
+            sol_learn, st_learn = plan.step_psd(uhn, uhm, k1, k0, guess=gh, tol=tol,
+                                                max_iter=4000)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             diff = float(torch.linalg.norm(sol_learn - sol_plain) / torch.linalg.norm(sol_plain))
@@ -135,8 +144,13 @@ def run_experiment(train_seeds, test_seeds, nsteps=60, epochs=20, batch=16, lr=1
     kw = c5_model()
     plan = fch.Plan(**kw, device=device)
     t0 = time.perf_counter()
-    tr = [psd_trajectory(plan, c5_initial(s), nsteps, tol=tol) for s in train_seeds]
-    te = [psd_trajectory(plan, c5_initial(s), nsteps, tol=tol) for s in test_seeds]
+    tr, te = [], []
+    for dst, seeds in ((tr, train_seeds), (te, test_seeds)):
+        for s in seeds:
+            dst.append(psd_trajectory(plan, c5_initial(s), nsteps, tol=tol))
+            if log:
+                log("trajectory seed %d: %d steps to t = %.3f" % (s, dst[-1][0].shape[0] - 1,
+                                                                  float(dst[-1][1].sum())))
     t_gen = time.perf_counter() - t0
     if log:
         log("generated %d + %d trajectories in %.1fs" % (len(tr), len(te), t_gen))
