@@ -196,6 +196,32 @@ def main():
         extra["psd_iterations_per_s"] = round(info["psd_iters"] / el, 1)
         extra["psd_fft_calls_per_step"] = round(4.0 * info["psd_iters"] / npsd, 2)
         extra["psd_steps_per_s"] = round(npsd / el, 1)
+        # c3: 2048^2 adaptive BDF2-PSD (i_tol 1e-10, LTE target 1e-6, k_max 0.05), the
+        # first 100 accepted steps after the startup step
+        log("c3: 2048^2 adaptive BDF2-PSD, 100 accepted steps")
+        kw3, u3 = inputs.workload("c3")
+        plan3 = fch.Plan(**kw3, device=dev)
+        a3 = plan3.forward(torch.from_numpy(u3).to(dev))
+        b3 = torch.empty_like(a3)
+        plan3.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info3 = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
+                          nsteps=101, k_first=1e-6,
+                          adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
+        torch.cuda.synchronize()
+        el3 = time.perf_counter() - t0
+        S3 = spec_bytes(kw3["N"])
+        acc3 = info3["accepted"]
+        extra["c3_psd_adaptive_2048"] = {
+            "accepted_steps": acc3, "rejected": info3["rejected"], "t": round(info3["t"], 6),
+            "psd_iters_per_step": round(info3["psd_iters"] / acc3, 2),
+            "psd_fft_calls_per_step": round(4.0 * info3["psd_iters"] / acc3, 2),
+            "total_fft_calls_per_step": round(info3["fft_calls"] / acc3, 2),
+            "ms_per_step": round(1e3 * el3 / acc3, 3),
+            "psd_iteration_GBps": round(11 * S3 * info3["psd_iters"] / el3 / 1e9, 1),
+            "bytes_per_psd_iteration": 11 * S3}
+        del plan3, a3, b3
         # 2D FFT bandwidth, streaming regime: R2C then C2R over a 32-field batch
         # (269 MB physical + 269 MB spectral + 269 MB staging, beyond the 256 MB
         # Infinity Cache), batched launches; and one field (cache-resident)
