@@ -643,3 +643,60 @@ def test_batch_limits(F, orc):
                                      C.c_void_p(Uh.data_ptr())) == F.FCH_E_INVALID
     assert lib.fch_inverse_batch_ws_bytes(plan.h, 0) == 0
     assert lib.fch_inverse_batch_ws_bytes(plan.h, 3) == 3 * 16 * 9 * 16
+
+
+def test_c2_adaptive_imex_and_sav_512(F, orc):
+    """The 512^2 workload (eps 0.05, six perturbed bilayers): adaptive
+    BDF2-IMEX and BDF2-SAV driven by the library (fch_step_*, fch_adapt_dt)
+    for 40 accepted steps; the oracle replays the accepted step sizes and the
+    states agree within the trajectory tolerance."""
+    kw, u0 = inputs.workload("c2")
+    kw = dict(kw, zeta=1.1, D0=kw["L"] ** 2 * 1.05)
+    plan, m = pair(F, orc, **kw)
+    uh0 = orc.r2c(u0)
+    opts = F.AdaptOpts(sigma_tol=1e-5)
+    k1 = 1e-6
+    for scheme in ("imex", "sav"):
+        log("c2 adaptive %s 512^2" % scheme)
+        a0 = dev(uh0)
+        r0 = plan.sav_r(a0) if scheme == "sav" else 0.0
+        if scheme == "imex":
+            cur = plan.step_imex(a0, None, k1, -1.0)
+        else:
+            cur, r1 = plan.step_sav(a0, None, r0, r0, k1, -1.0)
+        prev = a0
+        rs = (r1, r0) if scheme == "sav" else None
+        Fn, Fm = plan.rhs(cur), plan.rhs(prev)
+        kn, kt = k1, k1
+        sched = [k1]
+        while len(sched) < 41:
+            if scheme == "imex":
+                trial = plan.step_imex(cur, prev, kt, kn)
+            else:
+                trial, rt = plan.step_sav(cur, prev, rs[0], rs[1], kt, kn)
+            Ft, acc, knext, e = plan.adapt_dt(trial, cur, Fn, Fm, kt, kn, opts)
+            if acc:
+                prev, cur = cur, trial
+                Fm, Fn = Fn, Ft
+                kn = kt
+                sched.append(kt)
+                if scheme == "sav":
+                    rs = (rt, rs[0])
+            kt = knext
+        assert sched[-1] > 3 * k1
+        # oracle replay of the accepted schedule
+        if scheme == "imex":
+            o_prev, o_cur = uh0, orc.imex_step(m, uh0, None, sched[0], -1.0)
+            for i in range(1, len(sched)):
+                o_prev, o_cur = o_cur, orc.imex_step(m, o_cur, o_prev, sched[i], sched[i - 1])
+        else:
+            ro = np.sqrt(orc.E1(m, uh0) + kw["D0"])
+            assert abs(ro - r0) < 1e-12 * ro
+            o_prev = uh0
+            o_cur, rc = orc.sav_step(m, uh0, None, ro, ro, sched[0], -1.0)
+            ro_prev = ro
+            for i in range(1, len(sched)):
+                nxt, rn = orc.sav_step(m, o_cur, o_prev, rc, ro_prev, sched[i], sched[i - 1])
+                o_prev, o_cur, ro_prev, rc = o_cur, nxt, rc, rn
+            assert abs(rc - rs[0]) < 1e-9 * abs(rc)
+        assert rel(host(cur), o_cur) < 1e-8, scheme
