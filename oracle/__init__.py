@@ -111,6 +111,9 @@ def _load():
         "oracle_adapt_decide": (None, [C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, C.c_double,
                                        C.POINTER(C.c_int), _D]),
+        "oracle_etd_phi": (None, [C.c_double, _D, _D, _D]),
+        "oracle_etd_step": (C.c_int, [_P, _D, C.c_double, C.c_double, C.c_double, _D, _D, _D,
+                                      _D]),
         "nn_bf16": (C.c_double, [C.c_double]),
         "nn_conv_fwd": (None, [C.c_int, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D, _D, _D,
                                C.c_int]),
@@ -342,11 +345,39 @@ def adapt_decide(e, k_trial, sigma_tol, k_min, k_max, rho_s=0.9, cap=1.0 + 2.0 *
     return bool(acc.value), kn.value
 
 
+# the constants of eq. ETD-L used for every simulation of Sec. 3.6
+KAPPA0, KAPPA2 = 1e-2, 15.0
+
+
+def etd_phi(z):
+    """(e^z, (e^z - 1)/z, (e^z - 1 - z)/z^2) at a real z."""
+    p0, p1, p2 = C.c_double(), C.c_double(), C.c_double()
+    _load().oracle_etd_phi(float(z), C.byref(p0), C.byref(p1), C.byref(p2))
+    return p0.value, p1.value, p2.value
+
+
+def etd_step(m: Model, uh_n, k, kappa0=KAPPA0, kappa2=KAPPA2, fh_n=None, fh_np1=None,
+             want_stage=False):
+    """One ETDRK2 step (eqs. ETDRK1, ETDRK2, ETD-L); returns u^{n+1} (and the
+    ETDRK1 stage u~ if want_stage)."""
+    un = _cplx(uh_n)
+    f0, f1 = _opt(fh_n), _opt(fh_np1)
+    out = np.empty_like(un)
+    st = np.empty_like(un)
+    rc = _load().oracle_etd_step(C.byref(m.c()), _ptr(un.view(np.float64)), k, kappa0, kappa2,
+                                 None if f0 is None else _ptr(f0.view(np.float64)),
+                                 None if f1 is None else _ptr(f1.view(np.float64)),
+                                 _ptr(out.view(np.float64)), _ptr(st.view(np.float64)))
+    if rc:
+        raise ValueError("ETD: k must be positive")
+    return (out, st) if want_stage else out
+
+
 # ---- drivers (plain loops over the steppers above) ------------------------
 def run_fixed(m: Model, scheme: str, uh0, k: float, nsteps: int, r0=None, psd_tol=1e-10,
               psd_iters=None, record=False):
     """Fixed-step trajectory: a first-order startup step from u^0, then BDF2
-    steps of size k.  ``psd_iters`` (list) replays a per-step PSD iteration
+    steps of size k (ETDRK2, a one-step method, takes nsteps equal steps).  ``psd_iters`` (list) replays a per-step PSD iteration
     count.  Returns the final spectrum (and the list of states if record)."""
     un = _cplx(uh0)
     um = None
@@ -363,6 +394,8 @@ def run_fixed(m: Model, scheme: str, uh0, k: float, nsteps: int, r0=None, psd_to
         elif scheme == "sav":
             new, r_new = sav_step(m, un, um, r_n, r_nm1, k, k_n)
             r_nm1, r_n = r_n, r_new
+        elif scheme == "etd":  # one-step method: no startup step
+            new = etd_step(m, un, k)
         elif scheme == "psd":
             fi = psd_iters[n] if psd_iters is not None else 0
             new, it, _, rc = psd_step(m, un, um, k, k_n, tol=psd_tol, fixed_iters=fi)

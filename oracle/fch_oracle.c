@@ -457,29 +457,18 @@ static void extrapolate(const oracle_params* P, const cplx* un, const cplx* um,
     for (size_t i = 0; i < m; ++i) ustar[i] = (g == 0.0) ? un[i] : un[i] + g * (un[i] - um[i]);
 }
 
-/* BDF2-IMEX (eqs. IMEX, IMEX-eq) with the nonlinearity N_IMEX written out
- * term by term:
+/* The IMEX nonlinearity N_IMEX = mu - L_IMEX u (eqs. e:IMEX-op, IMEX) as a half
+ * spectrum, written out term by term:
  *   N = eps^2 (alpha - W'') Lap u + eps^2 Lap(alpha u - W') + W'' W'
- *       - alpha^2 u + eps^2 eta1 Lap u - eta2 W'
- * and (a - Lap L_IMEX) u^{n+1} = -b u^n - c u^{n-1} + Lap N(u*). */
-int oracle_imex_step(const oracle_params* P, const double* uh_n_, const double* uh_nm1_,
-                     double k_np1, double k_n, const double* fh_, double* uh_np1_) {
+ *       - alpha^2 u + eps^2 eta1 Lap u - eta2 W' */
+static void imex_nonlin(const oracle_params* P, const cplx* uh, cplx* Nh) {
     int N = P->N, H = N / 2 + 1;
     size_t n = nphys(P), m = nspec(P);
-    const cplx* un = (const cplx*)uh_n_;
-    const cplx* um = (const cplx*)uh_nm1_;
-    const cplx* fh = (const cplx*)fh_;
-    cplx* out = (cplx*)uh_np1_;
-    double a, b, c;
-    oracle_bdf2_coef(k_np1, k_n, &a, &b, &c);
     double al = oracle_alpha_m(P);
     double e2 = P->eps * P->eps, eta1 = eff_eta(P, P->eta1), eta2 = eff_eta(P, P->eta2);
-
-    cplx* us = malloc(m * sizeof(cplx));
-    extrapolate(P, un, um, k_np1, k_n, us);
     fields_t f;
     fields_alloc(P, &f);
-    fields_eval(P, (const double*)us, &f);
+    fields_eval(P, (const double*)uh, &f);
     double* t1 = malloc(n * sizeof(double));
     double* t2 = malloc(n * sizeof(double));
     for (size_t i = 0; i < n; ++i) {
@@ -491,20 +480,46 @@ int oracle_imex_step(const oracle_params* P, const double* uh_n_, const double* 
     cplx* T2 = malloc(m * sizeof(cplx));
     oracle_r2c(N, t1, (double*)T1, method_for(N));
     oracle_r2c(N, t2, (double*)T2, method_for(N));
+    for (int ky = 0; ky < N; ++ky)
+        for (int kx = 0; kx < H; ++kx) {
+            size_t i = (size_t)ky * H + kx;
+            Nh[i] = T1[i] - k2_at(P, ky, kx) * e2 * T2[i];
+        }
+    free(T1); free(T2); free(t1); free(t2);
+    fields_free(&f);
+}
+
+/* BDF2-IMEX (eqs. IMEX, IMEX-eq):
+ * (a - Lap L_IMEX) u^{n+1} = -b u^n - c u^{n-1} + Lap N_IMEX(u*). */
+int oracle_imex_step(const oracle_params* P, const double* uh_n_, const double* uh_nm1_,
+                     double k_np1, double k_n, const double* fh_, double* uh_np1_) {
+    int N = P->N, H = N / 2 + 1;
+    size_t m = nspec(P);
+    const cplx* un = (const cplx*)uh_n_;
+    const cplx* um = (const cplx*)uh_nm1_;
+    const cplx* fh = (const cplx*)fh_;
+    cplx* out = (cplx*)uh_np1_;
+    double a, b, c;
+    oracle_bdf2_coef(k_np1, k_n, &a, &b, &c);
+    double al = oracle_alpha_m(P);
+    double e2 = P->eps * P->eps;
+
+    cplx* us = malloc(m * sizeof(cplx));
+    extrapolate(P, un, um, k_np1, k_n, us);
+    cplx* Nh = malloc(m * sizeof(cplx));
+    imex_nonlin(P, us, Nh);
     cplx* tmp = malloc(m * sizeof(cplx));
     for (int ky = 0; ky < N; ++ky)
         for (int kx = 0; kx < H; ++kx) {
             size_t i = (size_t)ky * H + kx;
             double k2 = k2_at(P, ky, kx);
-            cplx Nh = T1[i] - k2 * e2 * T2[i];
             double Lh = e2 * e2 * k2 * k2 + 2.0 * al * e2 * k2 + al * al;
-            cplx rhs = -b * un[i] - (c != 0.0 ? c * um[i] : 0.0) - k2 * Nh;
+            cplx rhs = -b * un[i] - (c != 0.0 ? c * um[i] : 0.0) - k2 * Nh[i];
             if (fh) rhs += fh[i];
             tmp[i] = rhs / (a + k2 * Lh);
         }
     memcpy(out, tmp, m * sizeof(cplx));
-    free(tmp); free(T1); free(T2); free(t1); free(t2); free(us);
-    fields_free(&f);
+    free(tmp); free(Nh); free(us);
     return 0;
 }
 
@@ -692,4 +707,95 @@ void oracle_adapt_decide(double e, double k_trial, double sigma_tol, double k_mi
     if (kn < k_min) kn = k_min;
     *accept = (e <= sigma_tol) || (k_trial <= k_min);
     *k_next = kn;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ETDRK2 (Sec. 3.6)                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* phi0 = e^z, phi1 = (e^z - 1)/z, phi2 = (e^z - 1 - z)/z^2: the multipliers
+ * of eqs. ETDRK1 and ETDRK2 at z = L k, since L^{-1}(e^{Lk} - I) = k phi1 and
+ * L^{-1}[L^{-1}(e^{Lk} - I) - k I] / k = k phi2.  Both quotients cancel near
+ * z = 0, so for |z| < 1 they are summed from their Taylor series
+ * phi_j(z) = sum_m z^m / (m + j)!; elsewhere phi1 comes from exp and
+ * phi2 = (phi1 - 1)/z. */
+void oracle_etd_phi(double z, double* phi0, double* phi1, double* phi2) {
+    *phi0 = exp(z);
+    if (fabs(z) < 1.0) {
+        double t1 = 1.0, t2 = 0.5, s1 = 0.0, s2 = 0.0;
+        for (int m = 0; m < 40; ++m) {
+            s1 += t1;
+            s2 += t2;
+            t1 *= z / (double)(m + 2);
+            t2 *= z / (double)(m + 3);
+        }
+        *phi1 = s1;
+        *phi2 = s2;
+    } else {
+        *phi1 = (exp(z) - 1.0) / z;
+        *phi2 = (*phi1 - 1.0) / z;
+    }
+}
+
+/* the linear operator of eq. ETD-L at |k|^2 = k2 (Lap -> -k2):
+ * Lap (eps^4 Lap^2 - 2 alpha eps^2 Lap + alpha^2) - kappa0 + kappa2 eps^2 Lap */
+static double etd_L(const oracle_params* P, double k2, double kappa0, double kappa2) {
+    double e2 = P->eps * P->eps, al = oracle_alpha_m(P);
+    return -k2 * (e2 * e2 * k2 * k2 + 2.0 * al * e2 * k2 + al * al) - kappa0 - kappa2 * e2 * k2;
+}
+
+/* the nonlinearity of eq. ETD-L, N(u) = Lap N_IMEX(u) + kappa0 u - kappa2 eps^2 Lap u,
+ * plus the forcing fh (nullable) */
+static void etd_N(const oracle_params* P, const cplx* uh, double kappa0, double kappa2,
+                  const cplx* fh, cplx* out) {
+    int N = P->N, H = N / 2 + 1;
+    size_t m = nspec(P);
+    double e2 = P->eps * P->eps;
+    cplx* Ni = malloc(m * sizeof(cplx));
+    imex_nonlin(P, uh, Ni);
+    for (int ky = 0; ky < N; ++ky)
+        for (int kx = 0; kx < H; ++kx) {
+            size_t i = (size_t)ky * H + kx;
+            double k2 = k2_at(P, ky, kx);
+            out[i] = -k2 * Ni[i] + kappa0 * uh[i] + kappa2 * e2 * k2 * uh[i];
+            if (fh) out[i] += fh[i];
+        }
+    free(Ni);
+}
+
+/* One ETDRK2 step of size k (eq. ETDRK2) with the split of eq. ETD-L:
+ *   u~      = e^{Lk} u^n + L^{-1}(e^{Lk} - I) N(u^n)            (eq. ETDRK1)
+ *   u^{n+1} = u~ + L^{-1}[L^{-1}(e^{Lk} - I) - k I] (N(u~) - N(u^n)) / k
+ * fh_n, fh_np1 (nullable): a forcing at t^n and t^{n+1}, treated as part of
+ * N (manufactured solutions only).  uh_stage (nullable out): u~. */
+int oracle_etd_step(const oracle_params* P, const double* uh_n_, double k, double kappa0,
+                    double kappa2, const double* fh_n, const double* fh_np1, double* uh_np1_,
+                    double* uh_stage_) {
+    if (!(k > 0.0)) return -1;
+    int N = P->N, H = N / 2 + 1;
+    size_t m = nspec(P);
+    const cplx* un = (const cplx*)uh_n_;
+    cplx* Nn = malloc(m * sizeof(cplx));
+    cplx* Nt = malloc(m * sizeof(cplx));
+    cplx* ut = malloc(m * sizeof(cplx));
+    etd_N(P, un, kappa0, kappa2, (const cplx*)fh_n, Nn);
+    for (int ky = 0; ky < N; ++ky)
+        for (int kx = 0; kx < H; ++kx) {
+            size_t i = (size_t)ky * H + kx;
+            double p0, p1, p2;
+            oracle_etd_phi(etd_L(P, k2_at(P, ky, kx), kappa0, kappa2) * k, &p0, &p1, &p2);
+            ut[i] = p0 * un[i] + k * p1 * Nn[i];
+        }
+    etd_N(P, ut, kappa0, kappa2, (const cplx*)fh_np1, Nt);
+    cplx* out = (cplx*)uh_np1_;
+    for (int ky = 0; ky < N; ++ky)
+        for (int kx = 0; kx < H; ++kx) {
+            size_t i = (size_t)ky * H + kx;
+            double p0, p1, p2;
+            oracle_etd_phi(etd_L(P, k2_at(P, ky, kx), kappa0, kappa2) * k, &p0, &p1, &p2);
+            out[i] = ut[i] + k * p2 * (Nt[i] - Nn[i]);
+        }
+    if (uh_stage_) memcpy(uh_stage_, ut, m * sizeof(cplx));
+    free(Nn); free(Nt); free(ut);
+    return 0;
 }

@@ -19,7 +19,8 @@
  *   H^{-1} gradient flow (eqs. sFCH, FCH), BDF2 coefficients (eq. BDF2Coef),
  *   AM3 predictor (eq. Predictor), the PSD residual and preconditioner
  *   (eq. residual, Sec. 3.3), the IMEX split (eqs. e:IMEX-op, IMEX-eq) and the
- *   SAV scheme (eqs. 4.1-4.8).
+ *   SAV scheme (eqs. 4.1-4.8), and the ETDRK2 scheme (Sec. 3.6, eqs.
+ *   ETDRK1, ETDRK2, ETD-L).
  */
 #ifndef FCH_ORACLE_H
 #define FCH_ORACLE_H
@@ -98,6 +99,15 @@ int oracle_psd_step(const oracle_params* P, const double* uh_n, const double* uh
                     double tol, int max_iter, double lambda, int fixed_iters,
                     double* uh_np1, int* iters, double* last_ratio);
 double oracle_lambda_table(double q, double k);     /* <0 if q not tabulated */
+
+/* ETDRK2 (Sec. 3.6, eqs. ETDRK1, ETDRK2, ETD-L).  phi0 = e^z,
+ * phi1 = (e^z - 1)/z, phi2 = (e^z - 1 - z)/z^2 (the limits 1, 1/2 at z = 0). */
+void oracle_etd_phi(double z, double* phi0, double* phi1, double* phi2);
+/* one step of size k; fh_n, fh_np1 nullable forcing at t^n, t^{n+1};
+ * uh_stage nullable out (the ETDRK1 stage u~).  Returns -1 for k <= 0. */
+int oracle_etd_step(const oracle_params* P, const double* uh_n, double k, double kappa0,
+                    double kappa2, const double* fh_n, const double* fh_np1, double* uh_np1,
+                    double* uh_stage);
 
 /* AM3 local error estimate e = ||u~ - u_p|| / ||u_p|| (physical L2 norms) */
 double oracle_am3_error(const oracle_params* P, const double* uh_trial, const double* uh_n,
