@@ -215,6 +215,24 @@ fch_status fch_step_psd(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* u
                         double k_np1, double k_n, const fch_c128* guess,
                         const fch_psd_opts* opts, fch_c128* uh_np1, fch_psd_stats* stats);
 
+/* ---- ETDRK2 (Sec. 3.6, eqs. ODE, ETDRK1, ETDRK2, ETD-L) ------------------- */
+/* u_t = L u + N(u) with the split of eq. ETD-L,
+ *   L = Lap (eps^4 Lap^2 - 2 alpha eps^2 Lap + alpha^2) - kappa0 + kappa2 eps^2 Lap,
+ *   N(u) = Lap N_IMEX(u) + kappa0 u - kappa2 eps^2 Lap u   (so L u + N(u) = Lap mu),
+ * and one step of size k:
+ *   u~      = e^{Lk} u^n + L^{-1}(e^{Lk} - I) N(u^n)                (eq. ETDRK1)
+ *   u^{n+1} = u~ + L^{-1}[L^{-1}(e^{Lk} - I) - k I](N(u~) - N(u^n))/k (eq. ETDRK2).
+ * L is diagonal in Fourier space and never positive; the multipliers are
+ * formed per wavenumber at z = L k as e^z, k (e^z - 1)/z, k (e^z - 1 - z)/z^2
+ * (a Taylor polynomial for |z| <= 1/2).  opts: kappa0, kappa2 >= 0; NULL
+ * selects the paper's 1e-2 and 15.  F_n (nullable): F(u^n) = Lap mu(u^n) as
+ * written by fch_rhs or fch_adapt_dt; with it the step evaluates the chemical
+ * potential once (4 FFT calls), without it twice (8).  uh_np1 may alias uh_n
+ * or F_n.  Device pointers; no synchronization. */
+typedef struct { double kappa0, kappa2; } fch_etd_opts;
+fch_status fch_step_etd(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* F_n, double k,
+                        const fch_etd_opts* opts, fch_c128* uh_np1);
+
 /* ---- adaptive time step (Sec. 3.2, Steps 2-4) ---------------------------- */
 /* F_trial = F(u~) = Lap mu(u~) (device out, the next step's cache);
  * u_p = u^n + (k~/6)[(3+2g)/(1+g) F(u~) + (3+g) F^n - g^2/(1+g) F^{n-1}], g = k~/k_n;
@@ -272,14 +290,21 @@ fch_status fch_adapt_dt_dev(fch_plan_t plan, const fch_c128* uh_trial, const fch
  * and uh_nm1 the one before it.  Fixed-step runs (adaptive = 0) take nsteps
  * steps of size k (the startup step counts as one); adaptive runs follow
  * Sec. 3.2 until t_end or nsteps accepted steps.  *rs (SAV only, host in/out):
- * r^n, r^{n-1}.  info (nullable, host out). */
-typedef enum { FCH_IMEX = 0, FCH_SAV = 1, FCH_PSD = 2 } fch_scheme;
+ * r^n, r^{n-1}.  info (nullable, host out).
+ * FCH_ETD (ETDRK2 with opts->etd) is a one-step method: fixed runs take
+ * nsteps ETDRK2 steps and ignore startup and the entering uh_nm1.  Adaptive
+ * ETD runs take the startup step as one ETDRK2 step of k_first without error
+ * control (the estimate needs F^{n-1}), then follow Sec. 3.2 with the ETDRK2
+ * result as the primary approximation of Step 1; each attempt starts from
+ * the cached F(u^n) (8 FFT calls, as for IMEX). */
+typedef enum { FCH_IMEX = 0, FCH_SAV = 1, FCH_PSD = 2, FCH_ETD = 3 } fch_scheme;
 typedef struct {
     int32_t scheme, adaptive, startup;
     int64_t nsteps;
     double  k, k_prev, k_first, t_end;
     fch_adapt_opts adapt;
     fch_psd_opts psd;
+    fch_etd_opts etd;
 } fch_run_opts;
 typedef struct {
     int64_t accepted, rejected, psd_iters, fft_calls;
@@ -311,6 +336,9 @@ typedef struct {
     int32_t N, done, nonfinite;
     int64_t accepted, rejected;
     double  t, k_last, k_next, err;
+    double  umax;   /* running max of u over the accepted states after the startup
+                       step (-inf before the first); the defect-onset indicator of
+                       Sec. 5.1 and Table f:defect-onsetR */
 } fch_member_info;
 /* Host-side setup: one plan (twiddles, launch variants) per size class on the
  * current device.  members: count parameter sets (N in 16..2048). */

@@ -828,6 +828,81 @@ fch_status fch_step_psd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   return FCH_OK;
 }
 
+// ---- ETDRK2 ----------------------------------------------------------------
+static fch_status etd_opts(const fch_etd_opts* o, double* k0, double* k2) {
+  *k0 = o ? o->kappa0 : 1e-2;  // the values of Sec. 3.6
+  *k2 = o ? o->kappa2 : 15.0;
+  if (!(*k0 >= 0.0) || !(*k2 >= 0.0) || !std::isfinite(*k0) || !std::isfinite(*k2))
+    return FCH_E_INVALID;
+  return FCH_OK;
+}
+
+namespace {
+// the second stage from u~ (in st) and w (in aux): its evaluation then
+// u^{n+1} = w + k phi2 N(u~), optionally followed by the inverse column
+// transforms of (u^{n+1}, Lap u^{n+1}) for the next evaluation
+fch_status etd_second(fch_plan_s* p, cd* ut, cd* out, bool next) {
+  CHK(row_mu(p, nullptr));
+  ColArgs b = col_args(p);
+  b.s0 = ut;
+  b.s1 = p->aux;
+  b.out = out;
+  CHK(col(p, fch::EPI_ETD2, next ? fch::PRO_NEXT_FIELD : fch::PRO_NONE, b));
+  p->stats.fft_calls += 4;
+  return FCH_OK;
+}
+// the first stage from the cached F(u^n): u~ into ut and w into aux, and the
+// inverse column transforms of (u~, Lap u~)
+fch_status etd_first_cached(fch_plan_s* p, const cd* un, const cd* Fn, cd* ut) {
+  ColArgs a = col_args(p);
+  a.s0 = un;
+  a.f_n = Fn;
+  a.out = ut;
+  a.aux = p->aux;
+  return col(p, fch::EPI_NONE, fch::PRO_ETD1, a);
+}
+// the first stage with its own evaluation of mu(u^n), whose (u^n, Lap u^n)
+// the pair buffer already holds column-inverted
+fch_status etd_first_eval(fch_plan_s* p, const cd* un, cd* ut) {
+  CHK(row_mu(p, nullptr));
+  ColArgs a = col_args(p);
+  a.s0 = un;
+  a.out = ut;
+  a.aux = p->aux;
+  CHK(col(p, fch::EPI_ETD1, fch::PRO_NEXT_FIELD, a));
+  p->stats.fft_calls += 4;
+  return FCH_OK;
+}
+StepCtl etd_ctl(double k, double kappa0, double kappa2) {
+  StepCtl v = ctl_zero();
+  v.k_np1 = k;
+  v.kappa0 = kappa0;
+  v.kappa2 = kappa2;
+  return v;
+}
+}  // namespace
+
+fch_status fch_step_etd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* F_n, double k,
+                        const fch_etd_opts* opts, fch_c128* uh_np1) {
+  if (!p || !uh_n || !uh_np1 || !finite_pos(k)) return FCH_E_INVALID;
+  double k0, k2;
+  CHK(etd_opts(opts, &k0, &k2));
+  CHK(need_ws(p));
+  CHK(ctl_set(p, etd_ctl(k, k0, k2)));
+  const cd* un = (const cd*)uh_n;
+  if (F_n) {
+    CHK(etd_first_cached(p, un, (const cd*)F_n, p->st));
+  } else {
+    ColArgs a = col_args(p);
+    a.s0 = un;
+    CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+    CHK(etd_first_eval(p, un, p->st));
+  }
+  CHK(etd_second(p, p->st, (cd*)uh_np1, false));
+  p->stats.steps += 1;
+  return FCH_OK;
+}
+
 // ---- adaptivity -----------------------------------------------------------
 static fch_status check_adapt(const fch_adapt_opts* o) {
   if (!o || !finite_pos(o->sigma_tol) || !finite_pos(o->k_min) || !(o->k_max >= o->k_min) ||
@@ -1102,7 +1177,9 @@ fch_status chain_replay(fch_plan_s* p, cd* cur, cd* prev) {
 fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128* uh_nm1,
                    double* rs, fch_run_info* info) {
   if (!p || !o || !uh_n || !uh_nm1 || uh_n == uh_nm1) return FCH_E_INVALID;
-  if (o->scheme < FCH_IMEX || o->scheme > FCH_PSD) return FCH_E_INVALID;
+  if (o->scheme < FCH_IMEX || o->scheme > FCH_ETD) return FCH_E_INVALID;
+  double ka0 = 0.0, ka2 = 0.0;
+  if (o->scheme == FCH_ETD) CHK(etd_opts(&o->etd, &ka0, &ka2));
   if (o->scheme == FCH_SAV && !rs) return FCH_E_INVALID;
   CHK(need_ws(p));
   cd* B0 = (cd*)uh_n;
@@ -1115,6 +1192,35 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     CHK(fch_sav_r(p, uh_n, &r0));
     rs[0] = r0;
     rs[1] = r0;
+  }
+
+  if (!o->adaptive && o->scheme == FCH_ETD) {
+    // one-step method: nsteps steps of size k; each first stage evaluates
+    // mu(u^n) and hands u~ to the second, whose column pass starts the next
+    // step's evaluation.  u^{n+1} overwrites u^{n-1}.
+    if (!finite_pos(o->k) || o->nsteps < 0) return FCH_E_INVALID;
+    if (o->nsteps > 0) {
+      CHK(ctl_set(p, etd_ctl(o->k, ka0, ka2)));
+      ColArgs a = col_args(p);
+      a.s0 = cur;
+      CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+    }
+    for (int64_t n = 0; n < o->nsteps; ++n) {
+      CHK(etd_first_eval(p, cur, spare));
+      CHK(etd_second(p, spare, prev, n + 1 < o->nsteps));
+      std::swap(cur, prev);
+      p->stats.steps += 1;
+    }
+    inf.accepted = o->nsteps;
+    inf.t = o->nsteps * o->k;
+    inf.k_last = o->k;
+    inf.k_next = o->k;
+    CHK(settle(p, B0, B1, cur, prev));
+    if (info) {
+      inf.fft_calls = p->stats.fft_calls;
+      *info = inf;
+    }
+    return FCH_OK;
   }
 
   if (!o->adaptive) {
@@ -1174,7 +1280,8 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
         }
       }
     } else {
-      while (done < o->nsteps) {
+      // SAV: steps at a changed ratio one at a time, then the fused chain
+      while (done < o->nsteps && (o->scheme != FCH_SAV || k_n != o->k)) {
         double rn = 0;
         int64_t it = 0;
         CHK(sav_or_psd_step(p, o, cur, prev, o->k, k_n, prev, rs, &rn, &it));
@@ -1183,6 +1290,52 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
         std::swap(cur, prev);
         k_n = o->k;
         ++done;
+      }
+      if (o->scheme == FCH_SAV && done < o->nsteps) {
+        // fused SAV chain at gamma = 1 with r on the device: row pass (E_1
+        // partials), SAV column pass (p over u^{n-1}, q, the (g_p, g_q)
+        // partials), then a column pass that solves for r^{n+1} in every
+        // workgroup, writes u^{n+1} = p + r^{n+1} q and starts the next step's
+        // evaluation.  No host synchronization until the end.
+        StepCtl v = ctl_zero();
+        set_bdf2(v, o->k, o->k);
+        v.rring[0] = rs[0];
+        v.rring[2] = rs[1];
+        CHK(ctl_set(p, v));
+        ColArgs a = col_args(p);
+        a.s0 = cur;
+        a.s1 = prev;
+        CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
+        int slot = 0;
+        while (done < o->nsteps) {
+          CHK(row_mu(p, p->rpart));
+          ColArgs b = col_args(p);
+          b.s0 = cur;
+          b.s1 = prev;
+          b.out = prev;
+          b.aux = p->aux;
+          b.partial = p->cpart;
+          b.sav_rpart = p->rpart;
+          b.sav_nrow = p->N / p->rv->R;
+          CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, b));
+          ColArgs c = col_args(p);
+          c.s0 = cur;
+          c.out = prev;
+          c.aux = p->aux;
+          c.sav_cpart = p->cpart;
+          c.sav_ncol = p->H;
+          c.rslot = slot;
+          CHK(col(p, fch::EPI_NONE, fch::PRO_SAV_NEXT, c));
+          slot = (slot + 1) % 3;
+          std::swap(cur, prev);
+          ++done;
+          p->stats.fft_calls += 4;
+          p->stats.steps += 1;
+        }
+        CHK(readback(p));
+        CHK(status_from_ctl(p));
+        rs[0] = p->hctl->rring[slot];
+        rs[1] = p->hctl->rring[(slot + 2) % 3];
       }
     }
     inf.accepted = done;
@@ -1210,6 +1363,11 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     CHK(fch_rhs(p, (const fch_c128*)cur, (fch_c128*)Fm));
     if (o->scheme == FCH_IMEX) {
       CHK(imex_attempt(p, cur, cur, k1, -1.0, prev));
+    } else if (o->scheme == FCH_ETD) {
+      CHK(ctl_set(p, etd_ctl(k1, ka0, ka2)));
+      CHK(etd_first_cached(p, cur, Fm, Ft));
+      CHK(etd_second(p, Ft, prev, false));
+      p->stats.steps += 1;
     } else {
       double rn = 0;
       int64_t it = 0;
@@ -1238,7 +1396,29 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     set_bdf2(v, kt, k_n);
     set_am3(v, kt, k_n);
     set_adapt(v, ad);
-    if (o->scheme == FCH_IMEX) {
+    if (o->scheme == FCH_ETD) {
+      // ETDRK2 attempt from the cached F(u^n) (Ft holds u~ until the AM3
+      // epilogue overwrites it with F of the trial state)
+      v.kappa0 = ka0;
+      v.kappa2 = ka2;
+      CHK(ctl_set(p, v));
+      CHK(etd_first_cached(p, cur, Fn, Ft));
+      CHK(etd_second(p, Ft, spare, true));
+      CHK(row_mu(p, nullptr));
+      ColArgs b = col_args(p);
+      b.s0 = spare;
+      b.s1 = cur;
+      b.f_n = Fn;
+      b.f_nm1 = Fm;
+      b.out = Ft;
+      b.partial = p->cpart;
+      CHK(col(p, fch::EPI_AM3, fch::PRO_NONE, b));
+      CHK(finalize(p, fch::FIN_AM3, false, true));
+      CHK(readback(p));
+      CHK(status_from_ctl(p));
+      p->stats.fft_calls += 4;
+      p->stats.steps += 1;
+    } else if (o->scheme == FCH_IMEX) {
       // fused: the step's column pass also starts the F(u~) evaluation
       CHK(ctl_set(p, v));
       ColArgs a = col_args(p);

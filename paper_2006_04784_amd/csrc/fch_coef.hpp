@@ -86,8 +86,12 @@ __host__ __device__ inline int sav_sstar(double E1, double D0, double& s) {
 
 // SAV scalar solve (eq. 4.8) from g_p = (X, a p + b u^n + c u^{n-1}) and
 // g_q = (X, q): r^{n+1} = (-b r^n - c r^{n-1} + g_p / 2) / (a - a g_q / 2)
+__host__ __device__ inline double sav_r_solve(const StepCtl& v, double r_n, double r_nm1,
+                                              double gp, double gq) {
+  return (-v.b * r_n - v.c * r_nm1 + 0.5 * gp) / (v.a - 0.5 * v.a * gq);
+}
 __host__ __device__ inline double sav_r_solve(const StepCtl& v, double gp, double gq) {
-  return (-v.b * v.r_n - v.c * v.r_nm1 + 0.5 * gp) / (v.a - 0.5 * v.a * gq);
+  return sav_r_solve(v, v.r_n, v.r_nm1, gp, gq);
 }
 
 // Sec. 3.3 stopping test after `iters` iterations whose last step ratio is

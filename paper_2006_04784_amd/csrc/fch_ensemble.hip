@@ -65,7 +65,7 @@ namespace {
 
 size_t member_bytes(const fch_ensemble_s* e, int N) {
   const size_t S = a256(spec_bytes(N));
-  return 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)) +
+  return 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)) + a256(sizeof(double) * (size_t)N) +
          a256(sizeof(double) * (size_t)e->opts.max_steps);
 }
 
@@ -88,7 +88,9 @@ size_t layout(fch_ensemble_s* e, bool assign) {
       m.P0 = (cd*)(b + 6 * S);
       m.P1 = (cd*)(b + 7 * S);
       m.cpart = (double*)(b + 8 * S);
-      m.klog = (double*)(b + 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)));
+      m.umaxpart = (double*)(b + 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)));
+      m.klog = (double*)(b + 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)) +
+                         a256(sizeof(double) * (size_t)N));
       m.klog_cap = e->opts.max_steps;
     }
     off += member_bytes(e, N);
@@ -111,9 +113,9 @@ fch_status enqueue_attempt(fch_ensemble_s* e) {
     const fch::RowVT* rv = c.plan->rv;
     const fch::ColVT* cv = c.plan->cv;
     HCHK(cv->col_ens(fch::ENS_PRO, e->dmem, c.first, c.count, c.stream));
-    HCHK(rv->row_ens(e->dmem, c.first, c.count, c.stream));
+    HCHK(rv->row_ens(e->dmem, c.first, c.count, 0, c.stream));
     HCHK(cv->col_ens(fch::ENS_IMEX, e->dmem, c.first, c.count, c.stream));
-    HCHK(rv->row_ens(e->dmem, c.first, c.count, c.stream));
+    HCHK(rv->row_ens(e->dmem, c.first, c.count, 1, c.stream));
     HCHK(cv->col_ens(fch::ENS_AM3, e->dmem, c.first, c.count, c.stream));
     HCHK(fch::launch_ens_control(e->dmem, c.first, c.count, c.stream));
     HCHK(hipEventRecord(c.join, c.stream));
@@ -260,6 +262,7 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   m.accepted = 1;
   m.rejected = 0;
   m.max_accepted = e->opts.max_steps;
+  m.umax = -INFINITY;
   fch::StepCtl& v = m.ctl;
   std::memset(&v, 0, sizeof(v));
   v.sigma_tol = e->opts.adapt.sigma_tol;
@@ -275,6 +278,8 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   v.done = (m.t >= m.t_end * (1.0 - 1e-14) || m.accepted >= m.max_accepted) ? 1 : 0;
   HCHK(hipStreamSynchronize(p->stream));
   HCHK(hipMemcpy(m.klog, &k1, sizeof(double), hipMemcpyHostToDevice));
+  const std::vector<double> ninf((size_t)m.c.N, -INFINITY);
+  HCHK(hipMemcpy(m.umaxpart, ninf.data(), sizeof(double) * ninf.size(), hipMemcpyHostToDevice));
   HCHK(hipMemcpy(e->dmem + k, &m, sizeof(EnsMember), hipMemcpyHostToDevice));
   e->loaded[k] = 1;
   return FCH_OK;
@@ -403,6 +408,7 @@ fch_status fch_ensemble_member(fch_ensemble_t e, int32_t member, fch_c128* uh, d
     info->k_last = m.ctl.k_n;
     info->k_next = m.ctl.k_next;
     info->err = m.ctl.err;
+    info->umax = m.umax;
   }
   return FCH_OK;
 }

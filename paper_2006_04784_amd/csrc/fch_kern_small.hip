@@ -115,7 +115,22 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
   if (m->ctl.done) return;
   const double c0 = sum_strided(m->cpart, m->H, 2, 0, red);
   const double c1 = sum_strided(m->cpart, m->H, 2, 1, red);
+  // largest u of the trial state: one value per workgroup of the trial
+  // evaluation's row pass (the other slots hold -inf); the slots are reset
+  double um = -INFINITY;
+  for (int i = threadIdx.x; i < m->c.N; i += 256) {
+    um = fmax(um, m->umaxpart[i]);
+    m->umaxpart[i] = -INFINITY;
+  }
+  __syncthreads();
+  red[threadIdx.x] = um;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
+  um = red[0];
   StepCtl& ctl = m->ctl;
   const double kt = ctl.k_np1;
   const double e = sqrt(c0 / c1);
@@ -138,6 +153,7 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
     m->t += kt;
     if (m->accepted < m->klog_cap) m->klog[m->accepted] = kt;
     m->accepted += 1;
+    m->umax = fmax(m->umax, um);
     ctl.k_n = kt;
   } else {
     m->rejected += 1;

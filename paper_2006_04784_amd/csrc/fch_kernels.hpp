@@ -19,6 +19,8 @@ struct StepCtl {
   double r_n, r_nm1, s_star, r_np1;   // SAV scalars
   double sigma_tol, k_min, k_max, rho_s, cap;
   double err, k_next, ratio, energy, E1;
+  double kappa0, kappa2;              // ETDRK2 split constants (eq. ETD-L); step k_np1
+  double rring[3];                    // SAV r history of the fused chain, slot n mod 3 = r^n
   int accept, iters, max_iter, fixed_iters;
   int done;       // PSD: 0 running, 1 converged / fixed count reached, 2 max_iter, 3 non-finite
   int nonfinite;  // set by any kernel that sees NaN/Inf
@@ -27,8 +29,17 @@ struct StepCtl {
 };
 
 enum RowMode { ROW_MU = 0, ROW_FWD = 1, ROW_INV = 2 };
-enum Epi { EPI_NONE = 0, EPI_MU, EPI_F, EPI_IMEX, EPI_SAV, EPI_PSD, EPI_AM3 };
-enum Pro { PRO_NONE = 0, PRO_FIELD, PRO_EXTRAP, PRO_PSD_INIT, PRO_NEXT_EXTRAP, PRO_NEXT_FIELD };
+enum Epi { EPI_NONE = 0, EPI_MU, EPI_F, EPI_IMEX, EPI_SAV, EPI_PSD, EPI_AM3, EPI_ETD1, EPI_ETD2 };
+enum Pro {
+  PRO_NONE = 0,
+  PRO_FIELD,
+  PRO_EXTRAP,
+  PRO_PSD_INIT,
+  PRO_NEXT_EXTRAP,
+  PRO_NEXT_FIELD,
+  PRO_ETD1,
+  PRO_SAV_NEXT
+};
 enum FinMode { FIN_SAV_S = 0, FIN_PSD, FIN_AM3, FIN_ENERGY };
 
 struct RowArgs {
@@ -55,11 +66,11 @@ struct ColArgs {
   cd* P0;
   cd* P1;
   const cd* s0;     // state / field input (u^n, u, u~)
-  const cd* s1;     // second input (u^{n-1}, or u^n for EPI_AM3)
-  cd* out;          // output (u^{n+1}, mu, F, PSD iterate); may alias s1
-  cd* aux;          // SAV q, PSD b u^n + c u^{n-1}
+  const cd* s1;     // second input (u^{n-1}, u^n for EPI_AM3, w for EPI_ETD2)
+  cd* out;          // output (u^{n+1}, mu, F, PSD iterate, ETD stage u~); may alias s1
+  cd* aux;          // SAV q, PSD b u^n + c u^{n-1}, ETD w = u~ - k phi2 N(u^n)
   const cd* guess;  // PSD initial guess (nullable)
-  const cd* f_n;    // AM3 F^n
+  const cd* f_n;    // AM3 F^n; PRO_ETD1 F(u^n)
   const cd* f_nm1;  // AM3 F^{n-1}
   const cd* X_in;   // single-field column transform input
   cd* X_out;        // single-field column transform output
@@ -70,6 +81,13 @@ struct ColArgs {
   // from which every workgroup forms s*; otherwise ctl->s_star is used
   const double* sav_rpart;
   int sav_nrow;
+  // PRO_SAV_NEXT: the column partial sums (g_p, g_q; sav_ncol pairs) of the
+  // SAV step, from which every workgroup solves for r^{n+1}; r^n and r^{n-1}
+  // are ctl->rring[rslot] and ctl->rring[(rslot + 2) % 3], r^{n+1} goes to
+  // ctl->rring[(rslot + 1) % 3]
+  const double* sav_cpart;
+  int sav_ncol;
+  int rslot;
 };
 
 struct FinArgs {
@@ -95,6 +113,8 @@ struct EnsMember {
   cd* P0;
   cd* P1;
   double* cpart;  // 2 per column
+  double* umaxpart;  // N slots: largest u per row workgroup of the trial evaluation (-inf unused)
+  double umax;       // running max of u over the accepted states after the startup step
   double* klog;   // accepted step sizes
   long long klog_cap;
   int cur, prev, trial, fn, fm, ft;
@@ -111,8 +131,9 @@ struct RowVT {
   int N, R, E, twl, threads;
   // e0/e1 (nullable): events attached to the dispatch (kernel execution time)
   hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-  // batched row pass (chemical-potential pieces) over members [first, first+count)
-  hipError_t (*row_ens)(EnsMember* m, int first, int count, hipStream_t s);
+  // batched row pass (chemical-potential pieces) over members [first, first+count);
+  // track: also the largest u per workgroup (into each member's umaxpart)
+  hipError_t (*row_ens)(EnsMember* m, int first, int count, int track, hipStream_t s);
   // ROW_FWD / ROW_INV over `batch` fields stored back to back
   hipError_t (*row_batch)(int mode, const RowArgs& a, int batch, size_t pstride, size_t sstride,
                           hipStream_t s);

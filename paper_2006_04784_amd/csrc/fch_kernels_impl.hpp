@@ -33,6 +33,70 @@ __device__ __forceinline__ double wavek2(const Consts& c, int kx, int ky) {
   return c.kscale * (double)(kx * kx + kyi * kyi);
 }
 
+// ---- ETDRK2 (Sec. 3.6) --------------------------------------------------------
+// e^z, phi1 = (e^z - 1)/z and phi2 = (e^z - 1 - z)/z^2 at z = L k are the
+// multipliers of eqs. ETDRK1 and ETDRK2: L^{-1}(e^{Lk} - I) = k phi1 and
+// L^{-1}[L^{-1}(e^{Lk} - I) - k I]/k = k phi2.  Both quotients cancel near
+// z = 0, so for |z| <= 1/2 phi2 is its degree-15 Taylor polynomial
+// sum_m z^m/(m+2)! (truncation error below 3e-21), phi1 = 1 + z phi2 and
+// e^z = 1 + z phi1; elsewhere all three come from expm1.
+constexpr double inv_factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;  // exact up to 18!
+  return 1.0 / f;
+}
+__device__ __forceinline__ void etd_phi(double z, double& e, double& p1, double& p2) {
+  if (fabs(z) <= 0.5) {
+    double s = inv_factorial(17);
+#pragma unroll
+    for (int n = 16; n >= 2; --n) s = fma(s, z, inv_factorial(n));
+    p2 = s;
+    p1 = fma(z, p2, 1.0);
+    e = fma(z, p1, 1.0);
+  } else {
+    const double m1 = expm1(z);
+    const double iz = 1.0 / z;
+    e = m1 + 1.0;
+    p1 = m1 * iz;
+    p2 = (m1 - z) * iz * iz;
+  }
+}
+
+// the linear operator of eq. ETD-L at |k|^2 = k2 (Laplacian -> -k2):
+// -k2 (eps^2 k2 + alpha)^2 - kappa0 - kappa2 eps^2 k2, never positive
+__device__ __forceinline__ double etd_L(const Consts& c, const StepCtl* ctl, double k2) {
+  const double e2k2 = c.eps2 * k2;
+  const double li = e2k2 + c.alpha;
+  return -k2 * li * li - ctl->kappa0 - ctl->kappa2 * e2k2;
+}
+
+// First stage at one wavenumber from u^n and F = Lap mu(u^n): the split's
+// nonlinearity N(u^n) = F - L u^n (eq. ETD-L), the ETDRK1 stage
+// u~ = e^{Lk} u^n + k phi1 N(u^n), and w = u~ - k phi2 N(u^n), so that the
+// second stage is u^{n+1} = w + k phi2 N(u~) (eq. ETDRK2).  k = k_np1.
+__device__ __forceinline__ void etd_stage1(const Consts& c, const StepCtl* ctl, double k2, cd un,
+                                           cd F, cd& ut, cd& w) {
+  const double L = etd_L(c, ctl, k2);
+  const double k = ctl->k_np1;
+  double e, p1, p2;
+  etd_phi(L * k, e, p1, p2);
+  const cd Nn = {F.x - L * un.x, F.y - L * un.y};
+  const double kp1 = k * p1, kp2 = k * p2;
+  ut = cd{e * un.x + kp1 * Nn.x, e * un.y + kp1 * Nn.y};
+  w = cd{ut.x - kp2 * Nn.x, ut.y - kp2 * Nn.y};
+}
+
+// Second stage from u~, F = Lap mu(u~) and w: u^{n+1} = w + k phi2 (F - L u~).
+__device__ __forceinline__ cd etd_stage2(const Consts& c, const StepCtl* ctl, double k2, cd ut,
+                                         cd F, cd w) {
+  const double L = etd_L(c, ctl, k2);
+  const double k = ctl->k_np1;
+  double e, p1, p2;
+  etd_phi(L * k, e, p1, p2);
+  const double kp2 = k * p2;
+  return cd{w.x + kp2 * (F.x - L * ut.x), w.y + kp2 * (F.y - L * ut.y)};
+}
+
 // deterministic reduction of K values over NT threads (a fixed butterfly
 // inside each wavefront, then the wavefront sums in order); thread 0 writes
 template <int NT, int K>
@@ -143,8 +207,10 @@ __device__ __forceinline__ int psd_check(const RowArgs& a) {
 // ===========================================================================
 // TWL: twiddle table copied to LDS (1) or read from global memory through
 // the vector caches (0, frees N*16 bytes of LDS per workgroup)
-template <int N, int R, int E, int MODE, int TWL>
-__device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
+// UMAX (ROW_MU, ensembles): the workgroup's largest u goes to umax_part[tile]
+template <int N, int R, int E, int MODE, int TWL, bool UMAX = false>
+__device__ __forceinline__ void row_body(const RowArgs& a, const int* done,
+                                         double* umax_part = nullptr) {
   constexpr int T = N / E;
   constexpr int NT = R * T;
   constexpr int M = N / 2;
@@ -232,6 +298,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   }
 
   double acc[2] = {0.0, 0.0};
+  double umax = -INFINITY;
   if constexpr (MODE == ROW_MU) {
     const Consts& c = a.c;
     bool bad = false;
@@ -250,6 +317,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
         acc[0] += -c.eps2 * lap * (W1 + c.zeta * u) + 0.5 * W1 * W1 - c.eta2 * W;  // G (eq. e:G-def)
         acc[1] += 0.5 * om * om - c.eta2 * W;                                       // energy density
         bad |= !(isfinite(u) && isfinite(lap));
+        if constexpr (UMAX) umax = fmax(umax, u);
         v[0][s] = cd{om, p};
       }
     };
@@ -295,6 +363,20 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done) {
   if constexpr (MODE == ROW_MU) {
     if (a.partial) block_reduce<NT, 2>(acc, red, a.partial + 2 * tile);
   }
+  if constexpr (UMAX) {
+    constexpr int NW = (NT + 63) / 64;
+#pragma unroll
+    for (int off = (NT < 64 ? NT : 64) / 2; off >= 1; off >>= 1)
+      umax = fmax(umax, __shfl_xor(umax, off, 64));
+    __syncthreads();  // red may still be read by the partial sums above
+    if ((tid & 63) == 0) red[tid >> 6] = umax;
+    __syncthreads();
+    if (tid == 0) {
+      double m = red[0];
+      for (int i = 1; i < NW; ++i) m = fmax(m, red[i]);
+      umax_part[tile] = m;
+    }
+  }
 }
 
 // ===========================================================================
@@ -331,11 +413,11 @@ __device__ __forceinline__ void hermitian_fix(cd (&f)[NV][E], cd* const (&lds)[2
 
 // ---- per-wavenumber algebra of the column pass --------------------------------
 // State values read at one wavenumber before the forward FFT: u^n, u^{n-1}
-// (IMEX, SAV), the PSD iterate and b u^n + c u^{n-1} (PSD), or the field U
-// whose (U, Lap U) fed the evaluation (MU, F, AM3).
+// (IMEX, SAV), the PSD iterate and b u^n + c u^{n-1} (PSD), u~ and w (ETD2),
+// or the field U whose (U, Lap U) fed the evaluation (MU, F, AM3, ETD1).
 template <int EPI>
 __device__ __forceinline__ void load_pre(const ColArgs& a, size_t g, cd& p0, cd& p1) {
-  if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV) {
+  if constexpr (EPI == EPI_IMEX || EPI == EPI_SAV || EPI == EPI_ETD2) {
     p0 = a.s0[g];
     p1 = a.s1[g];
   } else if constexpr (EPI == EPI_PSD) {
@@ -350,8 +432,9 @@ __device__ __forceinline__ void load_pre(const ColArgs& a, size_t g, cd& p0, cd&
 // Epilogue at one wavenumber from the forward-transformed omega^, p^:
 // mu^ = -eps^2 |k|^2 omega^ + p^ - eps^2 eta1 |k|^2 U^ (eq. FCH with Lap ->
 // -|k|^2), then the scheme's diagonal algebra.  o0: the output (u^{n+1},
-// mu^, F^, the next PSD iterate, F(u~)); o1: SAV q^ or PSD d^; Ua: the field
-// the partial sums need (U, or X for SAV); un, um: u^n, u^{n-1}.
+// mu^, F^, the next PSD iterate, F(u~), the ETD stage u~); o1: SAV q^, PSD d^
+// or ETD w; Ua: the field the partial sums need (U, or X for SAV); un, um:
+// u^n, u^{n-1}.
 template <int EPI>
 __device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, double sstar,
                                           double k2, double wgt, cd om, cd pp, cd p0, cd p1,
@@ -407,6 +490,10 @@ __device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, d
     o1 = d;
   } else if constexpr (EPI == EPI_AM3) {
     o0 = cscale(mu, -k2);
+  } else if constexpr (EPI == EPI_ETD1) {
+    etd_stage1(c, ctl, k2, U, cscale(mu, -k2), o0, o1);
+  } else if constexpr (EPI == EPI_ETD2) {
+    o0 = etd_stage2(c, ctl, k2, U, cscale(mu, -k2), p1);
   }
 }
 
@@ -434,6 +521,11 @@ __device__ __forceinline__ void post_point(const ColArgs& a, const StepCtl* ctl,
     acc[0] += wgt * cnorm2(o1);
     acc[1] += wgt * cnorm2(o0);
     unext = o0;
+  } else if constexpr (EPI == EPI_ETD1) {
+    a.aux[g] = o1;
+    unext = o0;
+  } else if constexpr (EPI == EPI_ETD2) {
+    unext = o0;
   } else if constexpr (EPI == EPI_AM3) {
     const cd u_n = a.s1[g], fn = a.f_n[g], fm = a.f_nm1[g];
     const cd up = {u_n.x + ctl->w1 * o0.x + ctl->w2 * fn.x + ctl->w3 * fm.x,
@@ -444,13 +536,18 @@ __device__ __forceinline__ void post_point(const ColArgs& a, const StepCtl* ctl,
 }
 
 // State values the prologue reads at one wavenumber (PRO_FIELD: U; EXTRAP and
-// PSD_INIT: u^n, u^{n-1} and, for PSD_INIT, the guess).
+// PSD_INIT: u^n, u^{n-1} and, for PSD_INIT, the guess; ETD1: u^n, F(u^n)).
 template <int PRO>
 __device__ __forceinline__ void load_pro(const ColArgs& a, size_t g, cd& s0v, cd& s1v, cd& gv) {
   s0v = a.s0[g];
   s1v = cd{0.0, 0.0};
   gv = cd{0.0, 0.0};
   if constexpr (PRO == PRO_EXTRAP || PRO == PRO_PSD_INIT) s1v = a.s1[g];
+  if constexpr (PRO == PRO_ETD1) s1v = a.f_n[g];
+  if constexpr (PRO == PRO_SAV_NEXT) {
+    s1v = a.out[g];
+    gv = a.aux[g];
+  }
   if constexpr (PRO == PRO_PSD_INIT) {
     if (a.guess) gv = a.guess[g];
   }
@@ -458,12 +555,26 @@ __device__ __forceinline__ void load_pro(const ColArgs& a, size_t g, cd& s0v, cd
 
 // Prologue at one wavenumber: U whose (U, Lap U) the next evaluation needs:
 // the field, the extrapolation u^n + gamma (u^n - u^{n-1}) (eq. Richardson),
-// or the PSD initial iterate (guess, keeping the mean of u^n; PSD_INIT also
-// writes b u^n + c u^{n-1} and the iterate).  PRO_NEXT_*: unext.
+// the PSD initial iterate (guess, keeping the mean of u^n; PSD_INIT also
+// writes b u^n + c u^{n-1} and the iterate), the ETDRK1 stage u~ from the
+// cached F(u^n) (ETD1 also writes u~ and w), or, after a SAV step, the
+// extrapolation of u^{n+1} = p + r^{n+1} q (eq. 4.8; SAV_NEXT writes u^{n+1}
+// over p; rr = r^{n+1}).  PRO_NEXT_*: unext.
 template <int PRO>
 __device__ __forceinline__ cd pro_point(const ColArgs& a, const StepCtl* ctl, size_t g,
-                                        bool mean_mode, cd s0v, cd s1v, cd gv, cd unext) {
-  if constexpr (PRO == PRO_FIELD) {
+                                        double k2, bool mean_mode, cd s0v, cd s1v, cd gv,
+                                        cd unext, double rr) {
+  if constexpr (PRO == PRO_SAV_NEXT) {
+    const cd u1 = {fma(rr, gv.x, s1v.x), fma(rr, gv.y, s1v.y)};
+    a.out[g] = u1;
+    return cadd(u1, cscale(csub(u1, s0v), ctl->gamma));
+  } else if constexpr (PRO == PRO_ETD1) {
+    cd ut, w;
+    etd_stage1(a.c, ctl, k2, s0v, s1v, ut, w);
+    a.out[g] = ut;
+    a.aux[g] = w;
+    return ut;
+  } else if constexpr (PRO == PRO_FIELD) {
     return s0v;
   } else if constexpr (PRO == PRO_EXTRAP) {
     return cadd(s0v, cscale(csub(s0v, s1v), ctl->gamma));
@@ -547,6 +658,27 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
     }
   }
 
+  // SAV_NEXT: r^{n+1} from the SAV step's partial sums (g_p, g_q), solved by
+  // every workgroup in the same order (eq. 4.8); workgroup 0 records it
+  double rnew = 0.0;
+  if constexpr (PRO == PRO_SAV_NEXT) {
+    __shared__ double sh_r;
+    double c0 = 0.0, c1 = 0.0;
+    fixed_sum2<T>(a.sav_cpart, a.sav_ncol, c0, c1);
+    if (t == 0) {
+      const int sl = a.rslot;
+      const double r = sav_r_solve(*a.ctl, a.ctl->rring[sl], a.ctl->rring[(sl + 2) % 3],
+                                   c.pars * c0, c.pars * c1);
+      sh_r = r;
+      if (blockIdx.x == 0) {
+        a.ctl->rring[(sl + 1) % 3] = r;
+        if (!isfinite(r)) a.ctl->nonfinite = 1;
+      }
+    }
+    __syncthreads();
+    rnew = sh_r;
+  }
+
   cd v[2][E];
   cd* const base[2] = {buf[0], buf[1]};
   // PRO_NEXT_*: the epilogue hands the next evaluation's field to the
@@ -603,7 +735,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
       // separate the two columns; Z(-k) comes from the thread holding N - ky:
       // omega^, p^ of column 0 are (Z + conj Z(-k))/2, of column N/2
       // (Z - conj Z(-k))/(2i)
-      constexpr bool P1 = (EPI == EPI_IMEX || EPI == EPI_SAV || EPI == EPI_PSD);
+      constexpr bool P1 = (EPI == EPI_IMEX || EPI == EPI_SAV || EPI == EPI_PSD || EPI == EPI_ETD2);
       cd sep[4][E];  // omega^_0, p^_0, omega^_{N/2}, p^_{N/2}
       __syncthreads();
 #pragma unroll
@@ -676,9 +808,11 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
           const int ky = t + s * T;
           cd s0v, s1v, gv;
           load_pro<PRO>(a, col + ky, s0v, s1v, gv);
-          const cd U = pro_point<PRO>(a, ctl, col + ky, false, s0v, s1v, gv, cd{0.0, 0.0});
+          const double k2 = wavek2(c, kx, ky);
+          const cd U =
+              pro_point<PRO>(a, ctl, col + ky, k2, false, s0v, s1v, gv, cd{0.0, 0.0}, rnew);
           v[0][s] = U;
-          v[1][s] = cscale(U, -wavek2(c, kx, ky));
+          v[1][s] = cscale(U, -k2);
         }
       } else {
 #pragma unroll
@@ -686,9 +820,11 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
           const int ky = t + s * T;
           cd s0v, s1v, gv;
           load_pro<PRO>(a, ky, s0v, s1v, gv);
-          v[0][s] = pro_point<PRO>(a, ctl, ky, ky == 0, s0v, s1v, gv, cd{0.0, 0.0});
+          v[0][s] = pro_point<PRO>(a, ctl, ky, wavek2(c, 0, ky), ky == 0, s0v, s1v, gv,
+                                   cd{0.0, 0.0}, rnew);
           load_pro<PRO>(a, colM + ky, s0v, s1v, gv);
-          v[1][s] = pro_point<PRO>(a, ctl, colM + ky, false, s0v, s1v, gv, cd{0.0, 0.0});
+          v[1][s] = pro_point<PRO>(a, ctl, colM + ky, wavek2(c, M, ky), false, s0v, s1v, gv,
+                                   cd{0.0, 0.0}, rnew);
         }
         __syncthreads();
 #pragma unroll
@@ -768,9 +904,12 @@ __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
   a.tw = m->tw;
   a.sav_rpart = nullptr;
   a.sav_nrow = 0;
+  a.sav_cpart = nullptr;
+  a.sav_ncol = 0;
+  a.rslot = 0;
 }
 
-template <int N, int R, int E, int TWL>
+template <int N, int R, int E, int TWL, bool UMAX>
 __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first) {
   EnsMember* m = mem + first + blockIdx.y;
   RowArgs a;
@@ -787,7 +926,7 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
   a.psd_part = nullptr;
   a.psd_ncol = 0;
   a.psd_iter = 0;
-  row_body<N, R, E, ROW_MU, TWL>(a, &m->ctl.done);
+  row_body<N, R, E, ROW_MU, TWL, UMAX>(a, &m->ctl.done, m->umaxpart);
 }
 
 // one attempt of adaptive BDF2-IMEX: PRO (u* and Lap u* of the step),

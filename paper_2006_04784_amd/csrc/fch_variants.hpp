@@ -41,8 +41,13 @@ struct RowImpl {
     }
     return hipGetLastError();
   }
-  static hipError_t row_ens(EnsMember* m, int first, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_row_ens<N, R, E, TWL>), dim3(N / R, count), dim3(NT), 0, s, m, first);
+  static hipError_t row_ens(EnsMember* m, int first, int count, int track, hipStream_t s) {
+    if (track)
+      hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, true>), dim3(N / R, count), dim3(NT), 0, s, m,
+                         first);
+    else
+      hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, false>), dim3(N / R, count), dim3(NT), 0, s, m,
+                         first);
     return hipGetLastError();
   }
   static hipError_t row_batch(int mode, const RowArgs& a, int batch, size_t pstride,
@@ -91,6 +96,11 @@ struct ColImpl {
     FCH_COL(EPI_SAV, PRO_NONE)
     FCH_COL(EPI_PSD, PRO_NEXT_FIELD)
     FCH_COL(EPI_AM3, PRO_NONE)
+    FCH_COL(EPI_NONE, PRO_ETD1)
+    FCH_COL(EPI_NONE, PRO_SAV_NEXT)
+    FCH_COL(EPI_ETD1, PRO_NEXT_FIELD)
+    FCH_COL(EPI_ETD2, PRO_NEXT_FIELD)
+    FCH_COL(EPI_ETD2, PRO_NONE)
 #undef FCH_COL
     return hipErrorInvalidValue;
   }

@@ -20,7 +20,9 @@ _lib = None
 
 FCH_OK, FCH_E_INVALID, FCH_E_UNSUPPORTED, FCH_E_HIP, FCH_E_NOMEM, FCH_E_NOCONV, FCH_E_NONFINITE = \
     0, -1, -2, -3, -4, -5, -6
-FCH_IMEX, FCH_SAV, FCH_PSD = 0, 1, 2
+FCH_IMEX, FCH_SAV, FCH_PSD, FCH_ETD = 0, 1, 2, 3
+# the ETDRK2 split constants used for every simulation of Sec. 3.6
+ETD_KAPPA0, ETD_KAPPA2 = 1e-2, 15.0
 
 
 class FchError(RuntimeError):
@@ -65,11 +67,15 @@ class fch_adapt_opts(C.Structure):
                 ("rho_s", C.c_double), ("cap", C.c_double)]
 
 
+class fch_etd_opts(C.Structure):
+    _fields_ = [("kappa0", C.c_double), ("kappa2", C.c_double)]
+
+
 class fch_run_opts(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("adaptive", C.c_int32), ("startup", C.c_int32),
                 ("nsteps", C.c_int64), ("k", C.c_double), ("k_prev", C.c_double),
                 ("k_first", C.c_double), ("t_end", C.c_double), ("adapt", fch_adapt_opts),
-                ("psd", fch_psd_opts)]
+                ("psd", fch_psd_opts), ("etd", fch_etd_opts)]
 
 
 class fch_run_info(C.Structure):
@@ -91,7 +97,8 @@ class fch_ensemble_info(C.Structure):
 class fch_member_info(C.Structure):
     _fields_ = [("N", C.c_int32), ("done", C.c_int32), ("nonfinite", C.c_int32),
                 ("accepted", C.c_int64), ("rejected", C.c_int64), ("t", C.c_double),
-                ("k_last", C.c_double), ("k_next", C.c_double), ("err", C.c_double)]
+                ("k_last", C.c_double), ("k_next", C.c_double), ("err", C.c_double),
+                ("umax", C.c_double)]
 
 
 _V = C.c_void_p
@@ -130,6 +137,7 @@ _SIGS = {
     "fch_inverse": (_I, [_V, _V, _V]),
     "fch_chem_potential": (_I, [_V, _V, _V, _PD]),
     "fch_step_imex": (_I, [_V, _V, _V, _D, _D, _V]),
+    "fch_step_etd": (_I, [_V, _V, _V, _D, C.POINTER(fch_etd_opts), _V]),
     "fch_step_sav": (_I, [_V, _V, _V, _D, _D, _D, _D, _V, _PD]),
     "fch_sav_r": (_I, [_V, _V, _PD]),
     "fch_step_psd": (_I, [_V, _V, _V, _D, _D, _V, C.POINTER(fch_psd_opts), _V,
@@ -404,6 +412,15 @@ class Plan:
         _check(lib().fch_step_imex(self.h, _p(uh_n), _p(uh_nm1), k_np1, k_n, _p(out)))
         return out
 
+    def step_etd(self, uh_n, k, F_n=None, kappa0=ETD_KAPPA0, kappa2=ETD_KAPPA2, out=None):
+        """One ETDRK2 step (fch_step_etd); F_n (optional) = F(u^n) = Lap mu(u^n)."""
+        self._chk_spec(uh_n, F_n)
+        out = self.spec() if out is None else out
+        o = fch_etd_opts(kappa0, kappa2)
+        self._sync_stream()
+        _check(lib().fch_step_etd(self.h, _p(uh_n), _p(F_n), k, C.byref(o), _p(out)))
+        return out
+
     def sav_r(self, uh):
         self._chk_spec(uh)
         r = C.c_double()
@@ -503,12 +520,13 @@ class Plan:
 
     def run(self, uh_n, uh_nm1, scheme="imex", adaptive=False, startup=True, nsteps=0, k=1e-3,
             k_prev=0.0, k_first=0.0, t_end=0.0, adapt: AdaptOpts = None, psd_tol=1e-10,
-            psd_max_iter=1000, psd_lambda=0.0, rs=None):
+            psd_max_iter=1000, psd_lambda=0.0, rs=None, kappa0=ETD_KAPPA0, kappa2=ETD_KAPPA2):
         self._chk_spec(uh_n, uh_nm1)
-        sch = {"imex": FCH_IMEX, "sav": FCH_SAV, "psd": FCH_PSD}[scheme]
+        sch = {"imex": FCH_IMEX, "sav": FCH_SAV, "psd": FCH_PSD, "etd": FCH_ETD}[scheme]
         o = fch_run_opts(sch, int(adaptive), int(startup), nsteps, k, k_prev, k_first, t_end,
                          (adapt or AdaptOpts()).c(),
-                         fch_psd_opts(psd_tol, psd_max_iter, psd_lambda, 0))
+                         fch_psd_opts(psd_tol, psd_max_iter, psd_lambda, 0),
+                         fch_etd_opts(kappa0, kappa2))
         r = (C.c_double * 2)(*(rs if rs is not None else (0.0, 0.0)))
         info = fch_run_info()
         self._sync_stream()

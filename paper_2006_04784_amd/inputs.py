@@ -113,6 +113,117 @@ def white_noise(N: int, seed: int = 0, scale: float = 1.0):
     return np.random.default_rng(seed).normal(0.0, scale, size=(N, N))
 
 
+# ---- the paper's benchmark initial data (Sec. 2.3, eq. dcoef, Table t:Benchmark) ----
+PAPER_L = 4 * np.pi          # Omega = [0, 4 pi]^2
+PAPER_N0 = 256               # mesh of the filtered strip
+PAPER_R = 0.14725            # strip half-width
+PAPER_LAMBDA0 = 7.0269e-3    # filter exponent
+PAPER_ALPHA0 = 1.7           # alpha_m(0) = W_0''(b_-), printed in Table t:Benchmark
+# Table t:Benchmark: q, eta_1/eps, eta_2/eps, d, N (eps = 0.1, gamma = 0.3) and the
+# printed initial mass
+PAPER_BENCHMARKS = {
+    "sub-critical": dict(q=0.0, eta1=1.45, eta2=3.0, d=0.2, N=256, mass=6.11),
+    "critical": dict(q=0.0, eta1=1.45, eta2=1.5, d=0.75, N=256, mass=7.61),
+    "super-critical": dict(q=0.0, eta1=1.45, eta2=3.0, d=0.5, N=256, mass=6.93),
+    "foot-1": dict(q=0.2, eta1=1.45, eta2=3.0, d=0.2, N=256, mass=6.11),
+    "foot-2": dict(q=0.5, eta1=1.45, eta2=3.0, d=0.2, N=512, mass=6.11),
+}
+
+
+def paper_curve(theta, eps: float = 0.1, L: float = PAPER_L):
+    """The curve Gamma in polar form about the box centre:
+    rho(theta) = 3 - (eps/2) cos(6 (theta - pi/11)) - eps^2 cos(theta - 3 pi/11)."""
+    rho = 3.0 - 0.5 * eps * np.cos(6.0 * (theta - np.pi / 11)) - eps * eps * np.cos(theta - 3 * np.pi / 11)
+    return rho * np.cos(theta) + L / 2, rho * np.sin(theta) + L / 2
+
+
+def _curve_distance(px, py, eps, L, samples=20000):
+    """Distance from the points (px, py) to Gamma, taken to a closed polyline
+    through `samples` points of Gamma and searched near each point's polar
+    angle (Gamma is star-shaped about the box centre; the points lie within
+    0.5 of radius 3)."""
+    th = 2 * np.pi * np.arange(samples) / samples
+    cx, cy = paper_curve(th, eps, L)
+    ang = np.mod(np.arctan2(py - L / 2, px - L / 2), 2 * np.pi)
+    centre = np.rint(ang / (2 * np.pi) * samples).astype(np.int64)
+    best = np.full(px.shape, np.inf)
+    win = samples // 200  # +-0.03 rad, several times the largest angular offset of the foot point
+    for off in range(-win, win):
+        i0 = np.mod(centre + off, samples)
+        i1 = np.mod(i0 + 1, samples)
+        ax, ay = cx[i0], cy[i0]
+        bx, by = cx[i1] - ax, cy[i1] - ay
+        t = np.clip(((px - ax) * bx + (py - ay) * by) / (bx * bx + by * by), 0.0, 1.0)
+        best = np.minimum(best, np.hypot(px - ax - t * bx, py - ay - t * by))
+    return best
+
+
+def paper_strip_indicator(N0: int = PAPER_N0, eps: float = 0.1, R: float = PAPER_R,
+                          L: float = PAPER_L, sub: int = 8):
+    """phi_Gamma on the N0 x N0 mesh: +1 inside the strip Gamma_R between the
+    offset curves Gamma_+- (the points within distance R of Gamma, R being far
+    below Gamma's smallest radius of curvature), -1 outside, each mesh value
+    being the average of the indicator over its cell (sub x sub points; only
+    cells the strip's edge crosses need more than their centre)."""
+    X, Y = grid(N0, L)
+    h = L / N0
+    phi = -np.ones((N0, N0))
+    r = np.hypot(X - L / 2, Y - L / 2)
+    ci, cj = np.nonzero(np.abs(r - 3.0) < 0.45)
+    d = _curve_distance(X[ci, cj], Y[ci, cj], eps, L)
+    inner = d < R - h
+    phi[ci[inner], cj[inner]] = 1.0
+    edge = np.abs(d - R) <= h
+    ei, ej = ci[edge], cj[edge]
+    o = (np.arange(sub) + 0.5) / sub - 0.5
+    ox, oy = np.meshgrid(o * h, o * h, indexing="xy")
+    px = (X[ei, ej][:, None] + ox.ravel()[None, :]).ravel()
+    py = (Y[ei, ej][:, None] + oy.ravel()[None, :]).ravel()
+    inside = (_curve_distance(px, py, eps, L) < R).reshape(len(ei), sub * sub)
+    phi[ei, ej] = 2.0 * inside.mean(axis=1) - 1.0
+    return phi
+
+
+def paper_initial_data(name: str, N: int = None, eps: float = 0.1, physical_k: bool = False,
+                       d: float = None):
+    """u^0_N = phi_256 + eps d / alpha_m(0)^2 (eq. dcoef) for a benchmark of
+    Table t:Benchmark.  phi_256 = F[phi_Gamma]: the DFT of the strip indicator
+    on the 256 mesh times exp(-lambda0 (k1^2 + k2^2)), summed as a
+    trigonometric polynomial and evaluated on the N x N grid (N >= 256).  The
+    filter takes the integer mode indices k1, k2 literally; physical_k uses the
+    wavenumbers 2 pi k / L instead.  d overrides the benchmark's background
+    parameter.  Returns (model keyword arguments, u0)."""
+    b = PAPER_BENCHMARKS[name]
+    d = b["d"] if d is None else d
+    N = N or b["N"]
+    N0 = PAPER_N0
+    if N < N0 or N % N0:
+        raise ValueError("N must be a multiple of %d" % N0)
+    phi = paper_strip_indicator(N0, eps)
+    ph = np.fft.fft2(phi)
+    k = np.fft.fftfreq(N0, d=1.0 / N0)           # integer indices -N0/2 .. N0/2-1
+    if physical_k:
+        k = k * 2 * np.pi / PAPER_L
+    ph *= np.exp(-PAPER_LAMBDA0 * (k[:, None] ** 2 + k[None, :] ** 2))
+    # zero-pad to N (the Nyquist row and column split evenly between +-N0/2)
+    big = np.zeros((N, N), complex)
+    h = N0 // 2
+    idx = np.concatenate([np.arange(h), np.arange(N - h, N)])
+    src = np.concatenate([np.arange(h), np.arange(N0 - h, N0)])
+    big[np.ix_(idx, idx)] = ph[np.ix_(src, src)]
+    if N > N0:
+        ny = big[N - h, :].copy()
+        big[N - h, :] = 0.5 * ny
+        big[h, :] = 0.5 * ny
+        nx = big[:, N - h].copy()
+        big[:, N - h] = 0.5 * nx
+        big[:, h] = 0.5 * nx
+    phiN = np.real(np.fft.ifft2(big)) * (N / N0) ** 2
+    u0 = phiN + eps * d / PAPER_ALPHA0 ** 2
+    kw = dict(N=N, L=PAPER_L, eps=eps, eta1=b["eta1"], eta2=b["eta2"], q=b["q"])
+    return kw, u0
+
+
 # ---- named workloads -------------------------------------------------------
 def workload(name: str, seed: int = 0):
     """(model keyword arguments, physical initial state) of a named workload.

@@ -138,3 +138,28 @@ def test_ensemble_step_queues_without_waiting(F):
             b, kb, mb = ref.member(i)
             assert ma["done"] and ma["accepted"] == mb["accepted"], (use_graph, i)
             assert torch.equal(a, b) and np.array_equal(ka, kb), (use_graph, i)
+
+
+def test_running_max_of_u(F):
+    """Each member's umax is the running maximum of u over its accepted states
+    (the trial evaluation's row pass records the largest u per workgroup and
+    the controller folds it in on acceptance), checked one attempt at a time
+    against the inverse transform of the member's current state."""
+    log("ensemble running max of u")
+    mem = members_small()[:3]
+    ens = build(F, mem, use_max=30)
+    plans = {m["N"]: F.Plan(**m) for m in mem}
+    run_max = [-np.inf] * len(mem)
+    last = [1] * len(mem)
+    for _ in range(40):
+        ens.step(1, use_graph=False)
+        for i, m in enumerate(mem):
+            uh, _, mi = ens.member(i, klog=False)
+            if mi["accepted"] > last[i]:
+                run_max[i] = max(run_max[i], float(plans[m["N"]].inverse(uh).max()))
+                last[i] = mi["accepted"]
+            if run_max[i] == -np.inf:
+                assert mi["umax"] == -np.inf
+            else:
+                assert abs(mi["umax"] - run_max[i]) <= 1e-12 * abs(run_max[i]), (i, mi, run_max[i])
+    assert all(np.isfinite(run_max))

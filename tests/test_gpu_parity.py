@@ -242,6 +242,43 @@ def test_sav_trajectory(F, orc):
     assert rel(host(b), states[-2]) < 1e-8
 
 
+def test_sav_fused_chain(F, orc):
+    """fch_run's fixed-step SAV chain keeps r on the device (the column pass
+    after each SAV step solves for r^{n+1} in every workgroup and starts the
+    next step); it matches a loop of fch_step_sav calls and the oracle's
+    states and scalars."""
+    log("sav fused chain c1 40 steps")
+    plan, m, uh0 = _c1(orc, F)
+    k = 1e-3
+    r0 = float(np.sqrt(orc.E1(m, uh0) + m.D0))
+    o_m, o_n = None, uh0
+    rm = rn = r0
+    for i in range(40):
+        new, rnew = orc.sav_step(m, o_n, o_m, rn, rm, k, -1.0 if i == 0 else k)
+        o_m, o_n = o_n, new
+        rm, rn = rn, rnew
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    info = plan.run(a, b, scheme="sav", nsteps=40, k=k)
+    assert rel(host(a), o_n) < 1e-8 and rel(host(b), o_m) < 1e-8
+    assert abs(info["rs"][0] - rn) < 1e-10 * abs(rn)
+    assert abs(info["rs"][1] - rm) < 1e-10 * abs(rm)
+    # the same steps one call at a time
+    x, y = dev(uh0), None
+    qn = qm = plan.sav_r(dev(uh0))
+    for i in range(40):
+        z, qnew = plan.step_sav(x, y if y is not None else x, qn, qm, k, -1.0 if i == 0 else k)
+        y, x = x, z
+        qm, qn = qn, qnew
+    assert rel(host(a), host(x)) < 1e-13 and rel(host(b), host(y)) < 1e-13
+    assert abs(info["rs"][0] - qn) < 1e-13 * abs(qn) and abs(info["rs"][1] - qm) < 1e-13 * abs(qm)
+    # continuing a run (rs in/out, k_prev = k) equals one longer run
+    a2, b2 = dev(uh0), torch.zeros_like(dev(uh0))
+    i1 = plan.run(a2, b2, scheme="sav", nsteps=25, k=k)
+    i2 = plan.run(a2, b2, scheme="sav", nsteps=15, k=k, k_prev=k, startup=False, rs=i1["rs"])
+    assert rel(host(a2), host(a)) < 1e-13
+    assert abs(i2["rs"][0] - info["rs"][0]) < 1e-13 * abs(info["rs"][0])
+
+
 # ---- PSD --------------------------------------------------------------------
 def test_psd_fixed_iterations_and_converged(F, orc):
     log("psd c1")
@@ -415,7 +452,7 @@ def test_long_trajectory_256_stays_on_oracle(F, orc):
 @pytest.mark.parametrize("N", [16, 64, 256, 512, 1024, 2048])
 def test_every_launch_variant(F, orc, N):
     """Each compiled row-pass and column-pass variant gives the oracle's
-    transforms and IMEX step."""
+    transforms, IMEX step and ETDRK2 step."""
     log("launch variants N=%d" % N)
     rows, cols = F.config_list(N)
     L = N * 4 * np.pi / 256
@@ -425,6 +462,7 @@ def test_every_launch_variant(F, orc, N):
     uh0 = orc.r2c(u0)
     u1 = orc.imex_step(m, uh0, None, 1e-3, -1.0)
     ref = orc.imex_step(m, u1, uh0, 1e-3, 1e-3)
+    ref_etd = orc.etd_step(m, u1, 1e-3)
     for i in range(max(len(rows), len(cols))):
         r, c = rows[i % len(rows)], cols[i % len(cols)]
         plan.set_config((r[0], r[1], r[2], c[0], c[1]))
@@ -437,6 +475,7 @@ def test_every_launch_variant(F, orc, N):
         a, b = dev(u1), dev(uh0)
         plan.run(a, b, scheme="imex", nsteps=1, k=1e-3, k_prev=1e-3, startup=False)
         assert rel(host(a), ref) < 1e-10, (r, c)
+        assert rel(host(plan.step_etd(dev(u1), 1e-3)), ref_etd) < 1e-10, (r, c)
 
 
 def test_autotune_picks_a_compiled_variant(F, orc):

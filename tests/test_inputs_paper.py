@@ -1,0 +1,56 @@
+"""The paper's benchmark initial data (Sec. 2.3, eq. dcoef, Table t:Benchmark):
+ * the initial masses printed in Table t:Benchmark (6.11, 7.61, 6.93, 6.11,
+   6.11), to their printed rounding;
+ * mass differences between benchmarks equal |Omega| eps (d1 - d0) / (2 alpha_m(0)^2)
+   exactly (the filter keeps the mean);
+ * the strip area equals 2 R times the length of Gamma (the area between the
+   offset curves of a closed curve whose curvature radius exceeds R);
+ * the 512 and 1024 grids are spectral interpolations of the 256 data (equal at
+   the shared points)."""
+import numpy as np
+import pytest
+
+from paper_2006_04784_amd import inputs
+
+
+def _mass(kw, u0):
+    h = kw["L"] / kw["N"]
+    return 0.5 * h * h * float(np.sum(u0 + 1.0))
+
+
+@pytest.fixture(scope="module")
+def ics():
+    return {name: inputs.paper_initial_data(name) for name in inputs.PAPER_BENCHMARKS}
+
+
+def test_table_masses(ics):
+    for name, (kw, u0) in ics.items():
+        assert abs(_mass(kw, u0) - inputs.PAPER_BENCHMARKS[name]["mass"]) <= 0.005, name
+
+
+def test_mass_differences_are_exact(ics):
+    base_kw, base = ics["sub-critical"]
+    m0 = _mass(base_kw, base)
+    for name, (kw, u0) in ics.items():
+        dd = inputs.PAPER_BENCHMARKS[name]["d"] - inputs.PAPER_BENCHMARKS["sub-critical"]["d"]
+        pred = 0.5 * inputs.PAPER_L ** 2 * 0.1 * dd / inputs.PAPER_ALPHA0 ** 2
+        assert abs(_mass(kw, u0) - m0 - pred) < 1e-10, name
+
+
+def test_strip_area_is_2R_times_length():
+    th = np.linspace(0.0, 2 * np.pi, 200001)
+    x, y = inputs.paper_curve(th)
+    length = float(np.sum(np.hypot(np.diff(x), np.diff(y))))
+    phi = inputs.paper_strip_indicator()
+    h = inputs.PAPER_L / inputs.PAPER_N0
+    area = h * h * float(np.sum(phi + 1.0)) / 2
+    assert abs(area - 2 * inputs.PAPER_R * length) < 2e-3 * area, (area, length)
+
+
+@pytest.mark.parametrize("N", [512, 1024])
+def test_finer_grids_interpolate(ics, N):
+    _, u256 = ics["sub-critical"]
+    kw, u = inputs.paper_initial_data("sub-critical", N=N)
+    s = N // 256
+    assert np.max(np.abs(u[::s, ::s] - u256)) < 1e-12
+    assert abs(_mass(kw, u) - _mass(dict(kw, N=256), u256)) < 1e-10
