@@ -298,6 +298,18 @@ def main():
                 "bytes_per_transform": fft_bytes}
             del U, Uh, ws
     if not args.no_extra:
+        # the critical-d sweep of Sec. 5.1 (Table f:defect-onsetR): 206 members of the
+        # critical benchmark (256^2, the paper's initial data), adaptive IMEX at
+        # sigma_tol 1e-5 to T = 250 in one batched ensemble
+        log("critical-d sweep: 206 members to T = 250")
+        from paper_2006_04784_amd import sweeps
+        sw = sweeps.critical_d_sweep(sweeps.paper_d_values(), sigma_tol=1e-5, t_end=250.0)
+        extra["critical_d_sweep"] = {
+            "scheme": "imex", "sigma_tol": 1e-5, "members": len(sw["d"]), "t_end": 250.0,
+            "d_critical": sw["d_critical"], "d_max_without_defect": sw["d_max_without_defect"],
+            "paper_d_critical_imex": 0.7540, "seconds": round(sw["seconds"], 2),
+            "accepted_steps": int(sum(sw["accepted"])),
+            "accepted_steps_per_s": round(sum(sw["accepted"]) / sw["seconds"], 1)}
         # batched ensemble: 64 adaptive IMEX runs of mixed size in captured graphs
         log("ensemble of 64 mixed-size adaptive runs")
         rng = np.random.default_rng(2024)

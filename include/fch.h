@@ -330,6 +330,7 @@ typedef struct {
     double  t_end;       /* end time of every member                              */
     int64_t max_steps;   /* cap on accepted steps per member (startup included)   */
     double  k_first;     /* first-order startup step; <= 0 selects adapt.k_min    */
+    double  umax_t0;     /* umax counts the accepted states at t >= umax_t0        */
 } fch_ensemble_opts;
 typedef struct { int64_t attempts, accepted, rejected; int32_t active; } fch_ensemble_info;
 typedef struct {
@@ -337,8 +338,8 @@ typedef struct {
     int64_t accepted, rejected;
     double  t, k_last, k_next, err;
     double  umax;   /* running max of u over the accepted states after the startup
-                       step (-inf before the first); the defect-onset indicator of
-                       Sec. 5.1 and Table f:defect-onsetR */
+                       step at t >= opts.umax_t0 (-inf before the first); the
+                       defect-onset indicator of Sec. 5.1 and Table f:defect-onsetR */
 } fch_member_info;
 /* Host-side setup: one plan (twiddles, launch variants) per size class on the
  * current device.  members: count parameter sets (N in 16..2048). */

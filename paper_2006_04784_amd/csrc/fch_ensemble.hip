@@ -140,7 +140,8 @@ fch_status fch_ensemble_create(const fch_params* members, int32_t count,
   if (!members || count < 1 || !opts || !out) return FCH_E_INVALID;
   const fch_adapt_opts& ad = opts->adapt;
   if (!(ad.sigma_tol > 0.0) || !(ad.k_min > 0.0) || !(ad.k_max >= ad.k_min) ||
-      !(ad.rho_s > 0.0) || std::isnan(ad.cap) || !(opts->t_end > 0.0) || opts->max_steps < 2)
+      !(ad.rho_s > 0.0) || std::isnan(ad.cap) || !(opts->t_end > 0.0) || opts->max_steps < 2 ||
+      std::isnan(opts->umax_t0))
     return FCH_E_INVALID;
   for (int i = 0; i < count; ++i) SCHK(fch::validate_params_internal(&members[i]));
   fch_ensemble_s* e = new (std::nothrow) fch_ensemble_s;
@@ -263,6 +264,7 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   m.rejected = 0;
   m.max_accepted = e->opts.max_steps;
   m.umax = -INFINITY;
+  m.umax_t0 = e->opts.umax_t0;
   fch::StepCtl& v = m.ctl;
   std::memset(&v, 0, sizeof(v));
   v.sigma_tol = e->opts.adapt.sigma_tol;

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
     m->t += kt;
     if (m->accepted < m->klog_cap) m->klog[m->accepted] = kt;
     m->accepted += 1;
-    m->umax = fmax(m->umax, um);
+    if (m->t >= m->umax_t0) m->umax = fmax(m->umax, um);
     ctl.k_n = kt;
   } else {
     m->rejected += 1;

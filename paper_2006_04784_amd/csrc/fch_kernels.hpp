@@ -115,6 +115,7 @@ struct EnsMember {
   double* cpart;  // 2 per column
   double* umaxpart;  // N slots: largest u per row workgroup of the trial evaluation (-inf unused)
   double umax;       // running max of u over the accepted states after the startup step
+  double umax_t0;    // ... at t >= umax_t0
   double* klog;   // accepted step sizes
   long long klog_cap;
   int cur, prev, trial, fn, fm, ft;

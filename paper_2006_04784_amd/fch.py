@@ -86,7 +86,7 @@ class fch_run_info(C.Structure):
 
 class fch_ensemble_opts(C.Structure):
     _fields_ = [("adapt", fch_adapt_opts), ("t_end", C.c_double), ("max_steps", C.c_int64),
-                ("k_first", C.c_double)]
+                ("k_first", C.c_double), ("umax_t0", C.c_double)]
 
 
 class fch_ensemble_info(C.Structure):
@@ -543,7 +543,7 @@ class Ensemble:
     members: list of dicts of Plan keyword arguments (N, L, eps, eta1, eta2, ...)."""
 
     def __init__(self, members, adapt: AdaptOpts = None, t_end=1.0, max_steps=1000, k_first=0.0,
-                 device="cuda:0"):
+                 device="cuda:0", umax_t0=0.0):
         self.device = torch.device(device)
         prms = []
         for kw in members:
@@ -558,7 +558,7 @@ class Ensemble:
         arr = (fch_params * len(prms))(*prms)
         self.Ns = [m["N"] for m in members]
         self.max_steps = max_steps
-        opts = fch_ensemble_opts((adapt or AdaptOpts()).c(), t_end, max_steps, k_first)
+        opts = fch_ensemble_opts((adapt or AdaptOpts()).c(), t_end, max_steps, k_first, umax_t0)
         h = _V()
         with torch.cuda.device(self.device):
             _check(lib().fch_ensemble_create(arr, len(prms), C.byref(opts), C.byref(h)))

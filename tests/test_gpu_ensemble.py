@@ -163,3 +163,17 @@ def test_running_max_of_u(F):
             else:
                 assert abs(mi["umax"] - run_max[i]) <= 1e-12 * abs(run_max[i]), (i, mi, run_max[i])
     assert all(np.isfinite(run_max))
+
+
+def test_defect_onset_dichotomy(F):
+    """The critical benchmark (Table t:Benchmark) with the paper's initial data
+    below and above the onset of defects (Sec. 5.1): after the initial
+    relaxation the maximum of u sits at the bilayer's peak, which the paper
+    puts at u = 0.3566, or near a defect's, about 0.74."""
+    log("defect onset dichotomy, critical benchmark 256^2")
+    from paper_2006_04784_amd import sweeps
+    res = sweeps.critical_d_sweep([0.745, 0.775], sigma_tol=1e-5, t_end=60.0, t0=45.0)
+    lo, hi = res["umax"]
+    assert abs(lo - 0.3566) < 0.005, res
+    assert 0.70 < hi < 0.80, res
+    assert res["d_critical"] == 0.775 and res["d_max_without_defect"] == 0.745
