@@ -457,11 +457,16 @@ static void extrapolate(const oracle_params* P, const cplx* un, const cplx* um,
     for (size_t i = 0; i < m; ++i) ustar[i] = (g == 0.0) ? un[i] : un[i] + g * (un[i] - um[i]);
 }
 
-/* The IMEX nonlinearity N_IMEX = mu - L_IMEX u (eqs. e:IMEX-op, IMEX) as a half
- * spectrum, written out term by term:
+/* The IMEX nonlinearity N = mu - L u (eqs. e:IMEX-op, IMEX) as a half spectrum,
+ * for the linear part L = eps^4 Lap^2 - beta1 alpha eps^2 Lap + beta2 alpha^2 of
+ * eq. e:SAV-L0, which is (eps^2 Lap - alpha)^2 at beta = (2, 1).  Written out
+ * term by term:
  *   N = eps^2 (alpha - W'') Lap u + eps^2 Lap(alpha u - W') + W'' W'
- *       - alpha^2 u + eps^2 eta1 Lap u - eta2 W' */
-static void imex_nonlin(const oracle_params* P, const cplx* uh, cplx* Nh) {
+ *       - alpha^2 u + eps^2 eta1 Lap u - eta2 W'
+ *       + (beta1 - 2) alpha eps^2 Lap u + (1 - beta2) alpha^2 u
+ * (the last line vanishes at beta = (2, 1)). */
+static void imex_nonlin(const oracle_params* P, const cplx* uh, double beta1, double beta2,
+                        cplx* Nh) {
     int N = P->N, H = N / 2 + 1;
     size_t n = nphys(P), m = nspec(P);
     double al = oracle_alpha_m(P);
@@ -474,6 +479,8 @@ static void imex_nonlin(const oracle_params* P, const cplx* uh, cplx* Nh) {
     for (size_t i = 0; i < n; ++i) {
         t1[i] = e2 * (al - f.W2[i] + eta1) * f.lap[i] + f.W2[i] * f.W1[i] - al * al * f.u[i]
               - eta2 * f.W1[i];
+        if (beta1 != 2.0 || beta2 != 1.0)
+            t1[i] += (beta1 - 2.0) * al * e2 * f.lap[i] + (1.0 - beta2) * al * al * f.u[i];
         t2[i] = al * f.u[i] - f.W1[i];
     }
     cplx* T1 = malloc(m * sizeof(cplx));
@@ -490,7 +497,9 @@ static void imex_nonlin(const oracle_params* P, const cplx* uh, cplx* Nh) {
 }
 
 /* BDF2-IMEX (eqs. IMEX, IMEX-eq):
- * (a - Lap L_IMEX) u^{n+1} = -b u^n - c u^{n-1} + Lap N_IMEX(u*). */
+ * (a - Lap L) u^{n+1} = -b u^n - c u^{n-1} + Lap N(u*), with L = L_IMEX at the
+ * default beta = (2, 1) and the stabilized L_0 of eq. e:SAV-L0 otherwise (the
+ * paper's IMEX family of Figure Find-Beta). */
 int oracle_imex_step(const oracle_params* P, const double* uh_n_, const double* uh_nm1_,
                      double k_np1, double k_n, const double* fh_, double* uh_np1_) {
     int N = P->N, H = N / 2 + 1;
@@ -507,13 +516,13 @@ int oracle_imex_step(const oracle_params* P, const double* uh_n_, const double* 
     cplx* us = malloc(m * sizeof(cplx));
     extrapolate(P, un, um, k_np1, k_n, us);
     cplx* Nh = malloc(m * sizeof(cplx));
-    imex_nonlin(P, us, Nh);
+    imex_nonlin(P, us, P->beta1, P->beta2, Nh);
     cplx* tmp = malloc(m * sizeof(cplx));
     for (int ky = 0; ky < N; ++ky)
         for (int kx = 0; kx < H; ++kx) {
             size_t i = (size_t)ky * H + kx;
             double k2 = k2_at(P, ky, kx);
-            double Lh = e2 * e2 * k2 * k2 + 2.0 * al * e2 * k2 + al * al;
+            double Lh = e2 * e2 * k2 * k2 + P->beta1 * al * e2 * k2 + P->beta2 * al * al;
             cplx rhs = -b * un[i] - (c != 0.0 ? c * um[i] : 0.0) - k2 * Nh[i];
             if (fh) rhs += fh[i];
             tmp[i] = rhs / (a + k2 * Lh);
@@ -752,7 +761,7 @@ static void etd_N(const oracle_params* P, const cplx* uh, double kappa0, double 
     size_t m = nspec(P);
     double e2 = P->eps * P->eps;
     cplx* Ni = malloc(m * sizeof(cplx));
-    imex_nonlin(P, uh, Ni);
+    imex_nonlin(P, uh, 2.0, 1.0, Ni);   /* eq. ETD-L takes L_IMEX itself */
     for (int ky = 0; ky < N; ++ky)
         for (int kx = 0; kx < H; ++kx) {
             size_t i = (size_t)ky * H + kx;

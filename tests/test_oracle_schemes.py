@@ -71,9 +71,11 @@ def _linear_setup(orc, N=32, L=2 * np.pi, eps=0.2, q=0.0):
     return m, X, Y, modes
 
 
-@pytest.mark.parametrize("scheme", ["imex", "psd"])
-def test_linear_regime_recurrence(orc, scheme):
+@pytest.mark.parametrize("scheme,beta", [("imex", (2.0, 1.0)), ("imex", (1.0, 2.0)),
+                                         ("imex", (2.75, 0.25)), ("psd", (2.0, 1.0))])
+def test_linear_regime_recurrence(orc, scheme, beta):
     m, X, Y, modes = _linear_setup(orc)
+    m.beta1, m.beta2 = beta
     eps, al = m.eps, orc.alpha_m(m)
     eta1, eta2 = m.eta1 * eps, m.eta2 * eps
     delta = 1e-7
@@ -100,7 +102,11 @@ def test_linear_regime_recurrence(orc, scheme):
         Lk = (eps * eps * k2 + al) ** 2
         vs = an + g * (an - am)
         if scheme == "imex":
-            pred = (-b * an - c * am + k2 * (eps * eps * eta1 * k2 + eta2 * al) * vs) / (a + k2 * Lk)
+            # linearized mu about b_-: [(eps^2 k2 + alpha)^2 - eps^2 eta1 k2 - eta2 alpha] v,
+            # split as L_0(beta) v + the explicit remainder
+            L0 = (eps * eps * k2) ** 2 + beta[0] * al * eps * eps * k2 + beta[1] * al * al
+            expl = Lk - eps * eps * eta1 * k2 - eta2 * al - L0
+            pred = (-b * an - c * am - k2 * expl * vs) / (a + k2 * L0)
         else:
             sigma = Lk - eps * eps * eta1 * k2 - eta2 * al
             pred = (-b * an - c * am) / (a + k2 * sigma)
@@ -116,8 +122,12 @@ def _c1(orc):
     return m, orc.r2c(u0)
 
 
-def test_sav_minus_imex_identity(orc):
+@pytest.mark.parametrize("beta", [(2.0, 1.0), (1.0, 2.0), (0.5, 2.5)])
+def test_sav_minus_imex_identity(orc, beta):
+    """With the same stabilized L_0(beta) (eq. e:SAV-L0) in both schemes, SAV with
+    r^{n+1} = s* is the IMEX step, so u_SAV - u_IMEX = (xi - 1) s* q."""
     m, uh0 = _c1(orc)
+    m.beta1, m.beta2 = beta
     k = 1e-3
     u1 = orc.imex_step(m, uh0, None, k, -1.0)
     r0 = float(np.sqrt(orc.E1(m, uh0) + m.D0))
