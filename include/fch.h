@@ -65,7 +65,8 @@ typedef struct {
     double  q;                 /* well regularization q >= 0 (eq. e:Wq-def)         */
     double  gamma_w;           /* well asymmetry gamma (0.3)                        */
     double  b_minus, b_plus;   /* well minima (-1, +1)                              */
-    double  beta1, beta2;      /* SAV stabilization of L_0 (eq. e:SAV-L0), (2, 1)   */
+    double  beta1, beta2;      /* stabilization of L_0 (eq. e:SAV-L0) in SAV and IMEX,
+                                  (2, 1) = L_IMEX                                    */
     double  zeta, D0;          /* SAV splitting constant (eq. 4.1) and energy shift
                                   D_0 > -min E_1 (Sec. 3.5); see fch_sav_constants */
 } fch_params;
@@ -184,8 +185,11 @@ fch_status fch_chem_potential(fch_plan_t plan, const fch_c128* uh, fch_c128* muh
  * NULL.  uh_np1 may alias uh_nm1. */
 
 /* BDF2-IMEX (eqs. e:IMEX-op, IMEX, Richardson, IMEX-eq):
- * (a + |k|^2 L_IMEX) u^{n+1} = -b u^n - c u^{n-1} - |k|^2 (mu(u*) - L_IMEX u*),
- * L_IMEX = (eps^2 |k|^2 + alpha_m)^2, u* = u^n + (k_np1/k_n)(u^n - u^{n-1}). */
+ * (a + |k|^2 L) u^{n+1} = -b u^n - c u^{n-1} - |k|^2 (mu(u*) - L u*),
+ * u* = u^n + (k_np1/k_n)(u^n - u^{n-1}), with the stabilized
+ * L = L_0 = eps^4 |k|^4 + beta1 alpha_m eps^2 |k|^2 + beta2 alpha_m^2 of eq. e:SAV-L0
+ * (the plan's beta1, beta2), which is L_IMEX = (eps^2 |k|^2 + alpha_m)^2 at the
+ * default beta = (2, 1); other values give the IMEX family of Figure Find-Beta. */
 fch_status fch_step_imex(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
                          double k_np1, double k_n, fch_c128* uh_np1);
 

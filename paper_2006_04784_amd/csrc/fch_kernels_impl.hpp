@@ -461,7 +461,8 @@ __device__ __forceinline__ void epi_point(const Consts& c, const StepCtl* ctl, d
   } else if constexpr (EPI == EPI_F) {
     o0 = cscale(mu, -k2);
   } else if constexpr (EPI == EPI_IMEX) {
-    const double Lk = (e2k2 + c.alpha) * (e2k2 + c.alpha);
+    // L_0(beta) of eq. e:SAV-L0; L_IMEX = (eps^2 |k|^2 + alpha)^2 at beta = (2, 1)
+    const double Lk = e2k2 * e2k2 + c.beta1 * c.alpha * e2k2 + c.beta2 * c.alpha * c.alpha;
     const cd Nh = csub(mu, cscale(U, Lk));
     const double inv = 1.0 / (ctl->a + k2 * Lk);
     o0 = cd{(-ctl->b * un.x - ctl->c * um.x - k2 * Nh.x) * inv,

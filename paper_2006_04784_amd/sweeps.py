@@ -1,5 +1,7 @@
-"""Critical background level of defect onset (Sec. 5.1, Table f:defect-onsetR)
-as one batched ensemble.
+"""Studies of the paper's benchmarks on the GPU path: the critical background
+level of defect onset (Sec. 5.1, Table f:defect-onsetR) as one batched
+ensemble or by bisection, FFT calls against the stabilization beta
+(Figure Find-Beta), and fixed-step temporal convergence (Table tab:rates).
 
 The critical benchmark of Table t:Benchmark is run for a range of the
 initial-data parameter d (eq. dcoef), one ensemble member per value, with
@@ -129,6 +131,65 @@ def critical_d_bisect(scheme, sigma_tol, ds=None, threshold=DEFECT_THRESHOLD, lo
             "seconds": time.perf_counter() - tw}
 
 
+def beta_sweep(scheme="sav", beta1s=(0.25, 0.5, 1.0, 1.5, 2.0, 2.5, 2.75), benchmarks=None,
+               t_end=10.0, sigma_tol=1e-5, max_steps=200000, device="cuda:0", log=None):
+    """FFT calls to reach t_end for the paper's benchmarks (Table t:Benchmark,
+    their initial data) against the stabilization beta_1 of L_0 with
+    beta_2 = 3 - beta_1 (Sec. 3.5, eq. e:SAV-L0), adaptive at sigma_tol.
+    Runs that hit max_steps accepted steps are marked capped."""
+    benchmarks = benchmarks or list(inputs.PAPER_BENCHMARKS)
+    out = {}
+    tw = time.perf_counter()
+    for name in benchmarks:
+        kw, u0 = inputs.paper_initial_data(name)
+        rows = []
+        for b1 in beta1s:
+            plan = fch.Plan(**kw, beta1=b1, beta2=3.0 - b1, device=device)
+            a = plan.forward(torch.from_numpy(np.ascontiguousarray(u0)).to(plan.device))
+            b = torch.empty_like(a)
+            plan.reset_stats()
+            t1 = time.perf_counter()
+            info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=t_end,
+                            k_first=1e-9, nsteps=max_steps,
+                            adapt=fch.AdaptOpts(sigma_tol=sigma_tol))
+            row = {"beta1": b1, "beta2": 3.0 - b1, "fft_calls": plan.stats()["fft_calls"],
+                   "accepted": info["accepted"], "rejected": info["rejected"],
+                   "t": info["t"], "capped": info["t"] < t_end * (1 - 1e-12),
+                   "seconds": round(time.perf_counter() - t1, 3)}
+            rows.append(row)
+            if log:
+                log("%s %s beta1 %.2f: %d FFT calls, %d steps%s, %.1f s" %
+                    (scheme, name, b1, row["fft_calls"], row["accepted"],
+                     " (capped)" if row["capped"] else "", time.perf_counter() - tw))
+            plan.close()
+        out[name] = rows
+    return out
+
+
+def temporal_convergence(name="sub-critical", T=0.32, ks=None, schemes=("psd", "imex", "sav", "etd"),
+                         ref_steps=1024, device="cuda:0"):
+    """Fixed-step errors at time T from a benchmark's initial data against a
+    fine BDF2-PSD reference (T / ref_steps, i_tol 1e-12), the comparison of
+    Table tab:rates.  Returns {scheme: [relative L2 errors]} and the ks."""
+    ks = list(ks or [0.08 / 2 ** j for j in range(7)])
+    kw, u0 = inputs.paper_initial_data(name)
+    plan = fch.Plan(**kw, device=device)
+    uh0 = plan.forward(torch.from_numpy(np.ascontiguousarray(u0)).to(plan.device))
+
+    def run(scheme, k, tol=1e-12):
+        a, b = uh0.clone(), torch.empty_like(uh0)
+        plan.run(a, b, scheme=scheme, nsteps=int(round(T / k)), k=k, psd_tol=tol,
+                 psd_max_iter=5000, psd_lambda=1.0)
+        return plan.inverse(a)
+
+    ref = run("psd", T / ref_steps)
+    nref = float(torch.linalg.norm(ref))
+    out = {"T": T, "k": ks}
+    for sch in schemes:
+        out[sch] = [float(torch.linalg.norm(run(sch, k) - ref)) / nref for k in ks]
+    return out
+
+
 def paper_d_values():
     """The paper's sweep: d = 0.7523, 0.7524, ..., 0.7728."""
     return [round(0.7523 + 1e-4 * i, 4) for i in range(206)]
@@ -149,7 +210,21 @@ if __name__ == "__main__":
                     help="ensemble-imex (all d at once) or imex / sav / psd / etd (bisection)")
     ap.add_argument("--psd-tol", type=float, default=1e-3)
     ap.add_argument("--k-max", type=float, default=float("inf"))
+    ap.add_argument("--beta-sweep", action="store_true",
+                    help="FFT calls to --t-end against beta_1 (beta_2 = 3 - beta_1) instead")
+    ap.add_argument("--max-steps", type=int, default=50000)
+    ap.add_argument("--rates", action="store_true",
+                    help="fixed-step errors at T = 0.32 against a fine PSD reference instead")
     args = ap.parse_args()
+    if args.rates:
+        print(json.dumps(temporal_convergence()))
+        sys.exit(0)
+    if args.beta_sweep:
+        sch = "sav" if args.scheme == "ensemble-imex" else args.scheme
+        print(json.dumps(beta_sweep(sch, t_end=args.t_end, sigma_tol=args.sigma,
+                                    max_steps=args.max_steps,
+                                    log=lambda m: print(m, file=sys.stderr, flush=True))))
+        sys.exit(0)
     ds = [d for d in paper_d_values()
           if (args.d_min is None or d >= args.d_min) and (args.d_max is None or d <= args.d_max)]
     err = lambda m: print(m, file=sys.stderr, flush=True)

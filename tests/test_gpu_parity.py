@@ -138,6 +138,25 @@ def test_imex_one_step_and_startup(F, orc):
     assert rel(host(b), u2_ref) < 1e-10
 
 
+@pytest.mark.parametrize("beta", [(1.0, 2.0), (2.75, 0.25)])
+def test_imex_stabilized_family(F, orc, beta):
+    """IMEX with the stabilized L_0(beta) of eq. e:SAV-L0 (Figure Find-Beta's
+    family) against the oracle: one step and a 50-step trajectory."""
+    log("imex beta=%s c1" % (beta,))
+    kw, u0 = inputs.workload("c1")
+    kw = dict(kw, zeta=1.1, D0=163.0, beta1=beta[0], beta2=beta[1])
+    plan, m = pair(F, orc, **kw)
+    uh0 = orc.r2c(u0)
+    u1_ref = orc.imex_step(m, uh0, None, 1e-3, -1.0)
+    u2_ref = orc.imex_step(m, u1_ref, uh0, 1.5e-3, 1e-3)
+    u2 = plan.step_imex(dev(u1_ref), dev(uh0), 1.5e-3, 1e-3)
+    assert rel(host(u2), u2_ref) < 1e-10
+    ref = orc.run_fixed(m, "imex", uh0, 1e-3, 50)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.run(a, b, scheme="imex", nsteps=50, k=1e-3)
+    assert rel(host(a), ref) < 1e-8
+
+
 def test_imex_trajectory_c1_200_steps(F, orc):
     log("imex trajectory c1 200 steps")
     plan, m, uh0 = _c1(orc, F)
@@ -739,3 +758,22 @@ def test_c2_adaptive_imex_and_sav_512(F, orc):
                 o_prev, o_cur, ro_prev, rc = o_cur, nxt, rc, rn
             assert abs(rc - rs[0]) < 1e-9 * abs(rc)
         assert rel(host(cur), o_cur) < 1e-8, scheme
+
+
+def test_temporal_convergence_on_paper_data(F):
+    """Fixed-step errors at T = 0.32 on the sub-critical benchmark's initial data
+    (256^2) against a fine PSD reference, the comparison of Table tab:rates:
+    every scheme converges at second order, PSD is the most accurate, SAV's
+    errors equal IMEX's, and ETDRK2's are the largest at equal k."""
+    log("temporal convergence, sub-critical 256^2")
+    from paper_2006_04784_amd import sweeps
+    ks = [0.01, 0.005, 0.0025, 0.00125]
+    r = sweeps.temporal_convergence(ks=ks)
+    rate = lambda e: [np.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
+    for sch in ("psd", "imex", "sav"):
+        assert min(rate(r[sch])) > 1.75, (sch, r[sch])
+    assert rate(r["etd"])[-1] > 1.5, r["etd"]
+    for i in range(len(ks)):
+        assert r["psd"][i] < 0.1 * r["imex"][i]
+        assert abs(r["sav"][i] - r["imex"][i]) < 0.02 * r["imex"][i]
+        assert r["etd"][i] > 2.0 * r["imex"][i]
