@@ -1,7 +1,8 @@
 """Studies of the paper's benchmarks on the GPU path: the critical background
 level of defect onset (Sec. 5.1, Table f:defect-onsetR) as one batched
 ensemble or by bisection, FFT calls against the stabilization beta
-(Figure Find-Beta), and fixed-step temporal convergence (Table tab:rates).
+(Figure Find-Beta), fixed-step temporal convergence (Table tab:rates) and the
+schemes' final states compared (Table t:Comp-error).
 
 The critical benchmark of Table t:Benchmark is run for a range of the
 initial-data parameter d (eq. dcoef), one ensemble member per value, with
@@ -190,6 +191,68 @@ def temporal_convergence(name="sub-critical", T=0.32, ks=None, schemes=("psd", "
     return out
 
 
+# Table tolPSD: the PSD tolerance ratio nu (i_tol = nu * sigma_tol, Sec. 3.3) and the
+# optimal k_max per q
+PSD_SETTINGS = {0.0: (1e-3, 0.05), 0.2: (2e-5, 0.02), 0.5: (1e-6, 0.01)}
+# Table t:Comp-error: final time per benchmark
+COMP_T = {"sub-critical": 250.0, "critical": 250.0, "super-critical": 250.0, "foot-1": 50.0,
+          "foot-2": 50.0}
+
+
+def scheme_comparison(benchmarks=None, sigma_tol=1e-5, schemes=("psd", "imex", "sav", "etd"),
+                      device="cuda:0", log=None, max_steps=5000000):
+    """Each scheme, adaptive at sigma_tol, from a benchmark's initial data to
+    its final time of Table t:Comp-error (PSD with i_tol = nu sigma_tol and k_max
+    of Table tolPSD; ETDRK2 only for the q = 0 benchmarks, as in the paper), and the
+    relative L2 differences of the final states: the quantities of Table
+    t:Comp-error.  Returns {benchmark: {"runs": {...}, "diff": {...}}}."""
+    benchmarks = benchmarks or list(COMP_T)
+    out = {}
+    tw = time.perf_counter()
+    for name in benchmarks:
+        kw, u0 = inputs.paper_initial_data(name)
+        plan = fch.Plan(**kw, device=device)
+        uh0 = plan.forward(torch.from_numpy(np.ascontiguousarray(u0)).to(plan.device))
+        nu, kmax = PSD_SETTINGS[kw["q"]]
+        finals, runs = {}, {}
+        for sch in schemes:
+            if sch == "etd" and kw["q"] != 0.0:
+                continue
+            a, b = uh0.clone(), torch.empty_like(uh0)
+            plan.reset_stats()
+            t1 = time.perf_counter()
+            try:
+                info = plan.run(a, b, scheme=sch, adaptive=True, startup=True,
+                                t_end=COMP_T[name], k_first=1e-9, nsteps=max_steps,
+                                psd_tol=nu * sigma_tol,
+                                psd_max_iter=20000,
+                                adapt=fch.AdaptOpts(sigma_tol=sigma_tol,
+                                                    k_max=kmax if sch == "psd" else float("inf")))
+            except fch.FchError as ex:   # e.g. a PSD solve that missed its tolerance
+                runs[sch] = {"error": str(ex)}
+                if log:
+                    log("%s %s: %s" % (name, sch, ex))
+                continue
+            finals[sch] = plan.inverse(a)
+            runs[sch] = {"accepted": info["accepted"], "rejected": info["rejected"],
+                         "t": info["t"], "fft_calls": plan.stats()["fft_calls"],
+                         "psd_iters": info["psd_iters"], "max_u": float(finals[sch].max()),
+                         "seconds": round(time.perf_counter() - t1, 2)}
+            if log:
+                log("%s %s: %d steps, %d FFT calls, max u %.3f, %.1f s" %
+                    (name, sch, info["accepted"], runs[sch]["fft_calls"], runs[sch]["max_u"],
+                     time.perf_counter() - tw))
+        diff = {}
+        pairs = [("imex", "psd"), ("sav", "psd"), ("sav", "imex"), ("etd", "psd")]
+        for x, y in pairs:
+            if x in finals and y in finals:
+                diff["%s/%s" % (x, y)] = float(torch.linalg.norm(finals[x] - finals[y]) /
+                                             torch.linalg.norm(finals[y]))
+        out[name] = {"T": COMP_T[name], "runs": runs, "diff": diff}
+        plan.close()
+    return out
+
+
 def paper_d_values():
     """The paper's sweep: d = 0.7523, 0.7524, ..., 0.7728."""
     return [round(0.7523 + 1e-4 * i, 4) for i in range(206)]
@@ -208,16 +271,23 @@ if __name__ == "__main__":
     ap.add_argument("--d-max", type=float, default=None)
     ap.add_argument("--scheme", default="ensemble-imex",
                     help="ensemble-imex (all d at once) or imex / sav / psd / etd (bisection)")
-    ap.add_argument("--psd-tol", type=float, default=1e-3)
+    ap.add_argument("--psd-nu", type=float, default=1e-3,
+                    help="PSD stopping tolerance i_tol = nu * sigma (Table tolPSD: 1e-3 at q = 0)")
     ap.add_argument("--k-max", type=float, default=float("inf"))
     ap.add_argument("--beta-sweep", action="store_true",
                     help="FFT calls to --t-end against beta_1 (beta_2 = 3 - beta_1) instead")
     ap.add_argument("--max-steps", type=int, default=50000)
+    ap.add_argument("--compare", action="store_true",
+                    help="all schemes on the five benchmarks to their final times instead")
     ap.add_argument("--rates", action="store_true",
                     help="fixed-step errors at T = 0.32 against a fine PSD reference instead")
     args = ap.parse_args()
     if args.rates:
         print(json.dumps(temporal_convergence()))
+        sys.exit(0)
+    if args.compare:
+        print(json.dumps(scheme_comparison(sigma_tol=args.sigma,
+                                           log=lambda m: print(m, file=sys.stderr, flush=True))))
         sys.exit(0)
     if args.beta_sweep:
         sch = "sav" if args.scheme == "ensemble-imex" else args.scheme
@@ -233,5 +303,5 @@ if __name__ == "__main__":
         res["sigma_tol"] = args.sigma
     else:
         res = critical_d_bisect(args.scheme, args.sigma, ds, log=err, t_end=args.t_end,
-                                t0=args.t0, k_max=args.k_max, psd_tol=args.psd_tol)
+                                t0=args.t0, k_max=args.k_max, psd_tol=args.psd_nu * args.sigma)
     print(json.dumps(res))
