@@ -253,7 +253,8 @@ fch_status fch_rhs(fch_plan_t plan, const fch_c128* uh, fch_c128* Fh);
 
 /* ---- the steps with device-resident scalars (graph-capturable) ------------
  * Same operations as fch_step_imex / fch_step_sav / fch_step_psd /
- * fch_adapt_dt (same kernels; results bit-identical for the same values),
+ * fch_step_etd / fch_adapt_dt (same kernels; results bit-identical for the
+ * same values),
  * but every per-step scalar is read from device memory when the launched
  * kernels run, every scalar result is written to device memory, and nothing
  * allocates, synchronizes or copies to the host.  A sequence of these calls
@@ -281,6 +282,11 @@ fch_status fch_step_sav_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c12
 fch_status fch_step_psd_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
                             const double* k_dev, const fch_c128* guess,
                             const fch_psd_opts* opts, fch_c128* uh_np1, int32_t* iters_dev,
+                            int32_t* status_dev);
+/* ETDRK2 step of fch_step_etd with k = k_dev[0] read on the device (k_dev[1]
+ * is not read); status_dev as above. */
+fch_status fch_step_etd_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* F_n,
+                            const double* k_dev, const fch_etd_opts* opts, fch_c128* uh_np1,
                             int32_t* status_dev);
 fch_status fch_adapt_dt_dev(fch_plan_t plan, const fch_c128* uh_trial, const fch_c128* uh_n,
                             const fch_c128* F_n, const fch_c128* F_nm1, const double* k_dev,

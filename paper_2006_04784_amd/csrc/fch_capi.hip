@@ -3,6 +3,7 @@
 // each call (which kernels run, in which order, on which buffers).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <utility>
 #include <cstdint>
@@ -348,6 +349,9 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
   bool ok = hipMalloc((void**)&p->tw, sizeof(cd) * N) == hipSuccess &&
             hipMalloc((void**)&p->ctl, sizeof(StepCtl)) == hipSuccess &&
             hipHostMalloc((void**)&p->hctl, sizeof(StepCtl), hipHostMallocDefault) == hipSuccess &&
+            hipMalloc((void**)&p->dmem, sizeof(fch::EnsMember)) == hipSuccess &&
+            hipHostMalloc((void**)&p->hmem, sizeof(fch::EnsMember), hipHostMallocDefault) ==
+                hipSuccess &&
             hipMemcpy(p->tw, htw, sizeof(cd) * N, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemset(p->ctl, 0, sizeof(StepCtl)) == hipSuccess;
   delete[] htw;
@@ -427,6 +431,8 @@ fch_status fch_plan_destroy(fch_plan_t p) {
   if (p->tw) (void)hipFree(p->tw);
   if (p->ctl) (void)hipFree(p->ctl);
   if (p->hctl) (void)hipHostFree(p->hctl);
+  if (p->dmem) (void)hipFree(p->dmem);
+  if (p->hmem) (void)hipHostFree(p->hmem);
   delete p;
   return FCH_OK;
 }
@@ -882,13 +888,10 @@ StepCtl etd_ctl(double k, double kappa0, double kappa2) {
 }
 }  // namespace
 
-fch_status fch_step_etd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* F_n, double k,
-                        const fch_etd_opts* opts, fch_c128* uh_np1) {
-  if (!p || !uh_n || !uh_np1 || !finite_pos(k)) return FCH_E_INVALID;
-  double k0, k2;
-  CHK(etd_opts(opts, &k0, &k2));
-  CHK(need_ws(p));
-  CHK(ctl_set(p, etd_ctl(k, k0, k2)));
+namespace {
+// the launches of one step once the control block holds k, kappa0, kappa2
+fch_status etd_step_launch(fch_plan_s* p, const fch_c128* uh_n, const fch_c128* F_n,
+                           fch_c128* uh_np1) {
   const cd* un = (const cd*)uh_n;
   if (F_n) {
     CHK(etd_first_cached(p, un, (const cd*)F_n, p->st));
@@ -901,6 +904,17 @@ fch_status fch_step_etd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* F_n,
   CHK(etd_second(p, p->st, (cd*)uh_np1, false));
   p->stats.steps += 1;
   return FCH_OK;
+}
+}  // namespace
+
+fch_status fch_step_etd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* F_n, double k,
+                        const fch_etd_opts* opts, fch_c128* uh_np1) {
+  if (!p || !uh_n || !uh_np1 || !finite_pos(k)) return FCH_E_INVALID;
+  double k0, k2;
+  CHK(etd_opts(opts, &k0, &k2));
+  CHK(need_ws(p));
+  CHK(ctl_set(p, etd_ctl(k, k0, k2)));
+  return etd_step_launch(p, uh_n, F_n, uh_np1);
 }
 
 // ---- adaptivity -----------------------------------------------------------
@@ -1050,6 +1064,21 @@ fch_status fch_step_psd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   CHK(psd_iterations(p, a, 0, limit));
   p->stats.steps += 1;
   return ctl_out(p, fch::OUT_PSD, nullptr, iters_dev, status_dev);
+}
+
+fch_status fch_step_etd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* F_n,
+                            const double* k_dev, const fch_etd_opts* opts, fch_c128* uh_np1,
+                            int32_t* status_dev) {
+  if (!p || !uh_n || !uh_np1 || !k_dev) return FCH_E_INVALID;
+  double k0, k2;
+  CHK(etd_opts(opts, &k0, &k2));
+  CHK(need_ws(p));
+  StepCtl v = ctl_zero();
+  v.kappa0 = k0;
+  v.kappa2 = k2;
+  CHK(ctl_dev(p, v, k_dev, nullptr, fch::CTL_K1_ONLY));
+  CHK(etd_step_launch(p, uh_n, F_n, uh_np1));
+  return ctl_out(p, fch::OUT_STATUS, nullptr, nullptr, status_dev);
 }
 
 fch_status fch_adapt_dt_dev(fch_plan_t p, const fch_c128* uh_trial, const fch_c128* uh_n,
@@ -1388,6 +1417,84 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   }
   const double t_end = o->t_end;
   const int64_t max_acc = o->nsteps > 0 ? o->nsteps : INT64_MAX;
+  if (o->scheme == FCH_IMEX && !p->prof_on) {
+    // Attempts under device control: the run is described as one ensemble
+    // member (state and F slots, time, step scalars) and each attempt is the
+    // batched kernels' sequence with the per-member controller, which accepts
+    // or rejects, rotates the slots and sets the next attempt's scalars.  The
+    // host only reads the member back between chunks of queued attempts
+    // (attempts queued after the run ended return at once).
+    fch::EnsMember& m = *p->hmem;
+    std::memset(&m, 0, sizeof(m));
+    m.c = p->c;
+    m.tw = p->tw;
+    m.ring[0] = cur;
+    m.ring[1] = prev;
+    m.ring[2] = spare;
+    m.fring[0] = Fn;
+    m.fring[1] = Fm;
+    m.fring[2] = Ft;
+    m.P0 = p->P0;
+    m.P1 = p->P1;
+    m.cpart = p->cpart;
+    m.umaxpart = p->rpart;  // N slots; never folded into umax (umax_t0 = inf)
+    m.umax = -INFINITY;
+    m.umax_t0 = INFINITY;
+    m.klog = nullptr;
+    m.klog_cap = 0;
+    m.cur = 0;
+    m.prev = 1;
+    m.trial = 2;
+    m.fn = 0;
+    m.fm = 1;
+    m.ft = 2;
+    m.t = t;
+    m.t_end = t_end;
+    m.accepted = inf.accepted;
+    m.rejected = 0;
+    m.max_accepted = max_acc;
+    m.H = p->H;
+    StepCtl& v = m.ctl;
+    set_adapt(v, ad);
+    if (kt > t_end - t) kt = t_end - t;
+    set_bdf2(v, kt, k_n);
+    set_am3(v, kt, k_n);
+    v.done = (t >= t_end * (1.0 - 1e-14) || inf.accepted >= max_acc) ? 1 : 0;
+    HIPCHK(hipMemcpyAsync(p->dmem, &m, sizeof(m), hipMemcpyHostToDevice, p->stream));
+    int64_t before = m.accepted + m.rejected;
+    while (!m.ctl.done) {
+      const int64_t left = max_acc - m.accepted;
+      const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(32, left));
+      for (int i = 0; i < chunk; ++i) {
+        HIPCHK(p->cv->col_ens(fch::ENS_PRO, p->dmem, 0, 1, p->stream));
+        HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 0, p->stream));
+        HIPCHK(p->cv->col_ens(fch::ENS_IMEX, p->dmem, 0, 1, p->stream));
+        HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 1, p->stream));
+        HIPCHK(p->cv->col_ens(fch::ENS_AM3, p->dmem, 0, 1, p->stream));
+        HIPCHK(fch::launch_ens_control(p->dmem, 0, 1, p->stream));
+      }
+      p->stats.launches += 6LL * chunk;
+      HIPCHK(hipMemcpyAsync(&m, p->dmem, sizeof(m), hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      if (m.ctl.nonfinite) return FCH_E_NONFINITE;
+    }
+    const int64_t attempts = m.accepted + m.rejected - before;
+    p->stats.fft_calls += 8 * attempts;
+    p->stats.rejected += m.rejected;
+    cur = m.ring[m.cur];
+    prev = m.ring[m.prev];
+    inf.accepted = m.accepted;
+    inf.rejected = m.rejected;
+    inf.t = m.t;
+    inf.k_last = m.ctl.k_n;
+    inf.k_next = m.ctl.k_next;
+    CHK(settle(p, B0, B1, cur, prev));
+    if (info) {
+      inf.fft_calls = p->stats.fft_calls;
+      *info = inf;
+    }
+    return FCH_OK;
+  }
   while (t < t_end * (1.0 - 1e-14) && inf.accepted < max_acc) {
     if (kt > t_end - t) kt = t_end - t;
     double r_new = 0.0;

@@ -182,7 +182,8 @@ hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s)
 // invalid; the PSD kernels then do nothing.
 __global__ void k_ctl_dev(StepCtl* ctl, StepCtl v, const double* k_dev, const double* r_dev,
                           double q, int flags) {
-  const double k1 = k_dev[0], k0 = k_dev[1];
+  // CTL_K1_ONLY: a one-step method reads only k_dev[0]
+  const double k1 = k_dev[0], k0 = (flags & CTL_K1_ONLY) ? 0.0 : k_dev[1];
   set_bdf2(v, k1, k0);
   if (flags & CTL_AM3) set_am3(v, k1, k0);
   if (flags & CTL_SAV) {

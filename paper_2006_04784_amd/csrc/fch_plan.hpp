@@ -22,6 +22,10 @@ struct fch_plan_s {
   double *rpart, *cpart;
   fch_stats stats;
   int psd_hint;
+  // device-controlled adaptive IMEX (fch_run): the run described as one
+  // ensemble member, in device memory, with a pinned mirror
+  fch::EnsMember* dmem;
+  fch::EnsMember* hmem;
   // kernel timing (fch_plan_profile)
   int prof_on;
   int prof_n;

@@ -138,6 +138,7 @@ _SIGS = {
     "fch_chem_potential": (_I, [_V, _V, _V, _PD]),
     "fch_step_imex": (_I, [_V, _V, _V, _D, _D, _V]),
     "fch_step_etd": (_I, [_V, _V, _V, _D, C.POINTER(fch_etd_opts), _V]),
+    "fch_step_etd_dev": (_I, [_V, _V, _V, _V, C.POINTER(fch_etd_opts), _V, _V]),
     "fch_step_sav": (_I, [_V, _V, _V, _D, _D, _D, _D, _V, _PD]),
     "fch_sav_r": (_I, [_V, _V, _PD]),
     "fch_step_psd": (_I, [_V, _V, _V, _D, _D, _V, C.POINTER(fch_psd_opts), _V,
@@ -502,6 +503,18 @@ class Plan:
         self._sync_stream()
         _check(lib().fch_step_psd_dev(self.h, _p(uh_n), _p(uh_nm1), _p(k_dev), _p(guess),
                                       C.byref(o), _p(out), _p(iters_dev), _p(status_dev)))
+        return out
+
+    def step_etd_dev(self, uh_n, k_dev, out, F_n=None, status_dev=None, kappa0=ETD_KAPPA0,
+                     kappa2=ETD_KAPPA2):
+        self._chk_spec(uh_n, F_n, out)
+        self._chk_dev(k_dev, 1, torch.float64)
+        if status_dev is not None:
+            self._chk_dev(status_dev, 1, torch.int32)
+        o = fch_etd_opts(kappa0, kappa2)
+        self._sync_stream()
+        _check(lib().fch_step_etd_dev(self.h, _p(uh_n), _p(F_n), _p(k_dev), C.byref(o),
+                                      _p(out), _p(status_dev)))
         return out
 
     def adapt_dt_dev(self, uh_trial, uh_n, F_n, F_nm1, k_dev, out, out_dev, status_dev=None,

@@ -515,8 +515,8 @@ def test_autotune_picks_a_compiled_variant(F, orc):
 
 # ---- device-scalar (graph-capturable) steps ---------------------------------
 def test_dev_steps_equal_host_steps(F, orc):
-    """fch_step_imex_dev / _sav_dev / _psd_dev / fch_adapt_dt_dev read their
-    scalars from device memory and equal the host-scalar calls bit for bit."""
+    """fch_step_imex_dev / _sav_dev / _psd_dev / _etd_dev / fch_adapt_dt_dev read
+    their scalars from device memory and equal the host-scalar calls bit for bit."""
     log("device-scalar steps c1")
     plan, m, uh0 = _c1(orc, F)
     k = 1e-3
@@ -551,6 +551,15 @@ def test_dev_steps_equal_host_steps(F, orc):
     o = out.cpu().numpy()
     assert torch.equal(Ft, Ftd) and o[0] == float(acc) and o[1] == kn and o[2] == err
     assert int(st.item()) == 0
+    # ETDRK2, with and without a cached F(u^n)
+    e1 = plan.step_etd(u1, 1.7 * k)
+    e1d = plan.step_etd_dev(u1, d(1.7 * k), plan.spec(), status_dev=st)
+    assert torch.equal(e1, e1d) and int(st.item()) == 0
+    e2 = plan.step_etd(u1, 1.7 * k, F_n=Fn)
+    e2d = plan.step_etd_dev(u1, d(1.7 * k), plan.spec(), F_n=Fn, status_dev=st)
+    assert torch.equal(e2, e2d) and int(st.item()) == 0
+    plan.step_etd_dev(u1, d(0.0), plan.spec(), status_dev=st)
+    assert int(st.item()) == -1
     # invalid scalars are reported on the device
     plan.step_imex_dev(u1, a0, d(-1.0, k), plan.spec(), st)
     assert int(st.item()) == -1
@@ -777,3 +786,51 @@ def test_temporal_convergence_on_paper_data(F):
         assert r["psd"][i] < 0.1 * r["imex"][i]
         assert abs(r["sav"][i] - r["imex"][i]) < 0.02 * r["imex"][i]
         assert r["etd"][i] > 2.0 * r["imex"][i]
+
+
+def test_adaptive_imex_device_control_matches_host_loop(F, orc):
+    """fch_run's adaptive IMEX runs its attempts under device control (the
+    ensemble's batched kernels and per-member controller on a one-member
+    view of the plan); with kernel timing on it falls back to the host loop.
+    Both take the same decisions and reach the same state; the step limit
+    and the final time are honoured exactly."""
+    log("adaptive imex: device control vs host loop")
+    N, L = 256, 4 * np.pi
+    plan, m = pair(F, orc, **model_kw(N, L))
+    uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=4))
+    opts = F.AdaptOpts(sigma_tol=1e-5)
+    res = []
+    for prof in (False, True):
+        plan.profile(prof)
+        a, b = dev(uh0), torch.zeros_like(dev(uh0))
+        info = plan.run(a, b, scheme="imex", adaptive=True, startup=True, t_end=0.05,
+                        nsteps=100000, adapt=opts)
+        res.append((host(a), host(b), info))
+        if prof:
+            plan.profile_read()
+            plan.profile(False)
+    (a0, b0, i0), (a1, b1, i1) = res
+    assert i0["accepted"] == i1["accepted"] and i0["rejected"] == i1["rejected"]
+    assert abs(i0["t"] - 0.05) < 1e-15 and abs(i1["t"] - 0.05) < 1e-15
+    # the error estimate is a small difference of states, so rounding differences
+    # between the two kernel sets (FMA contraction) reach it at about 1e-11
+    assert abs(i0["k_next"] - i1["k_next"]) <= 1e-9 * i1["k_next"]
+    assert rel(a0, a1) < 1e-12 and rel(b0, b1) < 1e-12
+    # a step limit stops the run after exactly that many accepted steps
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    info = plan.run(a, b, scheme="imex", adaptive=True, startup=True, t_end=10.0, nsteps=37,
+                    adapt=opts)
+    assert info["accepted"] == 37 and info["t"] < 10.0
+
+
+def test_psd_iterations_match_table_tolPSD(F):
+    """Adaptive BDF2-PSD on the sub-critical benchmark's initial data (256^2,
+    sigma_tol 1e-5, i_tol = nu sigma_tol with nu = 1e-3 and k_max = 0.05 from
+    Table tolPSD, lambda from Table SearchSize) to T = 250: the total iteration
+    count lands within 15% of the 38.2 thousand the paper prints for q = 0 at
+    that k_max (its row spans 34.8k-41.4k over k_max)."""
+    log("psd iterations, sub-critical 256^2 to T = 250")
+    from paper_2006_04784_amd import sweeps
+    r = sweeps.scheme_comparison(["sub-critical"], schemes=("psd",))
+    it = r["sub-critical"]["runs"]["psd"]["psd_iters"]
+    assert abs(it - 38200) < 0.15 * 38200, it
