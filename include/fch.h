@@ -47,7 +47,7 @@ typedef struct { double re, im; } fch_c128;
 typedef enum {
     FCH_OK = 0,
     FCH_E_INVALID = -1,     /* bad argument (size, null pointer, E1 + D0 <= 0, ...) */
-    FCH_E_UNSUPPORTED = -2, /* N outside the supported powers of two 16..2048       */
+    FCH_E_UNSUPPORTED = -2, /* N outside the supported powers of two 16..4096       */
     FCH_E_HIP = -3,         /* a HIP runtime call failed                            */
     FCH_E_NOMEM = -4,       /* workspace missing or too small                        */
     FCH_E_NOCONV = -5,      /* PSD reached max_iter; last iterate and stats written  */
@@ -56,7 +56,7 @@ typedef enum {
 
 /* Model parameters (paper Table t:Benchmark notation). */
 typedef struct {
-    int32_t N;                 /* grid points per side: power of two, 16..2048      */
+    int32_t N;                 /* grid points per side: power of two, 16..4096      */
     double  L;                 /* side of the periodic square, > 0                  */
     double  eps;               /* interface width epsilon, > 0                      */
     double  eta1, eta2;        /* functionalization parameters as given             */
@@ -301,7 +301,8 @@ fch_status fch_adapt_dt_dev(fch_plan_t plan, const fch_c128* uh_trial, const fch
  * steps of size k (the startup step counts as one); adaptive runs follow
  * Sec. 3.2 until t_end or nsteps accepted steps.  *rs (SAV only, host in/out):
  * r^n, r^{n-1}.  info (nullable, host out).
- * FCH_ETD (ETDRK2 with opts->etd) is a one-step method: fixed runs take
+ * FCH_ETD (ETDRK2 with opts->etd, taken as given: zeros mean kappa0 = kappa2 = 0,
+ * not the paper's values) is a one-step method: fixed runs take
  * nsteps ETDRK2 steps and ignore startup and the entering uh_nm1.  Adaptive
  * ETD runs take the startup step as one ETDRK2 step of k_first without error
  * control (the estimate needs F^{n-1}), then follow Sec. 3.2 with the ETDRK2
@@ -352,7 +353,7 @@ typedef struct {
                        defect-onset indicator of Sec. 5.1 and Table f:defect-onsetR */
 } fch_member_info;
 /* Host-side setup: one plan (twiddles, launch variants) per size class on the
- * current device.  members: count parameter sets (N in 16..2048). */
+ * current device.  members: count parameter sets (N in 16..4096). */
 fch_status fch_ensemble_create(const fch_params* members, int32_t count,
                                const fch_ensemble_opts* opts, fch_ensemble_t* out);
 fch_status fch_ensemble_destroy(fch_ensemble_t ens);

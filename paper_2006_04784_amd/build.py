@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfch.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["fch_capi.hip", "fch_ensemble.hip", "fch_registry.hip", "fch_kern_small.hip", "fch_nn.hip"] + [
-    "fch_kern_n%d.hip" % n for n in (2048, 1024, 512, 256, 128, 64, 32, 16)]
+    "fch_kern_n%d.hip" % n for n in (4096, 2048, 1024, 512, 256, 128, 64, 32, 16)]
 
 
 def build(verbose: bool = True) -> str:

@@ -14,6 +14,7 @@ FCH_DECL(256)
 FCH_DECL(512)
 FCH_DECL(1024)
 FCH_DECL(2048)
+FCH_DECL(4096)
 #undef FCH_DECL
 
 static const RowVT* const* rows_for(int N, int* n) {
@@ -26,6 +27,7 @@ static const RowVT* const* rows_for(int N, int* n) {
     case 512: return row_variants_512(n);
     case 1024: return row_variants_1024(n);
     case 2048: return row_variants_2048(n);
+    case 4096: return row_variants_4096(n);
   }
   *n = 0;
   return nullptr;
@@ -40,6 +42,7 @@ static const ColVT* const* cols_for(int N, int* n) {
     case 512: return col_variants_512(n);
     case 1024: return col_variants_1024(n);
     case 2048: return col_variants_2048(n);
+    case 4096: return col_variants_4096(n);
   }
   *n = 0;
   return nullptr;

@@ -65,7 +65,7 @@ def test_sav_constants_reading(fch):
 def test_plan_create_rejects_bad_params_before_touching_the_device(fch):
     h = C.c_void_p()
     for kw, code in [(dict(N=48), fch.FCH_E_INVALID), (dict(N=8), fch.FCH_E_UNSUPPORTED),
-                     (dict(N=4096), fch.FCH_E_UNSUPPORTED), (dict(L=-1.0), fch.FCH_E_INVALID),
+                     (dict(N=8192), fch.FCH_E_UNSUPPORTED), (dict(L=-1.0), fch.FCH_E_INVALID),
                      (dict(eps=0.0), fch.FCH_E_INVALID), (dict(q=-0.1), fch.FCH_E_INVALID),
                      (dict(eta1=float("nan")), fch.FCH_E_INVALID)]:
         assert fch.lib().fch_plan_create(C.byref(_prm(fch, **kw)), C.byref(h)) == code, kw
@@ -73,7 +73,7 @@ def test_plan_create_rejects_bad_params_before_touching_the_device(fch):
 
 
 def test_compiled_configurations(fch):
-    for N in (16, 32, 64, 128, 256, 512, 1024, 2048):
+    for N in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
         rows, cols = fch.config_list(N)
         assert rows and cols, N
         for (R, rE, twl) in rows:
@@ -84,7 +84,7 @@ def test_compiled_configurations(fch):
         for (cE, ctw) in cols:
             assert N % cE == 0 and (cE == N or N >= cE * cE) and ctw in (0, 1)
             assert 2 * 16 * (N + N // 8 + 1) + 16 * N * ctw + 16 * (N // cE) <= 160 * 1024
-    assert fch.lib().fch_row_config_count(4096) == 0
+    assert fch.lib().fch_row_config_count(8192) == 0
     assert fch.lib().fch_col_config_count(100) == 0
     c = fch.fch_launch_cfg()
     assert fch.lib().fch_config_get(1024, 99, 0, C.byref(c)) == fch.FCH_E_UNSUPPORTED

@@ -834,3 +834,24 @@ def test_psd_iterations_match_table_tolPSD(F):
     r = sweeps.scheme_comparison(["sub-critical"], schemes=("psd",))
     it = r["sub-critical"]["runs"]["psd"]["psd_iters"]
     assert abs(it - 38200) < 0.15 * 38200, it
+
+
+def test_largest_grid_4096(F, orc):
+    """N = 4096, the largest supported grid (its fused column epilogues spill
+    registers): transforms, the fused IMEX chain (startup and one BDF2 step)
+    and an ETDRK2 step against the oracle."""
+    log("4096^2: transforms, IMEX chain, ETDRK2 step")
+    N, L = 4096, 64 * np.pi
+    kw = model_kw(N, L)
+    plan, m = pair(F, orc, **kw)
+    u0 = inputs.circle_bilayer(N, L, 0.1, seed=5)
+    uh0 = orc.r2c(u0)
+    uh = plan.forward(torch.from_numpy(u0).cuda())
+    assert rel(host(uh), uh0) < 1e-13
+    assert rel(plan.inverse(uh).cpu().numpy(), u0) < 1e-13
+    ref = orc.run_fixed(m, "imex", uh0, 1e-3, 2)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.run(a, b, scheme="imex", nsteps=2, k=1e-3)
+    assert rel(host(a), ref) < 1e-10
+    e = plan.step_etd(dev(uh0), 1e-3)
+    assert rel(host(e), orc.etd_step(m, uh0, 1e-3)) < 1e-10
