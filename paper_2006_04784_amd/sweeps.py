@@ -1,8 +1,9 @@
 """Studies of the paper's benchmarks on the GPU path: the critical background
 level of defect onset (Sec. 5.1, Table f:defect-onsetR) as one batched
 ensemble or by bisection, FFT calls against the stabilization beta
-(Figure Find-Beta), fixed-step temporal convergence (Table tab:rates) and the
-schemes' final states compared (Table t:Comp-error).
+(Figure Find-Beta), fixed-step temporal convergence (Table tab:rates), the
+schemes' final states compared (Table t:Comp-error) and grid refinement
+(Table t:GRE).
 
 The critical benchmark of Table t:Benchmark is run for a range of the
 initial-data parameter d (eq. dcoef), one ensemble member per value, with
@@ -253,6 +254,51 @@ def scheme_comparison(benchmarks=None, sigma_tol=1e-5, schemes=("psd", "imex", "
     return out
 
 
+def grid_refinement(benchmarks=None, sigma_tol=1e-5, pairs=None, device="cuda:0", log=None):
+    """Adaptive BDF2-PSD (i_tol = nu sigma_tol, k_max of Table tolPSD) from a
+    benchmark's initial data at N and 2N to its final time of Table
+    t:Comp-error; the absolute L2 difference h (sum over the N grid of
+    (u_N - u_2N)^2)^(1/2), u_2N taken at the shared points: the quantity of
+    Table t:GRE.  pairs: {benchmark: [(N, 2N), ...]}."""
+    benchmarks = benchmarks or list(COMP_T)
+    if pairs is None:
+        pairs = {b: [(256, 512)] for b in benchmarks}
+        if "foot-2" in pairs:     # the paper also refines foot-2 from 512 to 1024
+            pairs["foot-2"] = [(256, 512), (512, 1024)]
+    out = {}
+    tw = time.perf_counter()
+    cache = {}
+
+    def final(name, N):
+        if (name, N) in cache:
+            return cache[(name, N)]
+        kw, u0 = inputs.paper_initial_data(name, N=N)
+        plan = fch.Plan(**kw, device=device)
+        nu, kmax = PSD_SETTINGS[kw["q"]]
+        a = plan.forward(torch.from_numpy(np.ascontiguousarray(u0)).to(plan.device))
+        b = torch.empty_like(a)
+        info = plan.run(a, b, scheme="psd", adaptive=True, startup=True, t_end=COMP_T[name],
+                        k_first=1e-9, nsteps=5000000, psd_tol=nu * sigma_tol,
+                        psd_max_iter=20000, adapt=fch.AdaptOpts(sigma_tol=sigma_tol, k_max=kmax))
+        u = plan.inverse(a).cpu().numpy()
+        plan.close()
+        if log:
+            log("%s N=%d: %d steps, %d PSD iterations, %.1f s" %
+                (name, N, info["accepted"], info["psd_iters"], time.perf_counter() - tw))
+        cache[(name, N)] = u
+        return u
+
+    for name in benchmarks:
+        rows = []
+        for (n1, n2) in pairs[name]:
+            u1, u2 = final(name, n1), final(name, n2)
+            h = inputs.PAPER_L / n1
+            err = float(h * np.sqrt(np.sum((u1 - u2[::n2 // n1, ::n2 // n1]) ** 2)))
+            rows.append({"N": n1, "N2": n2, "abs_l2": err})
+        out[name] = rows
+    return out
+
+
 def paper_d_values():
     """The paper's sweep: d = 0.7523, 0.7524, ..., 0.7728."""
     return [round(0.7523 + 1e-4 * i, 4) for i in range(206)]
@@ -277,6 +323,9 @@ if __name__ == "__main__":
     ap.add_argument("--beta-sweep", action="store_true",
                     help="FFT calls to --t-end against beta_1 (beta_2 = 3 - beta_1) instead")
     ap.add_argument("--max-steps", type=int, default=50000)
+    ap.add_argument("--benchmarks", default="", help="comma-separated subset for --gre")
+    ap.add_argument("--gre", action="store_true",
+                    help="PSD grid refinement errors N vs 2N (Table t:GRE) instead")
     ap.add_argument("--compare", action="store_true",
                     help="all schemes on the five benchmarks to their final times instead")
     ap.add_argument("--rates", action="store_true",
@@ -284,6 +333,10 @@ if __name__ == "__main__":
     args = ap.parse_args()
     if args.rates:
         print(json.dumps(temporal_convergence()))
+        sys.exit(0)
+    if args.gre:
+        print(json.dumps(grid_refinement(args.benchmarks.split(",") if args.benchmarks else None,
+                                         log=lambda m: print(m, file=sys.stderr, flush=True))))
         sys.exit(0)
     if args.compare:
         print(json.dumps(scheme_comparison(sigma_tol=args.sigma,
