@@ -1417,7 +1417,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   }
   const double t_end = o->t_end;
   const int64_t max_acc = o->nsteps > 0 ? o->nsteps : INT64_MAX;
-  if (o->scheme == FCH_IMEX && !p->prof_on) {
+  if ((o->scheme == FCH_IMEX || o->scheme == FCH_ETD) && !p->prof_on) {
     // Attempts under device control: the run is described as one ensemble
     // member (state and F slots, time, step scalars) and each attempt is the
     // batched kernels' sequence with the per-member controller, which accepts
@@ -1436,6 +1436,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     m.fring[2] = Ft;
     m.P0 = p->P0;
     m.P1 = p->P1;
+    m.aux = p->aux;
     m.cpart = p->cpart;
     m.umaxpart = p->rpart;  // N slots; never folded into umax (umax_t0 = inf)
     m.umax = -INFINITY;
@@ -1459,16 +1460,19 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     if (kt > t_end - t) kt = t_end - t;
     set_bdf2(v, kt, k_n);
     set_am3(v, kt, k_n);
+    v.kappa0 = ka0;
+    v.kappa2 = ka2;
     v.done = (t >= t_end * (1.0 - 1e-14) || inf.accepted >= max_acc) ? 1 : 0;
+    const bool etd = (o->scheme == FCH_ETD);
     HIPCHK(hipMemcpyAsync(p->dmem, &m, sizeof(m), hipMemcpyHostToDevice, p->stream));
     int64_t before = m.accepted + m.rejected;
     while (!m.ctl.done) {
       const int64_t left = max_acc - m.accepted;
       const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(32, left));
       for (int i = 0; i < chunk; ++i) {
-        HIPCHK(p->cv->col_ens(fch::ENS_PRO, p->dmem, 0, 1, p->stream));
+        HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD_PRO : fch::ENS_PRO, p->dmem, 0, 1, p->stream));
         HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 0, p->stream));
-        HIPCHK(p->cv->col_ens(fch::ENS_IMEX, p->dmem, 0, 1, p->stream));
+        HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD2 : fch::ENS_IMEX, p->dmem, 0, 1, p->stream));
         HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 1, p->stream));
         HIPCHK(p->cv->col_ens(fch::ENS_AM3, p->dmem, 0, 1, p->stream));
         HIPCHK(fch::launch_ens_control(p->dmem, 0, 1, p->stream));

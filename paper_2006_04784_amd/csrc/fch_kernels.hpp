@@ -112,6 +112,7 @@ struct EnsMember {
   cd* fring[3];  // F = Lap mu of the states: slots fn, fm, ft
   cd* P0;
   cd* P1;
+  cd* aux;        // ETDRK2 attempts: w = u~ - k phi2 N(u^n) (u~ sits in fring[ft])
   double* cpart;  // 2 per column
   double* umaxpart;  // N slots: largest u per row workgroup of the trial evaluation (-inf unused)
   double umax;       // running max of u over the accepted states after the startup step
@@ -124,7 +125,8 @@ struct EnsMember {
   int H;
   int pad;
 };
-enum EnsStage { ENS_PRO = 0, ENS_IMEX = 1, ENS_AM3 = 2 };
+// IMEX attempt: PRO, row, IMEX, row, AM3; ETDRK2 attempt: ETD_PRO, row, ETD2, row, AM3
+enum EnsStage { ENS_PRO = 0, ENS_IMEX = 1, ENS_AM3 = 2, ENS_ETD_PRO = 3, ENS_ETD2 = 4 };
 
 // Launch tables of the compiled variants of one grid size.  Row-pass and
 // column-pass variants are chosen independently.

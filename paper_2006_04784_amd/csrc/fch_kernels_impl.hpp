@@ -931,7 +931,9 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
 }
 
 // one attempt of adaptive BDF2-IMEX: PRO (u* and Lap u* of the step),
-// IMEX (the step, then u~ and Lap u~ for F(u~)), AM3 (F(u~) and the error sums)
+// IMEX (the step, then u~ and Lap u~ for F(u~)), AM3 (F(u~) and the error sums);
+// of adaptive ETDRK2: ETD_PRO (first stage from the cached F(u^n)), ETD2 (the
+// step, then the trial's (u, Lap u)), AM3
 template <int N, int E, int TWL, int STAGE>
 __global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
   EnsMember* m = mem + first + blockIdx.y;
@@ -946,6 +948,19 @@ __global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
     a.s1 = m->ring[m->prev];
     a.out = m->ring[m->trial];
     col_body<N, E, EPI_IMEX, PRO_NEXT_FIELD, TWL>(a, &m->ctl.done);
+  } else if constexpr (STAGE == ENS_ETD_PRO) {
+    // u~ and w from u^n and the cached F(u^n); u~ goes to the F slot that the
+    // attempt's AM3 stage overwrites last
+    a.s0 = m->ring[m->cur];
+    a.f_n = m->fring[m->fn];
+    a.out = m->fring[m->ft];
+    a.aux = m->aux;
+    col_body<N, E, EPI_NONE, PRO_ETD1, TWL>(a, &m->ctl.done);
+  } else if constexpr (STAGE == ENS_ETD2) {
+    a.s0 = m->fring[m->ft];
+    a.s1 = m->aux;
+    a.out = m->ring[m->trial];
+    col_body<N, E, EPI_ETD2, PRO_NEXT_FIELD, TWL>(a, &m->ctl.done);
   } else {
     a.s0 = m->ring[m->trial];
     a.s1 = m->ring[m->cur];

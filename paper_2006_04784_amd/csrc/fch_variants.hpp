@@ -124,6 +124,12 @@ struct ColImpl {
       case ENS_AM3:
         hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_AM3>), grid, dim3(CT), 0, s, m, first);
         break;
+      case ENS_ETD_PRO:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_ETD_PRO>), grid, dim3(CT), 0, s, m, first);
+        break;
+      case ENS_ETD2:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_ETD2>), grid, dim3(CT), 0, s, m, first);
+        break;
       default:
         return hipErrorInvalidValue;
     }

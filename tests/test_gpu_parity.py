@@ -788,13 +788,14 @@ def test_temporal_convergence_on_paper_data(F):
         assert r["etd"][i] > 2.0 * r["imex"][i]
 
 
-def test_adaptive_imex_device_control_matches_host_loop(F, orc):
-    """fch_run's adaptive IMEX runs its attempts under device control (the
-    ensemble's batched kernels and per-member controller on a one-member
-    view of the plan); with kernel timing on it falls back to the host loop.
-    Both take the same decisions and reach the same state; the step limit
-    and the final time are honoured exactly."""
-    log("adaptive imex: device control vs host loop")
+@pytest.mark.parametrize("scheme", ["imex", "etd"])
+def test_adaptive_device_control_matches_host_loop(F, orc, scheme):
+    """fch_run's adaptive IMEX and ETDRK2 run their attempts under device
+    control (the ensemble's batched kernels and per-member controller on a
+    one-member view of the plan); with kernel timing on they fall back to
+    the host loop.  Both take the same decisions and reach the same state;
+    the step limit and the final time are honoured exactly."""
+    log("adaptive %s: device control vs host loop" % scheme)
     N, L = 256, 4 * np.pi
     plan, m = pair(F, orc, **model_kw(N, L))
     uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=4))
@@ -803,7 +804,7 @@ def test_adaptive_imex_device_control_matches_host_loop(F, orc):
     for prof in (False, True):
         plan.profile(prof)
         a, b = dev(uh0), torch.zeros_like(dev(uh0))
-        info = plan.run(a, b, scheme="imex", adaptive=True, startup=True, t_end=0.05,
+        info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=0.05,
                         nsteps=100000, adapt=opts)
         res.append((host(a), host(b), info))
         if prof:
@@ -818,7 +819,7 @@ def test_adaptive_imex_device_control_matches_host_loop(F, orc):
     assert rel(a0, a1) < 1e-12 and rel(b0, b1) < 1e-12
     # a step limit stops the run after exactly that many accepted steps
     a, b = dev(uh0), torch.zeros_like(dev(uh0))
-    info = plan.run(a, b, scheme="imex", adaptive=True, startup=True, t_end=10.0, nsteps=37,
+    info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=10.0, nsteps=37,
                     adapt=opts)
     assert info["accepted"] == 37 and info["t"] < 10.0
 
