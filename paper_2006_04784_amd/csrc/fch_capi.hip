@@ -1491,7 +1491,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     inf.rejected = m.rejected;
     inf.t = m.t;
     inf.k_last = m.ctl.k_n;
-    inf.k_next = m.ctl.k_next;
+    inf.k_next = attempts > 0 ? m.ctl.k_next : kt;  // no attempt: the first trial step
     CHK(settle(p, B0, B1, cur, prev));
     if (info) {
       inf.fft_calls = p->stats.fft_calls;

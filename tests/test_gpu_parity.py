@@ -822,6 +822,10 @@ def test_adaptive_device_control_matches_host_loop(F, orc, scheme):
     info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=10.0, nsteps=37,
                     adapt=opts)
     assert info["accepted"] == 37 and info["t"] < 10.0
+    # a run that ends with its startup step reports that step as the next trial
+    info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=1e-6, k_first=1e-6,
+                    adapt=opts)
+    assert info["accepted"] == 1 and info["k_next"] == 1e-6
 
 
 def test_psd_iterations_match_table_tolPSD(F):
