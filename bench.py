@@ -184,6 +184,17 @@ def main():
         extra["adaptive_imex_attempts_per_s"] = round(
             (info["accepted"] + info["rejected"]) / el, 1)
         extra["adaptive_imex_mean_step"] = info["t"] / max(info["accepted"], 1)
+        # adaptive SAV (the same control; r kept on the device)
+        a2, b2 = uh0.clone(), torch.empty_like(uh0)
+        plan.run(a2, b2, scheme="sav", adaptive=True, startup=True, t_end=1.0, nsteps=50,
+                 adapt=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = plan.run(a2, b2, scheme="sav", adaptive=True, startup=True, t_end=10.0,
+                        nsteps=300, adapt=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        extra["adaptive_sav_accepted_steps_per_s"] = round(info["accepted"] / el, 1)
         # ETDRK2 (Sec. 3.6): two chemical-potential evaluations (8 FFT calls,
         # 22 S of algorithmic traffic) per fixed step; adaptive attempts start
         # from the cached F(u^n) like IMEX's

@@ -1417,7 +1417,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   }
   const double t_end = o->t_end;
   const int64_t max_acc = o->nsteps > 0 ? o->nsteps : INT64_MAX;
-  if ((o->scheme == FCH_IMEX || o->scheme == FCH_ETD) && !p->prof_on) {
+  if ((o->scheme == FCH_IMEX || o->scheme == FCH_ETD || o->scheme == FCH_SAV) && !p->prof_on) {
     // Attempts under device control: the run is described as one ensemble
     // member (state and F slots, time, step scalars) and each attempt is the
     // batched kernels' sequence with the per-member controller, which accepts
@@ -1438,7 +1438,14 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     m.P1 = p->P1;
     m.aux = p->aux;
     m.cpart = p->cpart;
-    m.umaxpart = p->rpart;  // N slots; never folded into umax (umax_t0 = inf)
+    // rpart serves twice, in stream order: SAV's E_1 partials (first row pass,
+    // read by the SAV column pass), then the trial row pass's largest u per
+    // workgroup (reset by the controller; never folded into umax here)
+    m.rpart = p->rpart;
+    m.umaxpart = p->rpart;
+    m.sav = (o->scheme == FCH_SAV) ? 1 : 0;
+    m.rslot = 0;
+    m.nrow = p->N / p->rv->R;
     m.umax = -INFINITY;
     m.umax_t0 = INFINITY;
     m.klog = nullptr;
@@ -1457,11 +1464,16 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     m.H = p->H;
     StepCtl& v = m.ctl;
     set_adapt(v, ad);
+    const double kt_first = kt;  // reported as the next trial if no attempt runs
     if (kt > t_end - t) kt = t_end - t;
     set_bdf2(v, kt, k_n);
     set_am3(v, kt, k_n);
     v.kappa0 = ka0;
     v.kappa2 = ka2;
+    if (m.sav) {
+      v.rring[0] = rs[0];  // r^n
+      v.rring[2] = rs[1];  // r^{n-1}
+    }
     v.done = (t >= t_end * (1.0 - 1e-14) || inf.accepted >= max_acc) ? 1 : 0;
     const bool etd = (o->scheme == FCH_ETD);
     HIPCHK(hipMemcpyAsync(p->dmem, &m, sizeof(m), hipMemcpyHostToDevice, p->stream));
@@ -1472,15 +1484,25 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
       for (int i = 0; i < chunk; ++i) {
         HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD_PRO : fch::ENS_PRO, p->dmem, 0, 1, p->stream));
         HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 0, p->stream));
-        HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD2 : fch::ENS_IMEX, p->dmem, 0, 1, p->stream));
+        if (m.sav) {
+          HIPCHK(p->cv->col_ens(fch::ENS_SAV, p->dmem, 0, 1, p->stream));
+          HIPCHK(p->cv->col_ens(fch::ENS_SAV_FIELD, p->dmem, 0, 1, p->stream));
+        } else {
+          HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD2 : fch::ENS_IMEX, p->dmem, 0, 1, p->stream));
+        }
         HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 1, p->stream));
         HIPCHK(p->cv->col_ens(fch::ENS_AM3, p->dmem, 0, 1, p->stream));
         HIPCHK(fch::launch_ens_control(p->dmem, 0, 1, p->stream));
       }
-      p->stats.launches += 6LL * chunk;
+      p->stats.launches += (m.sav ? 7LL : 6LL) * chunk;
       HIPCHK(hipMemcpyAsync(&m, p->dmem, sizeof(m), hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));
       if (m.ctl.nonfinite) return FCH_E_NONFINITE;
+      if (m.ctl.invalid) return FCH_E_INVALID;
+    }
+    if (m.sav) {
+      rs[0] = m.ctl.rring[m.rslot];
+      rs[1] = m.ctl.rring[(m.rslot + 2) % 3];
     }
     const int64_t attempts = m.accepted + m.rejected - before;
     p->stats.fft_calls += 8 * attempts;
@@ -1491,7 +1513,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     inf.rejected = m.rejected;
     inf.t = m.t;
     inf.k_last = m.ctl.k_n;
-    inf.k_next = attempts > 0 ? m.ctl.k_next : kt;  // no attempt: the first trial step
+    inf.k_next = attempts > 0 ? m.ctl.k_next : kt_first;
     CHK(settle(p, B0, B1, cur, prev));
     if (info) {
       inf.fft_calls = p->stats.fft_calls;

@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
   const double e = sqrt(c0 / c1);
   const int accept = am3_decide(ctl, e);
   const double kn = ctl.k_next;
-  if (!isfinite(e)) {
-    ctl.nonfinite = 1;
+  if (!isfinite(e) || ctl.invalid) {  // invalid: SAV's E_1 + D_0 <= 0
+    if (!ctl.invalid) ctl.nonfinite = 1;
     ctl.done = 1;
     return;
   }
@@ -154,6 +154,7 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
     if (m->accepted < m->klog_cap) m->klog[m->accepted] = kt;
     m->accepted += 1;
     if (m->t >= m->umax_t0) m->umax = fmax(m->umax, um);
+    if (m->sav) m->rslot = (m->rslot + 1) % 3;  // r^{n+1} becomes r^n
     ctl.k_n = kt;
   } else {
     m->rejected += 1;

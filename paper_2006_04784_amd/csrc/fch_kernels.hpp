@@ -38,7 +38,8 @@ enum Pro {
   PRO_NEXT_EXTRAP,
   PRO_NEXT_FIELD,
   PRO_ETD1,
-  PRO_SAV_NEXT
+  PRO_SAV_NEXT,
+  PRO_SAV_FIELD
 };
 enum FinMode { FIN_SAV_S = 0, FIN_PSD, FIN_AM3, FIN_ENERGY };
 
@@ -81,7 +82,7 @@ struct ColArgs {
   // from which every workgroup forms s*; otherwise ctl->s_star is used
   const double* sav_rpart;
   int sav_nrow;
-  // PRO_SAV_NEXT: the column partial sums (g_p, g_q; sav_ncol pairs) of the
+  // PRO_SAV_NEXT / PRO_SAV_FIELD: the column partial sums (g_p, g_q; sav_ncol pairs) of the
   // SAV step, from which every workgroup solves for r^{n+1}; r^n and r^{n-1}
   // are ctl->rring[rslot] and ctl->rring[(rslot + 2) % 3], r^{n+1} goes to
   // ctl->rring[(rslot + 1) % 3]
@@ -112,7 +113,8 @@ struct EnsMember {
   cd* fring[3];  // F = Lap mu of the states: slots fn, fm, ft
   cd* P0;
   cd* P1;
-  cd* aux;        // ETDRK2 attempts: w = u~ - k phi2 N(u^n) (u~ sits in fring[ft])
+  cd* aux;        // ETDRK2 attempts: w = u~ - k phi2 N(u^n) (u~ sits in fring[ft]); SAV: q
+  double* rpart;  // SAV attempts: E_1 partial sums of the first row pass (2 per row workgroup)
   double* cpart;  // 2 per column
   double* umaxpart;  // N slots: largest u per row workgroup of the trial evaluation (-inf unused)
   double umax;       // running max of u over the accepted states after the startup step
@@ -120,13 +122,25 @@ struct EnsMember {
   double* klog;   // accepted step sizes
   long long klog_cap;
   int cur, prev, trial, fn, fm, ft;
+  int sav;    // SAV attempts: r^n = ctl.rring[rslot], r^{n-1} = ctl.rring[(rslot + 2) % 3]
+  int rslot;  // (the controller advances rslot on acceptance)
+  int nrow;   // row-pass workgroups (SAV: the E_1 partial pairs)
   double t, t_end;
   long long accepted, rejected, max_accepted;
   int H;
   int pad;
 };
-// IMEX attempt: PRO, row, IMEX, row, AM3; ETDRK2 attempt: ETD_PRO, row, ETD2, row, AM3
-enum EnsStage { ENS_PRO = 0, ENS_IMEX = 1, ENS_AM3 = 2, ENS_ETD_PRO = 3, ENS_ETD2 = 4 };
+// IMEX attempt: PRO, row, IMEX, row, AM3; ETDRK2 attempt: ETD_PRO, row, ETD2, row, AM3;
+// SAV attempt: PRO, row (E_1 partials), SAV, SAV_FIELD, row, AM3
+enum EnsStage {
+  ENS_PRO = 0,
+  ENS_IMEX = 1,
+  ENS_AM3 = 2,
+  ENS_ETD_PRO = 3,
+  ENS_ETD2 = 4,
+  ENS_SAV = 5,
+  ENS_SAV_FIELD = 6
+};
 
 // Launch tables of the compiled variants of one grid size.  Row-pass and
 // column-pass variants are chosen independently.

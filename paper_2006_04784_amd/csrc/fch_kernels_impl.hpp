@@ -545,7 +545,7 @@ __device__ __forceinline__ void load_pro(const ColArgs& a, size_t g, cd& s0v, cd
   gv = cd{0.0, 0.0};
   if constexpr (PRO == PRO_EXTRAP || PRO == PRO_PSD_INIT) s1v = a.s1[g];
   if constexpr (PRO == PRO_ETD1) s1v = a.f_n[g];
-  if constexpr (PRO == PRO_SAV_NEXT) {
+  if constexpr (PRO == PRO_SAV_NEXT || PRO == PRO_SAV_FIELD) {
     s1v = a.out[g];
     gv = a.aux[g];
   }
@@ -560,14 +560,16 @@ __device__ __forceinline__ void load_pro(const ColArgs& a, size_t g, cd& s0v, cd
 // writes b u^n + c u^{n-1} and the iterate), the ETDRK1 stage u~ from the
 // cached F(u^n) (ETD1 also writes u~ and w), or, after a SAV step, the
 // extrapolation of u^{n+1} = p + r^{n+1} q (eq. 4.8; SAV_NEXT writes u^{n+1}
-// over p; rr = r^{n+1}).  PRO_NEXT_*: unext.
+// over p; rr = r^{n+1}), or u^{n+1} itself (SAV_FIELD, for F of a trial
+// state).  PRO_NEXT_*: unext.
 template <int PRO>
 __device__ __forceinline__ cd pro_point(const ColArgs& a, const StepCtl* ctl, size_t g,
                                         double k2, bool mean_mode, cd s0v, cd s1v, cd gv,
                                         cd unext, double rr) {
-  if constexpr (PRO == PRO_SAV_NEXT) {
+  if constexpr (PRO == PRO_SAV_NEXT || PRO == PRO_SAV_FIELD) {
     const cd u1 = {fma(rr, gv.x, s1v.x), fma(rr, gv.y, s1v.y)};
     a.out[g] = u1;
+    if constexpr (PRO == PRO_SAV_FIELD) return u1;
     return cadd(u1, cscale(csub(u1, s0v), ctl->gamma));
   } else if constexpr (PRO == PRO_ETD1) {
     cd ut, w;
@@ -659,10 +661,10 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
     }
   }
 
-  // SAV_NEXT: r^{n+1} from the SAV step's partial sums (g_p, g_q), solved by
-  // every workgroup in the same order (eq. 4.8); workgroup 0 records it
+  // SAV_NEXT / SAV_FIELD: r^{n+1} from the SAV step's partial sums (g_p, g_q),
+  // solved by every workgroup in the same order (eq. 4.8); workgroup 0 records it
   double rnew = 0.0;
-  if constexpr (PRO == PRO_SAV_NEXT) {
+  if constexpr (PRO == PRO_SAV_NEXT || PRO == PRO_SAV_FIELD) {
     __shared__ double sh_r;
     double c0 = 0.0, c1 = 0.0;
     fixed_sum2<T>(a.sav_cpart, a.sav_ncol, c0, c1);
@@ -921,7 +923,7 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
   a.u_out = nullptr;
   a.X_in = nullptr;
   a.X_out = nullptr;
-  a.partial = nullptr;
+  a.partial = (!UMAX && m->sav) ? m->rpart : nullptr;  // SAV: E_1 partials of u*
   a.ctl = &m->ctl;
   a.tw = m->tw;
   a.psd_part = nullptr;
@@ -933,7 +935,8 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
 // one attempt of adaptive BDF2-IMEX: PRO (u* and Lap u* of the step),
 // IMEX (the step, then u~ and Lap u~ for F(u~)), AM3 (F(u~) and the error sums);
 // of adaptive ETDRK2: ETD_PRO (first stage from the cached F(u^n)), ETD2 (the
-// step, then the trial's (u, Lap u)), AM3
+// step, then the trial's (u, Lap u)), AM3; of adaptive SAV: PRO, SAV (p, q and
+// the r-solve sums), SAV_FIELD (r^{n+1}, the trial and its (u, Lap u)), AM3
 template <int N, int E, int TWL, int STAGE>
 __global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
   EnsMember* m = mem + first + blockIdx.y;
@@ -961,6 +964,26 @@ __global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
     a.s1 = m->aux;
     a.out = m->ring[m->trial];
     col_body<N, E, EPI_ETD2, PRO_NEXT_FIELD, TWL>(a, &m->ctl.done);
+  } else if constexpr (STAGE == ENS_SAV) {
+    // p into the trial slot, q into aux, the (g_p, g_q) partials; s* from the
+    // first row pass's E_1 partials
+    a.s0 = m->ring[m->cur];
+    a.s1 = m->ring[m->prev];
+    a.out = m->ring[m->trial];
+    a.aux = m->aux;
+    a.partial = m->cpart;
+    a.sav_rpart = m->rpart;
+    a.sav_nrow = m->nrow;
+    col_body<N, E, EPI_SAV, PRO_NONE, TWL>(a, &m->ctl.done);
+  } else if constexpr (STAGE == ENS_SAV_FIELD) {
+    // r^{n+1}, u^{n+1} = p + r^{n+1} q over p, and its (u, Lap u) for F
+    a.s0 = m->ring[m->cur];
+    a.out = m->ring[m->trial];
+    a.aux = m->aux;
+    a.sav_cpart = m->cpart;
+    a.sav_ncol = m->H;
+    a.rslot = m->rslot;
+    col_body<N, E, EPI_NONE, PRO_SAV_FIELD, TWL>(a, &m->ctl.done);
   } else {
     a.s0 = m->ring[m->trial];
     a.s1 = m->ring[m->cur];

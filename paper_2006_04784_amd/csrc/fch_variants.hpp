@@ -130,6 +130,12 @@ struct ColImpl {
       case ENS_ETD2:
         hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_ETD2>), grid, dim3(CT), 0, s, m, first);
         break;
+      case ENS_SAV:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_SAV>), grid, dim3(CT), 0, s, m, first);
+        break;
+      case ENS_SAV_FIELD:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_SAV_FIELD>), grid, dim3(CT), 0, s, m, first);
+        break;
       default:
         return hipErrorInvalidValue;
     }

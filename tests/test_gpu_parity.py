@@ -788,13 +788,14 @@ def test_temporal_convergence_on_paper_data(F):
         assert r["etd"][i] > 2.0 * r["imex"][i]
 
 
-@pytest.mark.parametrize("scheme", ["imex", "etd"])
+@pytest.mark.parametrize("scheme", ["imex", "etd", "sav"])
 def test_adaptive_device_control_matches_host_loop(F, orc, scheme):
-    """fch_run's adaptive IMEX and ETDRK2 run their attempts under device
-    control (the ensemble's batched kernels and per-member controller on a
-    one-member view of the plan); with kernel timing on they fall back to
-    the host loop.  Both take the same decisions and reach the same state;
-    the step limit and the final time are honoured exactly."""
+    """fch_run's adaptive IMEX, ETDRK2 and SAV run their attempts under
+    device control (the ensemble's batched kernels and per-member controller
+    on a one-member view of the plan; SAV's r history rotates on the device);
+    with kernel timing on they fall back to the host loop.  Both take the
+    same decisions and reach the same state (and SAV scalars); the step limit
+    and the final time are honoured exactly."""
     log("adaptive %s: device control vs host loop" % scheme)
     N, L = 256, 4 * np.pi
     plan, m = pair(F, orc, **model_kw(N, L))
@@ -817,6 +818,9 @@ def test_adaptive_device_control_matches_host_loop(F, orc, scheme):
     # between the two kernel sets (FMA contraction) reach it at about 1e-11
     assert abs(i0["k_next"] - i1["k_next"]) <= 1e-9 * i1["k_next"]
     assert rel(a0, a1) < 1e-12 and rel(b0, b1) < 1e-12
+    if scheme == "sav":
+        for x, y in zip(i0["rs"], i1["rs"]):
+            assert abs(x - y) <= 1e-12 * abs(y)
     # a step limit stops the run after exactly that many accepted steps
     a, b = dev(uh0), torch.zeros_like(dev(uh0))
     info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=10.0, nsteps=37,
