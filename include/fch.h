@@ -325,8 +325,12 @@ fch_status fch_run(fch_plan_t plan, const fch_run_opts* opts, fch_c128* uh_n, fc
                    double* rs, fch_run_info* info);
 
 /* ---- batched ensembles ---------------------------------------------------- */
-/* Many independent adaptive BDF2-IMEX runs (Sec. 3.2 step control, each
- * member with its own parameters, state and step size) advanced together.
+/* Many independent adaptive runs (Sec. 3.2 step control, each member with its
+ * own parameters, state and step size) advanced together, all with one scheme:
+ * BDF2-IMEX (the default), BDF2-SAV (each member's r history on the device) or
+ * ETDRK2.  The description below is for IMEX; SAV attempts add a column pass
+ * (the r-solve and the trial) after the SAV step, and ETDRK2 attempts start
+ * from the cached F(u^n).
  * Members are grouped by N into size classes; an attempt runs, for every
  * class, the batched column pass (u*, Lap u*), row pass, column pass (the
  * IMEX step, then u~, Lap u~), row pass, column pass (F(u~), AM3 sums) and a
@@ -342,15 +346,20 @@ typedef struct {
     int64_t max_steps;   /* cap on accepted steps per member (startup included)   */
     double  k_first;     /* first-order startup step; <= 0 selects adapt.k_min    */
     double  umax_t0;     /* umax counts the accepted states at t >= umax_t0        */
+    int32_t scheme;      /* FCH_IMEX (0), FCH_SAV or FCH_ETD for every member      */
+    fch_etd_opts etd;    /* FCH_ETD: kappa0, kappa2, taken as given                */
 } fch_ensemble_opts;
 typedef struct { int64_t attempts, accepted, rejected; int32_t active; } fch_ensemble_info;
 typedef struct {
     int32_t N, done, nonfinite;
+    int32_t invalid;  /* SAV: E_1 + D_0 <= 0 at a stage state; the member stopped */
     int64_t accepted, rejected;
     double  t, k_last, k_next, err;
     double  umax;   /* running max of u over the accepted states after the startup
                        step at t >= opts.umax_t0 (-inf before the first); the
                        defect-onset indicator of Sec. 5.1 and Table f:defect-onsetR */
+    double  r_n, r_nm1;  /* SAV: the auxiliary scalar r of the last two accepted
+                            states (eq. 4.8); 0 for the other schemes */
 } fch_member_info;
 /* Host-side setup: one plan (twiddles, launch variants) per size class on the
  * current device.  members: count parameter sets (N in 16..4096). */
@@ -363,7 +372,8 @@ fch_status fch_ensemble_set_stream(fch_ensemble_t ens, void* stream);
 size_t     fch_ensemble_workspace_bytes(fch_ensemble_t ens);
 fch_status fch_ensemble_set_workspace(fch_ensemble_t ens, void* dptr, size_t bytes);
 /* Loads member i from a physical N*N state (device): forward transform,
- * F(u^0), a first-order step of size k_first, F(u^1).  Synchronizes. */
+ * F(u^0), a startup step of size k_first (first-order BDF for IMEX and SAV,
+ * with r^0 = sqrt(E_1(u^0) + D_0); an ETDRK2 step), F(u^1).  Synchronizes. */
 fch_status fch_ensemble_load(fch_ensemble_t ens, int32_t member, const double* u0);
 /* Autotunes each class's launch variants on its first member (after load). */
 fch_status fch_ensemble_autotune(fch_ensemble_t ens, int32_t reps);

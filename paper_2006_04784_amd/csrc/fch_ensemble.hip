@@ -63,10 +63,12 @@ struct fch_ensemble_s {
 
 namespace {
 
+// three states, three F spectra, the pair buffer, aux (SAV q / ETDRK2 w), the
+// column partials, the umax slots, the E_1 row partials (SAV) and the step log
 size_t member_bytes(const fch_ensemble_s* e, int N) {
   const size_t S = a256(spec_bytes(N));
-  return 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)) + a256(sizeof(double) * (size_t)N) +
-         a256(sizeof(double) * (size_t)e->opts.max_steps);
+  return 9 * S + a256(sizeof(double) * 2 * (N / 2 + 1)) + a256(sizeof(double) * (size_t)N) +
+         a256(sizeof(double) * 2 * (size_t)N) + a256(sizeof(double) * (size_t)e->opts.max_steps);
 }
 
 size_t layout(fch_ensemble_s* e, bool assign) {
@@ -87,10 +89,15 @@ size_t layout(fch_ensemble_s* e, bool assign) {
       for (int k = 0; k < 3; ++k) m.fring[k] = (cd*)(b + (3 + k) * S);
       m.P0 = (cd*)(b + 6 * S);
       m.P1 = (cd*)(b + 7 * S);
-      m.cpart = (double*)(b + 8 * S);
-      m.umaxpart = (double*)(b + 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)));
-      m.klog = (double*)(b + 8 * S + a256(sizeof(double) * 2 * (N / 2 + 1)) +
-                         a256(sizeof(double) * (size_t)N));
+      m.aux = (cd*)(b + 8 * S);
+      char* q = b + 9 * S;
+      m.cpart = (double*)q;
+      q += a256(sizeof(double) * 2 * (N / 2 + 1));
+      m.umaxpart = (double*)q;
+      q += a256(sizeof(double) * (size_t)N);
+      m.rpart = (double*)q;
+      q += a256(sizeof(double) * 2 * (size_t)N);
+      m.klog = (double*)q;
       m.klog_cap = e->opts.max_steps;
     }
     off += member_bytes(e, N);
@@ -104,17 +111,27 @@ EnsClass* class_of(fch_ensemble_s* e, int idx) {
   return nullptr;
 }
 
-// every class: PRO, row, IMEX(+u~ prologue), row, AM3, controller; classes on
-// their own streams between a fork and a join on the ensemble stream
+// every class: PRO, row, IMEX(+u~ prologue), row, AM3, controller (SAV: PRO,
+// row with E_1 partials, SAV, SAV_FIELD, row, AM3; ETDRK2: ETD_PRO, row, ETD2,
+// row, AM3); classes on their own streams between a fork and a join on the
+// ensemble stream
 fch_status enqueue_attempt(fch_ensemble_s* e) {
   HCHK(hipEventRecord(e->fork, e->stream));
   for (auto& c : e->classes) {
     HCHK(hipStreamWaitEvent(c.stream, e->fork, 0));
     const fch::RowVT* rv = c.plan->rv;
     const fch::ColVT* cv = c.plan->cv;
-    HCHK(cv->col_ens(fch::ENS_PRO, e->dmem, c.first, c.count, c.stream));
+    const int sch = e->opts.scheme;
+    HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD_PRO : fch::ENS_PRO, e->dmem, c.first, c.count,
+                     c.stream));
     HCHK(rv->row_ens(e->dmem, c.first, c.count, 0, c.stream));
-    HCHK(cv->col_ens(fch::ENS_IMEX, e->dmem, c.first, c.count, c.stream));
+    if (sch == FCH_SAV) {
+      HCHK(cv->col_ens(fch::ENS_SAV, e->dmem, c.first, c.count, c.stream));
+      HCHK(cv->col_ens(fch::ENS_SAV_FIELD, e->dmem, c.first, c.count, c.stream));
+    } else {
+      HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD2 : fch::ENS_IMEX, e->dmem, c.first, c.count,
+                       c.stream));
+    }
     HCHK(rv->row_ens(e->dmem, c.first, c.count, 1, c.stream));
     HCHK(cv->col_ens(fch::ENS_AM3, e->dmem, c.first, c.count, c.stream));
     HCHK(fch::launch_ens_control(e->dmem, c.first, c.count, c.stream));
@@ -141,7 +158,10 @@ fch_status fch_ensemble_create(const fch_params* members, int32_t count,
   const fch_adapt_opts& ad = opts->adapt;
   if (!(ad.sigma_tol > 0.0) || !(ad.k_min > 0.0) || !(ad.k_max >= ad.k_min) ||
       !(ad.rho_s > 0.0) || std::isnan(ad.cap) || !(opts->t_end > 0.0) || opts->max_steps < 2 ||
-      std::isnan(opts->umax_t0))
+      std::isnan(opts->umax_t0) ||
+      (opts->scheme != FCH_IMEX && opts->scheme != FCH_SAV && opts->scheme != FCH_ETD) ||
+      !(opts->etd.kappa0 >= 0.0) || !(opts->etd.kappa2 >= 0.0) ||
+      !std::isfinite(opts->etd.kappa0) || !std::isfinite(opts->etd.kappa2))
     return FCH_E_INVALID;
   for (int i = 0; i < count; ++i) SCHK(fch::validate_params_internal(&members[i]));
   fch_ensemble_s* e = new (std::nothrow) fch_ensemble_s;
@@ -245,13 +265,28 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   const fch::Consts keep = p->c;
   p->c = m.c;  // the member's parameters for the setup calls
   const double k1 = e->opts.k_first > 0.0 ? e->opts.k_first : e->opts.adapt.k_min;
+  const int sch = e->opts.scheme;
+  double r0 = 0.0, r1 = 0.0;
   fch_status st = fch_forward(p, u0, (fch_c128*)m.ring[0]);
   if (st == FCH_OK) st = fch_rhs(p, (const fch_c128*)m.ring[0], (fch_c128*)m.fring[0]);
-  if (st == FCH_OK)
-    st = fch_step_imex(p, (const fch_c128*)m.ring[0], nullptr, k1, -1.0, (fch_c128*)m.ring[1]);
+  const fch_c128* u0h = (const fch_c128*)m.ring[0];
+  fch_c128* u1h = (fch_c128*)m.ring[1];
+  if (st == FCH_OK) {
+    if (sch == FCH_SAV) {
+      st = fch_sav_r(p, u0h, &r0);
+      if (st == FCH_OK) st = fch_step_sav(p, u0h, nullptr, r0, r0, k1, -1.0, u1h, &r1);
+    } else if (sch == FCH_ETD) {
+      st = fch_step_etd(p, u0h, (const fch_c128*)m.fring[0], k1, &e->opts.etd, u1h);
+    } else {
+      st = fch_step_imex(p, u0h, nullptr, k1, -1.0, u1h);
+    }
+  }
   if (st == FCH_OK) st = fch_rhs(p, (const fch_c128*)m.ring[1], (fch_c128*)m.fring[1]);
   p->c = keep;
   SCHK(st);
+  m.sav = (sch == FCH_SAV) ? 1 : 0;
+  m.rslot = 0;
+  m.nrow = m.c.N / p->rv->R;
   m.cur = 1;
   m.prev = 0;
   m.trial = 2;
@@ -272,6 +307,10 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   v.k_max = e->opts.adapt.k_max;
   v.rho_s = e->opts.adapt.rho_s;
   v.cap = e->opts.adapt.cap;
+  v.kappa0 = e->opts.etd.kappa0;
+  v.kappa2 = e->opts.etd.kappa2;
+  v.rring[0] = r1;  // SAV: r^n (slot rslot = 0) and r^{n-1}
+  v.rring[2] = r0;
   // Step 0: the first trial step equals the last step
   double kt = k1;
   if (kt > m.t_end - m.t) kt = m.t_end - m.t;
@@ -294,6 +333,12 @@ fch_status fch_ensemble_autotune(fch_ensemble_t e, int32_t reps) {
     if (!e->loaded[c.first]) return FCH_E_INVALID;
     SCHK(fch_autotune(c.plan, (const fch_c128*)m.ring[m.cur], (const fch_c128*)m.ring[m.prev],
                       m.ctl.k_n, reps, nullptr, nullptr));
+    // the row variant fixes the number of E_1 partial pairs SAV sums
+    const int nrow = e->prm[c.first].N / c.plan->rv->R;
+    for (int k = c.first; k < c.first + c.count; ++k) {
+      e->hmem[k].nrow = nrow;
+      HCHK(hipMemcpy(&e->dmem[k].nrow, &nrow, sizeof(int), hipMemcpyHostToDevice));
+    }
   }
   drop_graph(e);  // launch variants changed
   return FCH_OK;
@@ -411,6 +456,9 @@ fch_status fch_ensemble_member(fch_ensemble_t e, int32_t member, fch_c128* uh, d
     info->k_next = m.ctl.k_next;
     info->err = m.ctl.err;
     info->umax = m.umax;
+    info->invalid = m.ctl.invalid;
+    info->r_n = m.sav ? m.ctl.rring[m.rslot] : 0.0;
+    info->r_nm1 = m.sav ? m.ctl.rring[(m.rslot + 2) % 3] : 0.0;
   }
   return FCH_OK;
 }

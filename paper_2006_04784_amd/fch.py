@@ -86,7 +86,8 @@ class fch_run_info(C.Structure):
 
 class fch_ensemble_opts(C.Structure):
     _fields_ = [("adapt", fch_adapt_opts), ("t_end", C.c_double), ("max_steps", C.c_int64),
-                ("k_first", C.c_double), ("umax_t0", C.c_double)]
+                ("k_first", C.c_double), ("umax_t0", C.c_double), ("scheme", C.c_int32),
+                ("etd", fch_etd_opts)]
 
 
 class fch_ensemble_info(C.Structure):
@@ -96,9 +97,10 @@ class fch_ensemble_info(C.Structure):
 
 class fch_member_info(C.Structure):
     _fields_ = [("N", C.c_int32), ("done", C.c_int32), ("nonfinite", C.c_int32),
-                ("accepted", C.c_int64), ("rejected", C.c_int64), ("t", C.c_double),
-                ("k_last", C.c_double), ("k_next", C.c_double), ("err", C.c_double),
-                ("umax", C.c_double)]
+                ("invalid", C.c_int32), ("accepted", C.c_int64), ("rejected", C.c_int64),
+                ("t", C.c_double), ("k_last", C.c_double), ("k_next", C.c_double),
+                ("err", C.c_double), ("umax", C.c_double), ("r_n", C.c_double),
+                ("r_nm1", C.c_double)]
 
 
 _V = C.c_void_p
@@ -551,12 +553,13 @@ class Plan:
 
 
 class Ensemble:
-    """Batched adaptive BDF2-IMEX runs (fch_ensemble_* of the C ABI).
+    """Batched adaptive runs (fch_ensemble_* of the C ABI), one scheme for every member:
+    "imex" (BDF2 IMEX), "sav" (BDF2 SAV) or "etd" (ETDRK2 with stabilizers kappa0, kappa2).
 
     members: list of dicts of Plan keyword arguments (N, L, eps, eta1, eta2, ...)."""
 
     def __init__(self, members, adapt: AdaptOpts = None, t_end=1.0, max_steps=1000, k_first=0.0,
-                 device="cuda:0", umax_t0=0.0):
+                 device="cuda:0", umax_t0=0.0, scheme="imex", kappa0=None, kappa2=None):
         self.device = torch.device(device)
         prms = []
         for kw in members:
@@ -571,7 +574,13 @@ class Ensemble:
         arr = (fch_params * len(prms))(*prms)
         self.Ns = [m["N"] for m in members]
         self.max_steps = max_steps
-        opts = fch_ensemble_opts((adapt or AdaptOpts()).c(), t_end, max_steps, k_first, umax_t0)
+        schemes = {"imex": FCH_IMEX, "sav": FCH_SAV, "etd": FCH_ETD}
+        if scheme not in schemes:
+            raise ValueError("ensemble scheme must be one of %s" % sorted(schemes))
+        etd = fch_etd_opts(ETD_KAPPA0 if kappa0 is None else kappa0,
+                           ETD_KAPPA2 if kappa2 is None else kappa2)
+        opts = fch_ensemble_opts((adapt or AdaptOpts()).c(), t_end, max_steps, k_first, umax_t0,
+                                 schemes[scheme], etd)
         h = _V()
         with torch.cuda.device(self.device):
             _check(lib().fch_ensemble_create(arr, len(prms), C.byref(opts), C.byref(h)))

@@ -29,10 +29,11 @@ DEFECT_THRESHOLD = 0.55   # between the bilayer's peak (0.3566) and a defect's (
 
 def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_THRESHOLD,
                      N=256, physical_k=False, max_steps=1000000, device="cuda:0", log=None,
-                     chunk=5000):
-    """Runs one member per d and returns a dict with the per-member running
-    max of u, accepted / rejected steps, end times, the critical d (None when
-    no member crosses the threshold) and the wall time."""
+                     chunk=5000, scheme="imex"):
+    """Runs one ensemble member per d with one scheme (imex, sav or etd) and
+    returns a dict with the per-member running max of u, accepted / rejected
+    steps, end times, the critical d (None when no member crosses the
+    threshold) and the wall time."""
     ds = [float(d) for d in ds]
     members, u0s = [], []
     for d in ds:
@@ -40,7 +41,8 @@ def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_
         members.append(kw)
         u0s.append(u0)
     ens = fch.Ensemble(members, adapt=fch.AdaptOpts(sigma_tol=sigma_tol), t_end=t_end,
-                       max_steps=max_steps, k_first=1e-9, device=device, umax_t0=t0)
+                       max_steps=max_steps, k_first=1e-9, device=device, umax_t0=t0,
+                       scheme=scheme)
     for i, u0 in enumerate(u0s):
         ens.load(i, torch.from_numpy(np.ascontiguousarray(u0)).to(device))
     ens.autotune(5)
@@ -61,7 +63,9 @@ def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_
     under = [d for d, u in zip(ds, umax) if not u > threshold]
     if any(r["nonfinite"] for r in rows):
         raise RuntimeError("a member reached a non-finite state")
-    return {"d": ds, "umax": umax, "accepted": [r["accepted"] for r in rows],
+    if any(r["invalid"] for r in rows):
+        raise RuntimeError("a SAV member reached E_1 + D_0 <= 0")
+    return {"scheme": scheme, "d": ds, "umax": umax, "accepted": [r["accepted"] for r in rows],
             "rejected": [r["rejected"] for r in rows], "t": [r["t"] for r in rows],
             "d_critical": min(over) if over else None,
             "d_max_without_defect": max(under) if under else None, "attempts": attempts,
@@ -316,7 +320,8 @@ if __name__ == "__main__":
     ap.add_argument("--d-min", type=float, default=None)
     ap.add_argument("--d-max", type=float, default=None)
     ap.add_argument("--scheme", default="ensemble-imex",
-                    help="ensemble-imex (all d at once) or imex / sav / psd / etd (bisection)")
+                    help="ensemble-imex / ensemble-sav / ensemble-etd (all d at once) or "
+                         "imex / sav / psd / etd (bisection with single runs)")
     ap.add_argument("--psd-nu", type=float, default=1e-3,
                     help="PSD stopping tolerance i_tol = nu * sigma (Table tolPSD: 1e-3 at q = 0)")
     ap.add_argument("--k-max", type=float, default=float("inf"))
@@ -343,7 +348,7 @@ if __name__ == "__main__":
                                            log=lambda m: print(m, file=sys.stderr, flush=True))))
         sys.exit(0)
     if args.beta_sweep:
-        sch = "sav" if args.scheme == "ensemble-imex" else args.scheme
+        sch = "sav" if args.scheme.startswith("ensemble-") else args.scheme
         print(json.dumps(beta_sweep(sch, t_end=args.t_end, sigma_tol=args.sigma,
                                     max_steps=args.max_steps,
                                     log=lambda m: print(m, file=sys.stderr, flush=True))))
@@ -351,8 +356,9 @@ if __name__ == "__main__":
     ds = [d for d in paper_d_values()
           if (args.d_min is None or d >= args.d_min) and (args.d_max is None or d <= args.d_max)]
     err = lambda m: print(m, file=sys.stderr, flush=True)
-    if args.scheme == "ensemble-imex":
-        res = critical_d_sweep(ds, sigma_tol=args.sigma, t_end=args.t_end, t0=args.t0, log=err)
+    if args.scheme.startswith("ensemble-"):
+        res = critical_d_sweep(ds, sigma_tol=args.sigma, t_end=args.t_end, t0=args.t0, log=err,
+                               scheme=args.scheme[len("ensemble-"):])
         res["sigma_tol"] = args.sigma
     else:
         res = critical_d_bisect(args.scheme, args.sigma, ds, log=err, t_end=args.t_end,

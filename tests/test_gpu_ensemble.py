@@ -177,3 +177,100 @@ def test_defect_onset_dichotomy(F):
     assert abs(lo - 0.3566) < 0.005, res
     assert 0.70 < hi < 0.80, res
     assert res["d_critical"] == 0.775 and res["d_max_without_defect"] == 0.745
+
+
+def build_scheme(F, mem, scheme, use_max=30, t_end=10.0):
+    ens = F.Ensemble(mem, adapt=F.AdaptOpts(sigma_tol=1e-5), t_end=t_end, max_steps=use_max,
+                     scheme=scheme)
+    for i, m in enumerate(mem):
+        ens.load(i, torch.from_numpy(initial(m, seed=10 + i)).cuda())
+    return ens
+
+
+@pytest.mark.parametrize("scheme", ["sav", "etd"])
+def test_ensemble_schemes_match_single_runs(F, scheme):
+    """SAV and ETDRK2 members of an ensemble reach the states, times and step
+    counts of independent single-plan adaptive runs of the same scheme (both
+    take the first-order startup step k_min; ETDRK2's single run evaluates its
+    first stage with the cached F(u^0), which rounds differently)."""
+    log("ensemble %s vs single runs" % scheme)
+    mem = members_small()
+    ens = build_scheme(F, mem, scheme)
+    info = ens.run(max_attempts=1000, sync_every=7, use_graph=True)
+    assert info["active"] == 0
+    tol = 1e-12 if scheme == "sav" else 1e-10
+    for i, m in enumerate(mem):
+        uh, klog, mi = ens.member(i)
+        assert mi["done"] and mi["accepted"] == 30 and not mi["nonfinite"] and not mi["invalid"]
+        plan = F.Plan(**m)
+        a = plan.forward(torch.from_numpy(initial(m, seed=10 + i)).cuda())
+        b = torch.empty_like(a)
+        ri = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=10.0,
+                      adapt=F.AdaptOpts(sigma_tol=1e-5), nsteps=30)
+        assert ri["accepted"] == mi["accepted"], (i, ri, mi)
+        assert rel(uh.cpu().numpy(), a.cpu().numpy()) < tol, i
+        assert abs(ri["t"] - mi["t"]) < tol * ri["t"]
+        if scheme == "sav":
+            assert abs(ri["rs"][0] - mi["r_n"]) < tol * abs(mi["r_n"])
+            assert abs(ri["rs"][1] - mi["r_nm1"]) < tol * abs(mi["r_nm1"])
+        else:
+            assert mi["r_n"] == 0.0 and mi["r_nm1"] == 0.0
+
+
+@pytest.mark.parametrize("scheme", ["sav", "etd"])
+def test_ensemble_scheme_member_replayed_by_oracle(F, orc, scheme):
+    """The accepted step sizes of an ensemble member, replayed by the oracle's
+    steppers from the same initial data, reproduce the member's state (and,
+    for SAV, its r)."""
+    log("ensemble %s member oracle replay" % scheme)
+    mem = members_small()[:2]
+    ens = build_scheme(F, mem, scheme, use_max=25)
+    ens.run(max_attempts=500, sync_every=5, use_graph=True)
+    for i, m in enumerate(mem):
+        uh, klog, mi = ens.member(i)
+        om = orc.Model(**m)
+        u0 = orc.r2c(initial(m, seed=10 + i))
+        assert len(klog) == 25 and klog[-1] > 10 * klog[0]
+        if scheme == "sav":
+            r0 = float(np.sqrt(orc.E1(om, u0) + om.D0))
+            cur, r1 = orc.sav_step(om, u0, None, r0, r0, klog[0], -1.0)
+            prev, rp = u0, r0
+            rc = r1
+            for j in range(1, len(klog)):
+                nxt, rn = orc.sav_step(om, cur, prev, rc, rp, klog[j], klog[j - 1])
+                prev, rp, cur, rc = cur, rc, nxt, rn
+            assert abs(rc - mi["r_n"]) < 1e-8 * abs(rc)
+            assert abs(rp - mi["r_nm1"]) < 1e-8 * abs(rp)
+        else:
+            cur = u0
+            for k in klog:
+                cur = orc.etd_step(om, cur, k)
+        assert rel(uh.cpu().numpy().T, cur) < 1e-8, i
+
+
+@pytest.mark.parametrize("scheme", ["sav", "etd"])
+def test_ensemble_scheme_mixed_sizes_autotuned(F, scheme):
+    """Mixed grid sizes after the autotuner picked each class's variants (the
+    SAV row pass's partial count follows the chosen variant): every member
+    still matches an independent single run."""
+    log("ensemble %s mixed sizes autotuned" % scheme)
+    rng = np.random.default_rng(11)
+    mem = []
+    for N in (256, 128, 512):
+        L = N * 4 * np.pi / 256
+        mem.append(dict(N=N, L=L, eps=0.1, eta1=rng.uniform(1.2, 1.6),
+                        eta2=rng.uniform(1.5, 2.5)))
+    ens = build_scheme(F, mem, scheme, use_max=12)
+    ens.autotune(reps=2)
+    info = ens.run(max_attempts=1000, sync_every=10, use_graph=True)
+    assert info["active"] == 0 and info["accepted"] == 12 * len(mem)
+    tol = 1e-12 if scheme == "sav" else 1e-10
+    for i, m in enumerate(mem):
+        uh, klog, mi = ens.member(i)
+        plan = F.Plan(**m)
+        a = plan.forward(torch.from_numpy(initial(m, seed=10 + i)).cuda())
+        b = torch.empty_like(a)
+        ri = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=10.0,
+                      adapt=F.AdaptOpts(sigma_tol=1e-5), nsteps=12)
+        assert ri["accepted"] == mi["accepted"] == 12
+        assert rel(uh.cpu().numpy(), a.cpu().numpy()) < tol, i
