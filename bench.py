@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip SAV/PSD/adaptive/FFT extras")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="of the extras, run only the two batched ensembles (for profiling)")
     ap.add_argument("--config", type=str, default="",
                     help="row_R,row_E,row_twl,col_E,col_twl launch config instead of autotuning")
     ap.add_argument("--graph", type=int, default=0,
@@ -155,7 +157,7 @@ def main():
                 "step_GBps": round(11 * S * steps_per_s / 1e9, 1)}
 
     extra = {}
-    if not args.no_extra:
+    if not args.no_extra and not args.ensemble_only:
         # SAV, fixed step
         log("SAV fixed step")
         rs = [plan.sav_r(a), 0.0]
@@ -312,15 +314,17 @@ def main():
         # the critical-d sweep of Sec. 5.1 (Table f:defect-onsetR): 206 members of the
         # critical benchmark (256^2, the paper's initial data), adaptive IMEX at
         # sigma_tol 1e-5 to T = 250 in one batched ensemble
-        log("critical-d sweep: 206 members to T = 250")
-        from paper_2006_04784_amd import sweeps
-        sw = sweeps.critical_d_sweep(sweeps.paper_d_values(), sigma_tol=1e-5, t_end=250.0)
-        extra["critical_d_sweep"] = {
-            "scheme": "imex", "sigma_tol": 1e-5, "members": len(sw["d"]), "t_end": 250.0,
-            "d_critical": sw["d_critical"], "d_max_without_defect": sw["d_max_without_defect"],
-            "paper_d_critical_imex": 0.7540, "seconds": round(sw["seconds"], 2),
-            "accepted_steps": int(sum(sw["accepted"])),
-            "accepted_steps_per_s": round(sum(sw["accepted"]) / sw["seconds"], 1)}
+        if not args.ensemble_only:
+            log("critical-d sweep: 206 members to T = 250")
+            from paper_2006_04784_amd import sweeps
+            sw = sweeps.critical_d_sweep(sweeps.paper_d_values(), sigma_tol=1e-5, t_end=250.0)
+            extra["critical_d_sweep"] = {
+                "scheme": "imex", "sigma_tol": 1e-5, "members": len(sw["d"]), "t_end": 250.0,
+                "d_critical": sw["d_critical"],
+                "d_max_without_defect": sw["d_max_without_defect"],
+                "paper_d_critical_imex": 0.7540, "seconds": round(sw["seconds"], 2),
+                "accepted_steps": int(sum(sw["accepted"])),
+                "accepted_steps_per_s": round(sum(sw["accepted"]) / sw["seconds"], 1)}
         # batched ensemble: 64 adaptive IMEX runs of mixed size in captured graphs
         log("ensemble of 64 mixed-size adaptive runs")
         rng = np.random.default_rng(2024)
@@ -350,7 +354,40 @@ def main():
                              "steps_per_member": ens_steps, "attempts": info["attempts"],
                              "rejected": info["rejected"], "seconds": round(el, 3)}
         ens.close()
-    if not args.no_extra:
+        # the same ensemble machinery on 16 equal 1024^2 members: one batched
+        # launch per stage covers all of them, so the row and column passes
+        # overlap across members instead of draining per field
+        log("ensemble of 16 adaptive 1024^2 runs")
+        mem = [dict(N=1024, L=1024 * 4 * np.pi / 256, eps=0.1,
+                    eta1=float(rng.uniform(1.2, 1.6)), eta2=float(rng.uniform(1.5, 2.5)))
+               for _ in range(16)]
+        ens = fch.Ensemble(mem, adapt=fch.AdaptOpts(sigma_tol=1e-5), t_end=1e9, max_steps=320)
+        for i, mi in enumerate(mem):
+            ens.load(i, torch.from_numpy(inputs.circle_bilayer(
+                1024, mi["L"], 0.1, seed=300 + i)).to(dev))
+        ens.autotune(reps=3)
+        ens.run(max_attempts=20, sync_every=20, use_graph=True)
+        torch.cuda.synchronize()
+
+        def member_attempts():
+            rows = [ens.member(i, state=False, klog=False)[2] for i in range(len(mem))]
+            return sum(r["accepted"] + r["rejected"] for r in rows)
+
+        a0 = member_attempts()
+        t0 = time.perf_counter()
+        info = ens.run(max_attempts=100000, sync_every=100, use_graph=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        att = member_attempts() - a0
+        S1024 = 16 * 1024 * 513
+        extra["ensemble_1024x16"] = {
+            "member_attempts_per_s": round(att / el, 1),
+            "bytes_per_member_attempt": 26 * S1024,
+            "GBps": round(26 * S1024 * att / el / 1e9, 1),
+            "frac_of_8TBps": round(26 * S1024 * att / el / 8e12, 4),
+            "member_attempts": att, "seconds": round(el, 3)}
+        ens.close()
+    if not args.no_extra and not args.ensemble_only:
         # learned PSD warm start at 256^2: PSD FFT calls per step, learned vs plain
         log("learned PSD warm start (data, training, held-out comparison)")
         from paper_2006_04784_amd import learned

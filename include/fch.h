@@ -375,7 +375,14 @@ fch_status fch_ensemble_set_workspace(fch_ensemble_t ens, void* dptr, size_t byt
  * F(u^0), a startup step of size k_first (first-order BDF for IMEX and SAV,
  * with r^0 = sqrt(E_1(u^0) + D_0); an ETDRK2 step), F(u^1).  Synchronizes. */
 fch_status fch_ensemble_load(fch_ensemble_t ens, int32_t member, const double* u0);
-/* Autotunes each class's launch variants on its first member (after load). */
+/* Autotunes each size class's launch variants on the batched work itself:
+ * every compiled (row, column) variant pair runs 1 + reps whole attempts of
+ * all the class's members, each pair from the same member memory, and the
+ * fastest pair is kept.  Member states, times and counters are restored
+ * afterwards, so tuning changes no result beyond rounding.  Needs every
+ * member loaded (FCH_E_INVALID) and the workspace (FCH_E_NOMEM); holds a
+ * temporary device copy of one class's member memory (hipMalloc) while it
+ * runs.  Synchronizes. */
 fch_status fch_ensemble_autotune(fch_ensemble_t ens, int32_t reps);
 /* Runs attempts until every member finished or max_attempts attempts ran. */
 fch_status fch_ensemble_run(fch_ensemble_t ens, int64_t max_attempts, int32_t sync_every,
@@ -387,8 +394,9 @@ fch_status fch_ensemble_run(fch_ensemble_t ens, int64_t max_attempts, int32_t sy
  * later fch_ensemble_run. */
 fch_status fch_ensemble_step(fch_ensemble_t ens, int32_t attempts, int32_t use_graph);
 /* Status of member i (host out); uh (device out, nullable) receives its last
- * accepted state; klog (host out, nullable, max_steps doubles) its accepted
- * step sizes.  Synchronizes. */
+ * accepted state, copied in order on the ensemble's caller stream
+ * (fch_ensemble_set_stream); klog (host out, nullable, max_steps doubles) its
+ * accepted step sizes.  Waits for the work queued so far. */
 fch_status fch_ensemble_member(fch_ensemble_t ens, int32_t member, fch_c128* uh, double* klog,
                                fch_member_info* info);
 

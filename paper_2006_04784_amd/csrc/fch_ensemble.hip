@@ -115,29 +115,114 @@ EnsClass* class_of(fch_ensemble_s* e, int idx) {
 // row with E_1 partials, SAV, SAV_FIELD, row, AM3; ETDRK2: ETD_PRO, row, ETD2,
 // row, AM3); classes on their own streams between a fork and a join on the
 // ensemble stream
+fch_status enqueue_class(fch_ensemble_s* e, const EnsClass& c, hipStream_t s) {
+  const fch::RowVT* rv = c.plan->rv;
+  const fch::ColVT* cv = c.plan->cv;
+  const int sch = e->opts.scheme;
+  HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD_PRO : fch::ENS_PRO, e->dmem, c.first, c.count, s));
+  HCHK(rv->row_ens(e->dmem, c.first, c.count, 0, s));
+  if (sch == FCH_SAV) {
+    HCHK(cv->col_ens(fch::ENS_SAV, e->dmem, c.first, c.count, s));
+    HCHK(cv->col_ens(fch::ENS_SAV_FIELD, e->dmem, c.first, c.count, s));
+  } else {
+    HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD2 : fch::ENS_IMEX, e->dmem, c.first, c.count, s));
+  }
+  HCHK(rv->row_ens(e->dmem, c.first, c.count, 1, s));
+  HCHK(cv->col_ens(fch::ENS_AM3, e->dmem, c.first, c.count, s));
+  HCHK(fch::launch_ens_control(e->dmem, c.first, c.count, s));
+  return FCH_OK;
+}
+
 fch_status enqueue_attempt(fch_ensemble_s* e) {
   HCHK(hipEventRecord(e->fork, e->stream));
   for (auto& c : e->classes) {
     HCHK(hipStreamWaitEvent(c.stream, e->fork, 0));
-    const fch::RowVT* rv = c.plan->rv;
-    const fch::ColVT* cv = c.plan->cv;
-    const int sch = e->opts.scheme;
-    HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD_PRO : fch::ENS_PRO, e->dmem, c.first, c.count,
-                     c.stream));
-    HCHK(rv->row_ens(e->dmem, c.first, c.count, 0, c.stream));
-    if (sch == FCH_SAV) {
-      HCHK(cv->col_ens(fch::ENS_SAV, e->dmem, c.first, c.count, c.stream));
-      HCHK(cv->col_ens(fch::ENS_SAV_FIELD, e->dmem, c.first, c.count, c.stream));
-    } else {
-      HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD2 : fch::ENS_IMEX, e->dmem, c.first, c.count,
-                       c.stream));
-    }
-    HCHK(rv->row_ens(e->dmem, c.first, c.count, 1, c.stream));
-    HCHK(cv->col_ens(fch::ENS_AM3, e->dmem, c.first, c.count, c.stream));
-    HCHK(fch::launch_ens_control(e->dmem, c.first, c.count, c.stream));
+    SCHK(enqueue_class(e, c, c.stream));
     HCHK(hipEventRecord(c.join, c.stream));
     HCHK(hipStreamWaitEvent(e->stream, c.join, 0));
   }
+  return FCH_OK;
+}
+
+// Batched tuning of one size class: every pair of compiled row and column
+// variants runs `reps` whole attempts of all the class's members (after one
+// untimed attempt), each pair from the same saved member memory, which is
+// restored at the end; the fastest pair stays.  Timing the batched launches
+// (not a single field's step) matters: with many members per launch the
+// best tile and radix choice trades latency for occupancy differently.
+fch_status tune_class(fch_ensemble_s* e, EnsClass& c, int reps) {
+  const int N = c.N;
+  const int nr = fch::row_variant_count(N), nc = fch::col_variant_count(N);
+  const size_t region = member_bytes(e, N) * (size_t)c.count;
+  char* base = (char*)e->hmem[c.first].ring[0];
+  std::vector<EnsMember> saved((size_t)c.count);
+  // everything below runs on the ensemble stream, which does not synchronize
+  // with the legacy null stream: the snapshot is ordered there too
+  HCHK(hipStreamSynchronize(e->user_stream));
+  HCHK(hipMemcpyAsync(saved.data(), e->dmem + c.first, sizeof(EnsMember) * c.count,
+                      hipMemcpyDeviceToHost, e->stream));
+  HCHK(hipStreamSynchronize(e->stream));
+  bool any = false;
+  for (const auto& m : saved) any |= !m.ctl.done;
+  if (!any) return FCH_OK;  // nothing would run
+  char* keep = nullptr;
+  if (hipMalloc((void**)&keep, region) != hipSuccess) return FCH_E_NOMEM;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  fch_status st = FCH_OK;
+  if (hipMemcpyAsync(keep, base, region, hipMemcpyDeviceToDevice, e->stream) != hipSuccess ||
+      hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+    st = FCH_E_HIP;
+  std::vector<EnsMember> trial = saved;
+  auto restore = [&](const fch::RowVT* rv) -> fch_status {
+    for (auto& m : trial) m.nrow = N / rv->R;
+    HCHK(hipMemcpyAsync(base, keep, region, hipMemcpyDeviceToDevice, e->stream));
+    HCHK(hipMemcpyAsync(e->dmem + c.first, trial.data(), sizeof(EnsMember) * c.count,
+                        hipMemcpyHostToDevice, e->stream));
+    return FCH_OK;
+  };
+  const fch::RowVT* keep_r = c.plan->rv;
+  const fch::ColVT* keep_c = c.plan->cv;
+  const fch::RowVT* best_r = keep_r;
+  const fch::ColVT* best_c = keep_c;
+  float best_ms = 0.f;
+  bool have = false;
+  for (int ri = 0; ri < nr && st == FCH_OK; ++ri) {
+    for (int ci = 0; ci < nc && st == FCH_OK; ++ci) {
+      c.plan->rv = fch::row_variant(N, ri);
+      c.plan->cv = fch::col_variant(N, ci);
+      st = restore(c.plan->rv);
+      if (st == FCH_OK) st = enqueue_class(e, c, e->stream);  // untimed
+      if (st == FCH_OK && hipEventRecord(ev[0], e->stream) != hipSuccess) st = FCH_E_HIP;
+      for (int r = 0; r < reps && st == FCH_OK; ++r) st = enqueue_class(e, c, e->stream);
+      if (st == FCH_OK && (hipEventRecord(ev[1], e->stream) != hipSuccess ||
+                           hipEventSynchronize(ev[1]) != hipSuccess))
+        st = FCH_E_HIP;
+      float ms = 0.f;
+      if (st == FCH_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) st = FCH_E_HIP;
+      if (st == FCH_OK && (!have || ms < best_ms)) {
+        best_ms = ms;
+        best_r = c.plan->rv;
+        best_c = c.plan->cv;
+        have = true;
+      }
+    }
+  }
+  c.plan->rv = (st == FCH_OK) ? best_r : keep_r;
+  c.plan->cv = (st == FCH_OK) ? best_c : keep_c;
+  const fch_status rs = restore(c.plan->rv);
+  if (st == FCH_OK) st = rs;
+  if (hipStreamSynchronize(e->stream) != hipSuccess && st == FCH_OK) st = FCH_E_HIP;
+  for (int k = c.first; k < c.first + c.count; ++k) e->hmem[k].nrow = N / c.plan->rv->R;
+  for (auto* x : ev)
+    if (x) (void)hipEventDestroy(x);
+  (void)hipFree(keep);
+  return st;
+}
+
+fch_status check_runnable(fch_ensemble_s* e) {
+  if (!e->ws) return FCH_E_NOMEM;
+  for (int k = 0; k < e->count; ++k)
+    if (!e->loaded[k]) return FCH_E_INVALID;
   return FCH_OK;
 }
 
@@ -262,6 +347,7 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   EnsClass* c = class_of(e, k);
   fch_plan_t p = c->plan;
   EnsMember& m = e->hmem[k];
+  HCHK(hipStreamSynchronize(e->stream));  // attempts still queued on the member
   const fch::Consts keep = p->c;
   p->c = m.c;  // the member's parameters for the setup calls
   const double k1 = e->opts.k_first > 0.0 ? e->opts.k_first : e->opts.adapt.k_min;
@@ -328,19 +414,9 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
 
 fch_status fch_ensemble_autotune(fch_ensemble_t e, int32_t reps) {
   if (!e || reps < 1) return FCH_E_INVALID;
-  for (auto& c : e->classes) {
-    const EnsMember& m = e->hmem[c.first];
-    if (!e->loaded[c.first]) return FCH_E_INVALID;
-    SCHK(fch_autotune(c.plan, (const fch_c128*)m.ring[m.cur], (const fch_c128*)m.ring[m.prev],
-                      m.ctl.k_n, reps, nullptr, nullptr));
-    // the row variant fixes the number of E_1 partial pairs SAV sums
-    const int nrow = e->prm[c.first].N / c.plan->rv->R;
-    for (int k = c.first; k < c.first + c.count; ++k) {
-      e->hmem[k].nrow = nrow;
-      HCHK(hipMemcpy(&e->dmem[k].nrow, &nrow, sizeof(int), hipMemcpyHostToDevice));
-    }
-  }
-  drop_graph(e);  // launch variants changed
+  SCHK(check_runnable(e));
+  drop_graph(e);  // launch variants change
+  for (auto& c : e->classes) SCHK(tune_class(e, c, reps));
   return FCH_OK;
 }
 
@@ -361,13 +437,6 @@ fch_status ensure_graph(fch_ensemble_s* e) {
     drop_graph(e);
     return FCH_E_HIP;
   }
-  return FCH_OK;
-}
-
-fch_status check_runnable(fch_ensemble_s* e) {
-  if (!e->ws) return FCH_E_NOMEM;
-  for (int k = 0; k < e->count; ++k)
-    if (!e->loaded[k]) return FCH_E_INVALID;
   return FCH_OK;
 }
 }  // namespace
@@ -442,7 +511,8 @@ fch_status fch_ensemble_member(fch_ensemble_t e, int32_t member, fch_c128* uh, d
   HCHK(hipStreamSynchronize(e->user_stream));
   HCHK(hipMemcpy(&m, e->dmem + k, sizeof(EnsMember), hipMemcpyDeviceToHost));
   if (uh)
-    HCHK(hipMemcpy(uh, m.ring[m.cur], spec_bytes(e->prm[k].N), hipMemcpyDeviceToDevice));
+    HCHK(hipMemcpyAsync(uh, m.ring[m.cur], spec_bytes(e->prm[k].N), hipMemcpyDeviceToDevice,
+                        e->user_stream));
   const long long nlog = std::min<long long>(m.accepted, m.klog_cap);
   if (klog && nlog > 0) HCHK(hipMemcpy(klog, m.klog, sizeof(double) * nlog, hipMemcpyDeviceToHost));
   if (info) {

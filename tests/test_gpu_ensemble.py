@@ -274,3 +274,58 @@ def test_ensemble_scheme_mixed_sizes_autotuned(F, scheme):
                       adapt=F.AdaptOpts(sigma_tol=1e-5), nsteps=12)
         assert ri["accepted"] == mi["accepted"] == 12
         assert rel(uh.cpu().numpy(), a.cpu().numpy()) < tol, i
+
+
+@pytest.mark.parametrize("scheme", ["imex", "sav"])
+def test_autotune_restores_members(F, scheme):
+    """The batched autotuner runs whole attempts of each class's members for
+    every variant pair, then restores them: states, step logs and counters
+    are bit for bit those before tuning, and a run after tuning matches an
+    untuned one to rounding with the same step counts."""
+    log("ensemble %s autotune restores members" % scheme)
+    mem = members_small()
+    ens = build_scheme(F, mem, scheme, use_max=20)
+    before = [ens.member(i) for i in range(len(mem))]
+    ens.autotune(reps=2)
+    for i in range(len(mem)):
+        u, k, mi = ens.member(i)
+        u0, k0, m0 = before[i]
+        assert torch.equal(u, u0) and np.array_equal(k, k0), i
+        assert mi == m0, (i, mi, m0)
+    ens.run(max_attempts=1000, sync_every=10, use_graph=True)
+    ref = build_scheme(F, mem, scheme, use_max=20)
+    ref.run(max_attempts=1000, sync_every=10, use_graph=True)
+    for i in range(len(mem)):
+        u, k, mi = ens.member(i)
+        r, kr, mr = ref.member(i)
+        assert mi["accepted"] == mr["accepted"] == 20 and mi["rejected"] == mr["rejected"], i
+        assert rel(u.cpu().numpy(), r.cpu().numpy()) < 1e-10, i
+        assert np.allclose(k, kr, rtol=1e-9, atol=0), i
+
+
+@pytest.mark.parametrize("N", [256, 1024])
+def test_device_control_every_variant(F, N):
+    """The batched stage kernels under every compiled (row, column) variant
+    pair: a device-controlled adaptive run (a one-member ensemble) of each
+    scheme gives the default variant's state and step counts to rounding."""
+    log("device control, every variant N=%d" % N)
+    rows, cols = F.config_list(N)
+    L = N * 4 * np.pi / 256
+    plan = F.Plan(N=N, L=L, eps=0.1, eta1=1.4, eta2=2.0)
+    u0 = torch.from_numpy(inputs.circle_bilayer(N, L, 0.1, seed=10)).cuda()
+
+    def go(scheme, cfg):
+        plan.set_config(cfg)
+        a = plan.forward(u0)
+        b = torch.empty_like(a)
+        ri = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=10.0,
+                      adapt=F.AdaptOpts(sigma_tol=1e-5), nsteps=6)
+        return a.cpu().numpy(), ri
+
+    for scheme in ("imex", "sav", "etd"):
+        ref, rr = go(scheme, None)
+        for r in rows:
+            for c in cols:
+                x, ri = go(scheme, r + c)
+                assert ri["accepted"] == rr["accepted"] and ri["rejected"] == rr["rejected"]
+                assert rel(x, ref) < 1e-12, (scheme, r, c)
