@@ -384,7 +384,10 @@ fch_status fch_ensemble_load(fch_ensemble_t ens, int32_t member, const double* u
  * temporary device copy of one class's member memory (hipMalloc) while it
  * runs.  Synchronizes. */
 fch_status fch_ensemble_autotune(fch_ensemble_t ens, int32_t reps);
-/* Runs attempts until every member finished or max_attempts attempts ran. */
+/* Runs attempts until every member finished or max_attempts attempts ran.
+ * FCH_E_NONFINITE if a member reached a non-finite state (that member stopped,
+ * the others ran on).  A SAV member that meets E_1 + D_0 <= 0 stops with
+ * fch_member_info.invalid set; the call still returns FCH_OK. */
 fch_status fch_ensemble_run(fch_ensemble_t ens, int64_t max_attempts, int32_t sync_every,
                             int32_t use_graph, fch_ensemble_info* info);
 /* Queues `attempts` attempts of all members (captured graph replays when

@@ -1,4 +1,4 @@
-// fch_ensemble.hip -- batched ensembles of adaptive BDF2-IMEX runs: size
+// fch_ensemble.hip -- batched ensembles of adaptive runs (BDF2-IMEX, BDF2-SAV or ETDRK2): size
 // classes, device-side step control and HIP-graph replay of one attempt.
 #include <hip/hip_runtime.h>
 

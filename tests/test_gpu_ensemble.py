@@ -329,3 +329,23 @@ def test_device_control_every_variant(F, N):
                 x, ri = go(scheme, r + c)
                 assert ri["accepted"] == rr["accepted"] and ri["rejected"] == rr["rejected"]
                 assert rel(x, ref) < 1e-12, (scheme, r, c)
+
+
+def test_ensemble_rejects_bad_scheme_options(F):
+    """PSD is not batched, and ETDRK2's stabilizers must be finite and >= 0:
+    fch_ensemble_create returns FCH_E_INVALID and creates nothing."""
+    import ctypes as C
+    log("ensemble bad scheme options")
+    m = members_small()[0]
+    prm = F.fch_params(m["N"], m["L"], m["eps"], m["eta1"], m["eta2"], 1, 0.0, 0.3, -1.0, 1.0,
+                       2.0, 1.0, m["zeta"], m["D0"])
+    arr = (F.fch_params * 1)(prm)
+    for scheme, k0, k2 in ((F.FCH_PSD, 0.01, 15.0), (7, 0.01, 15.0), (F.FCH_ETD, -1.0, 15.0),
+                           (F.FCH_ETD, 0.01, float("nan")), (F.FCH_ETD, float("inf"), 15.0)):
+        o = F.fch_ensemble_opts(F.AdaptOpts().c(), 1.0, 10, 0.0, 0.0, scheme,
+                                F.fch_etd_opts(k0, k2))
+        h = C.c_void_p()
+        assert F.lib().fch_ensemble_create(arr, 1, C.byref(o), C.byref(h)) == F.FCH_E_INVALID
+        assert not h.value
+    with pytest.raises(ValueError):
+        F.Ensemble([m], scheme="psd")
