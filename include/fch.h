@@ -299,7 +299,8 @@ fch_status fch_adapt_dt_dev(fch_plan_t plan, const fch_c128* uh_trial, const fch
  * k_first is taken from uh_n).  On return uh_n holds the last accepted state
  * and uh_nm1 the one before it.  Fixed-step runs (adaptive = 0) take nsteps
  * steps of size k (the startup step counts as one); adaptive runs follow
- * Sec. 3.2 until t_end or nsteps accepted steps.  *rs (SAV only, host in/out):
+ * Sec. 3.2 until t_end or nsteps accepted steps, their startup step being
+ * min(k_first, t_end) (k_first <= 0 selects adapt.k_min).  *rs (SAV only, host in/out):
  * r^n, r^{n-1}.  info (nullable, host out).
  * FCH_ETD (ETDRK2 with opts->etd, taken as given: zeros mean kappa0 = kappa2 = 0,
  * not the paper's values) is a one-step method: fixed runs take
@@ -344,7 +345,7 @@ typedef struct {
     fch_adapt_opts adapt;
     double  t_end;       /* end time of every member                              */
     int64_t max_steps;   /* cap on accepted steps per member (startup included)   */
-    double  k_first;     /* first-order startup step; <= 0 selects adapt.k_min    */
+    double  k_first;     /* startup step (<= 0: adapt.k_min), at most t_end       */
     double  umax_t0;     /* umax counts the accepted states at t >= umax_t0        */
     int32_t scheme;      /* FCH_IMEX (0), FCH_SAV or FCH_ETD for every member      */
     fch_etd_opts etd;    /* FCH_ETD: kappa0, kappa2, taken as given                */
@@ -415,7 +416,8 @@ fch_status fch_ensemble_member(fch_ensemble_t ens, int32_t member, fch_c128* uh,
  * the output, no activation).  H % 16 == 0, W % 32 == 0.  Products run on the
  * BF16 matrix cores with FP32 accumulation; stored activations are rounded
  * to bfloat16 (nearest, ties to even).  stream: a hipStream_t. */
-/* z = bias + conv(x, w); hidden: z and y = SiLU(z) (bf16); output: o (f32). */
+/* z = bias + conv(x, w); hidden: y = SiLU(z) and, unless z is null (inference:
+ * only training's backward pass reads z), z (bf16); output: o (f32). */
 fch_status fch_nn_conv_fwd(int32_t B, int32_t H, int32_t W, int32_t cout, const void* x,
                            const void* w, const float* bias, void* z, void* y, float* o,
                            void* stream);

@@ -1388,7 +1388,8 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   cd* Ft = p->Fc[2];
   double t = 0.0, k_n = o->k_prev, kt = o->k;
   if (o->startup) {
-    const double k1 = o->k_first > 0.0 ? o->k_first : ad->k_min;
+    // the startup step is clamped to the run like the last step (t_end > 0)
+    const double k1 = std::min(o->k_first > 0.0 ? o->k_first : ad->k_min, o->t_end);
     CHK(fch_rhs(p, (const fch_c128*)cur, (fch_c128*)Fm));
     if (o->scheme == FCH_IMEX) {
       CHK(imex_attempt(p, cur, cur, k1, -1.0, prev));

