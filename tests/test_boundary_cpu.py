@@ -88,3 +88,30 @@ def test_compiled_configurations(fch):
     assert fch.lib().fch_col_config_count(100) == 0
     c = fch.fch_launch_cfg()
     assert fch.lib().fch_config_get(1024, 99, 0, C.byref(c)) == fch.FCH_E_UNSUPPORTED
+
+
+def test_ensemble_create_rejects_bad_options_before_touching_the_device(fch):
+    """fch_ensemble_create validates its options and every member before any
+    device work: PSD is not batched, ETDRK2 stabilizers must be finite and
+    >= 0, t_end > 0, at least two steps, supported grid sizes."""
+    arr = (fch.fch_params * 1)(_prm(fch))
+    ok = dict(t_end=1.0, max_steps=10, k_first=0.0, umax_t0=0.0, scheme=fch.FCH_IMEX,
+              etd=(0.01, 15.0))
+
+    def opts(**kw):
+        o = dict(ok, **kw)
+        return fch.fch_ensemble_opts(fch.AdaptOpts().c(), o["t_end"], o["max_steps"],
+                                     o["k_first"], o["umax_t0"], o["scheme"],
+                                     fch.fch_etd_opts(*o["etd"]))
+
+    h = C.c_void_p()
+    for kw in (dict(scheme=fch.FCH_PSD), dict(scheme=7), dict(scheme=fch.FCH_ETD, etd=(-1.0, 15.0)),
+               dict(scheme=fch.FCH_ETD, etd=(0.01, float("nan"))), dict(t_end=0.0),
+               dict(max_steps=1), dict(umax_t0=float("nan"))):
+        assert fch.lib().fch_ensemble_create(arr, 1, C.byref(opts(**kw)), C.byref(h)) == \
+            fch.FCH_E_INVALID, kw
+        assert not h.value
+    assert fch.lib().fch_ensemble_create(arr, 0, C.byref(opts()), C.byref(h)) == fch.FCH_E_INVALID
+    big = (fch.fch_params * 1)(_prm(fch, N=8192))
+    assert fch.lib().fch_ensemble_create(big, 1, C.byref(opts()), C.byref(h)) == \
+        fch.FCH_E_UNSUPPORTED
