@@ -382,3 +382,30 @@ def test_ensemble_extreme_sizes_and_degenerate_runs(F):
                 assert mi["accepted"] == 2
             assert rel(uh.cpu().numpy(), a.cpu().numpy()) < 1e-12, (kw, i)
         ens.close()
+
+
+@pytest.mark.parametrize("scheme", ["sav", "etd"])
+def test_scheme_graph_replay_and_queued_steps_equal_eager(F, scheme):
+    """SAV and ETDRK2 ensembles: graph replays (run and queued fch_ensemble_step
+    chunks, with the host's own syncs between them) reach the eager launches'
+    states, step logs, counters and SAV scalars bit for bit."""
+    log("ensemble %s graph / queued / eager" % scheme)
+    mem = members_small()
+    ref = build_scheme(F, mem, scheme, use_max=25)
+    ref.run(max_attempts=1000, sync_every=1, use_graph=False)
+    e2 = build_scheme(F, mem, scheme, use_max=25)
+    for _ in range(200):
+        info = e2.run(max_attempts=1, sync_every=1, use_graph=True)
+        torch.cuda.synchronize()
+        if info["active"] == 0:
+            break
+    e3 = build_scheme(F, mem, scheme, use_max=25)
+    for _ in range(30):   # more attempts than any member needs: finished ones idle
+        e3.step(attempts=4, use_graph=True)
+    e3.run(max_attempts=1, sync_every=1, use_graph=True)
+    for i in range(len(mem)):
+        a, ka, ma = ref.member(i)
+        for e in (e2, e3):
+            b, kb, mb = e.member(i)
+            assert ma == mb, (i, ma, mb)
+            assert np.array_equal(ka, kb) and torch.equal(a, b), i
