@@ -369,7 +369,8 @@ fch_status fch_ensemble_create(const fch_params* members, int32_t count,
 fch_status fch_ensemble_destroy(fch_ensemble_t ens);
 fch_status fch_ensemble_set_stream(fch_ensemble_t ens, void* stream);
 /* Device workspace for every member (three states, three F spectra, the
- * pair buffer, partial sums, the step log) and each class plan. */
+ * pair buffer, partial sums, the step log) and each class plan.  Setting a
+ * workspace (again) leaves every member unloaded: load them before a run. */
 size_t     fch_ensemble_workspace_bytes(fch_ensemble_t ens);
 fch_status fch_ensemble_set_workspace(fch_ensemble_t ens, void* dptr, size_t bytes);
 /* Loads member i from a physical N*N state (device): forward transform,

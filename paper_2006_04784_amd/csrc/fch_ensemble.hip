@@ -333,9 +333,15 @@ fch_status fch_ensemble_set_workspace(fch_ensemble_t e, void* dptr, size_t bytes
   if (!e || !dptr || ((uintptr_t)dptr & 255)) return FCH_E_INVALID;
   if (bytes < layout(e, false)) return FCH_E_NOMEM;
   drop_graph(e);
+  if (e->stream) HCHK(hipStreamSynchronize(e->stream));  // attempts on the old workspace
   e->ws = (char*)dptr;
   e->ws_bytes = bytes;
   layout(e, true);
+  // members live in the workspace: a new one holds none of them yet
+  for (int k = 0; k < e->count; ++k) {
+    e->loaded[k] = 0;
+    e->hmem[k].ctl.done = 1;
+  }
   HCHK(hipMemcpy(e->dmem, e->hmem.data(), sizeof(EnsMember) * e->count, hipMemcpyHostToDevice));
   return FCH_OK;
 }

@@ -409,3 +409,31 @@ def test_scheme_graph_replay_and_queued_steps_equal_eager(F, scheme):
             b, kb, mb = e.member(i)
             assert ma == mb, (i, ma, mb)
             assert np.array_equal(ka, kb) and torch.equal(a, b), i
+
+
+def test_new_workspace_needs_reloaded_members(F):
+    """A workspace set again holds no member: running refuses (FCH_E_INVALID)
+    until every member is loaded into it, and then reaches the same states as
+    an ensemble that never moved."""
+    import ctypes as C
+    log("ensemble workspace moved")
+    mem = members_small()[:3]
+    ref = build(F, mem, use_max=15)
+    ref.run(max_attempts=500, sync_every=5, use_graph=True)
+    ens = build(F, mem, use_max=15)
+    nbytes = F.lib().fch_ensemble_workspace_bytes(ens.h)
+    ws2 = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws2.data_ptr()) % 256
+    assert F.lib().fch_ensemble_set_workspace(ens.h, C.c_void_p(ws2.data_ptr() + off),
+                                              nbytes) == F.FCH_OK
+    ens.ws = ws2
+    with pytest.raises(F.FchError) as ei:
+        ens.run(max_attempts=5, sync_every=5, use_graph=True)
+    assert ei.value.code == F.FCH_E_INVALID
+    for i, m in enumerate(mem):
+        ens.load(i, torch.from_numpy(initial(m, seed=10 + i)).cuda())
+    ens.run(max_attempts=500, sync_every=5, use_graph=True)
+    for i in range(len(mem)):
+        a, ka, ma = ens.member(i)
+        b, kb, mb = ref.member(i)
+        assert ma == mb and np.array_equal(ka, kb) and torch.equal(a, b), i
