@@ -169,8 +169,10 @@ fch_status tune_class(fch_ensemble_s* e, EnsClass& c, int reps) {
   if (hipMalloc((void**)&keep, region) != hipSuccess) return FCH_E_NOMEM;
   hipEvent_t ev[2] = {nullptr, nullptr};
   fch_status st = FCH_OK;
-  if (hipMemcpyAsync(keep, base, region, hipMemcpyDeviceToDevice, e->stream) != hipSuccess ||
-      hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+  // without a snapshot nothing may run, and nothing is restored
+  const bool snap =
+      hipMemcpyAsync(keep, base, region, hipMemcpyDeviceToDevice, e->stream) == hipSuccess;
+  if (!snap || hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
     st = FCH_E_HIP;
   std::vector<EnsMember> trial = saved;
   auto restore = [&](const fch::RowVT* rv) -> fch_status {
@@ -209,8 +211,10 @@ fch_status tune_class(fch_ensemble_s* e, EnsClass& c, int reps) {
   }
   c.plan->rv = (st == FCH_OK) ? best_r : keep_r;
   c.plan->cv = (st == FCH_OK) ? best_c : keep_c;
-  const fch_status rs = restore(c.plan->rv);
-  if (st == FCH_OK) st = rs;
+  if (snap) {
+    const fch_status rs = restore(c.plan->rv);
+    if (st == FCH_OK) st = rs;
+  }
   if (hipStreamSynchronize(e->stream) != hipSuccess && st == FCH_OK) st = FCH_E_HIP;
   for (int k = c.first; k < c.first + c.count; ++k) e->hmem[k].nrow = N / c.plan->rv->R;
   for (auto* x : ev)
