@@ -27,6 +27,15 @@ from . import fch, inputs
 DEFECT_THRESHOLD = 0.55   # between the bilayer's peak (0.3566) and a defect's (about 0.74)
 
 
+def onset(ds, umax, threshold=DEFECT_THRESHOLD):
+    """(smallest d whose running max of u crosses the threshold, largest d that
+    does not), either None when there is no such d (Sec. 5.1 defect onset; a
+    NaN maximum counts as no defect)."""
+    over = [d for d, u in zip(ds, umax) if u > threshold]
+    under = [d for d, u in zip(ds, umax) if not u > threshold]
+    return (min(over) if over else None), (max(under) if under else None)
+
+
 def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_THRESHOLD,
                      N=256, physical_k=False, max_steps=1000000, device="cuda:0", log=None,
                      chunk=5000, scheme="imex"):
@@ -59,16 +68,14 @@ def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_
     wall = time.perf_counter() - tw
     rows = [ens.member(i, state=False, klog=False)[2] for i in range(len(ds))]
     umax = [r["umax"] for r in rows]
-    over = [d for d, u in zip(ds, umax) if u > threshold]
-    under = [d for d, u in zip(ds, umax) if not u > threshold]
+    d_crit, d_free = onset(ds, umax, threshold)
     if any(r["nonfinite"] for r in rows):
         raise RuntimeError("a member reached a non-finite state")
     if any(r["invalid"] for r in rows):
         raise RuntimeError("a SAV member reached E_1 + D_0 <= 0")
     return {"scheme": scheme, "d": ds, "umax": umax, "accepted": [r["accepted"] for r in rows],
             "rejected": [r["rejected"] for r in rows], "t": [r["t"] for r in rows],
-            "d_critical": min(over) if over else None,
-            "d_max_without_defect": max(under) if under else None, "attempts": attempts,
+            "d_critical": d_crit, "d_max_without_defect": d_free, "attempts": attempts,
             "seconds": wall}
 
 

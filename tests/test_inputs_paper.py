@@ -54,3 +54,20 @@ def test_finer_grids_interpolate(ics, N):
     s = N // 256
     assert np.max(np.abs(u[::s, ::s] - u256)) < 1e-12
     assert abs(_mass(kw, u) - _mass(dict(kw, N=256), u256)) < 1e-10
+
+
+def test_defect_onset_from_running_maxima():
+    """Sec. 5.1's reading: the onset is the smallest d whose running max of u
+    crosses the threshold; the sweep also reports the largest d without a
+    defect, which exceeds the onset when the outcome is not monotone in d."""
+    from paper_2006_04784_amd import sweeps
+    ds = sweeps.paper_d_values()
+    assert len(ds) == 206 and ds[0] == 0.7523 and ds[-1] == 0.7728
+    assert all(abs(b - a - 1e-4) < 1e-12 for a, b in zip(ds, ds[1:]))
+    um = [0.358 if d < 0.7600 else 0.75 for d in ds]
+    assert sweeps.onset(ds, um) == (0.76, 0.7599)
+    um[ds.index(0.7650)] = 0.357          # one member above the onset without a defect
+    assert sweeps.onset(ds, um) == (0.76, 0.765)
+    assert sweeps.onset(ds, [0.358] * len(ds)) == (None, 0.7728)
+    assert sweeps.onset(ds, [float("nan")] * len(ds)) == (None, 0.7728)
+    assert sweeps.onset(ds, [0.9] * len(ds)) == (0.7523, None)
