@@ -115,3 +115,28 @@ def test_ensemble_create_rejects_bad_options_before_touching_the_device(fch):
     big = (fch.fch_params * 1)(_prm(fch, N=8192))
     assert fch.lib().fch_ensemble_create(big, 1, C.byref(opts()), C.byref(h)) == \
         fch.FCH_E_UNSUPPORTED
+
+
+def test_every_entry_point_rejects_null_arguments(fch):
+    """Each compute entry point checks its handle and pointers on the host
+    before any device work: all-null (and zero-size) arguments return
+    FCH_E_INVALID, and the size queries return 0 for a null handle."""
+    L = fch.lib()
+    sizes = {"fch_plan_workspace_bytes", "fch_ensemble_workspace_bytes",
+             "fch_inverse_batch_ws_bytes", "fch_nn_bwd_w_scratch_floats",
+             "fch_nn_features_work_doubles"}
+    host_only = {"fch_sav_constants", "fch_alpha_m", "fch_row_config_count",
+                 "fch_col_config_count", "fch_config_get", "fch_status_string"}
+    checked = 0
+    for name, (res, args) in fch._SIGS.items():
+        if name in host_only:
+            continue
+        vals = [0 if a in (C.c_int32, C.c_int64, C.c_size_t, C.c_double) else None for a in args]
+        r = getattr(L, name)(*vals)
+        if name in sizes:
+            if args[0] is C.c_void_p:
+                assert r == 0, name
+        else:
+            assert r == fch.FCH_E_INVALID, (name, r)
+        checked += 1
+    assert checked > 50
