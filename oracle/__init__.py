@@ -377,8 +377,9 @@ def etd_step(m: Model, uh_n, k, kappa0=KAPPA0, kappa2=KAPPA2, fh_n=None, fh_np1=
 def run_fixed(m: Model, scheme: str, uh0, k: float, nsteps: int, r0=None, psd_tol=1e-10,
               psd_iters=None, record=False):
     """Fixed-step trajectory: a first-order startup step from u^0, then BDF2
-    steps of size k (ETDRK2, a one-step method, takes nsteps equal steps).  ``psd_iters`` (list) replays a per-step PSD iteration
-    count.  Returns the final spectrum (and the list of states if record)."""
+    steps of size k (ETDRK2, a one-step method, takes nsteps equal steps).
+    ``psd_iters`` (list) replays a per-step PSD iteration count.  Returns the
+    final spectrum (and the list of states if record)."""
     un = _cplx(uh0)
     um = None
     r_n = r_nm1 = None
