@@ -437,3 +437,38 @@ def test_new_workspace_needs_reloaded_members(F):
         a, ka, ma = ens.member(i)
         b, kb, mb = ref.member(i)
         assert ma == mb and np.array_equal(ka, kb) and torch.equal(a, b), i
+
+
+def test_adaptive_512_step_sequence_matches_oracle_controller(F, orc):
+    """The 512^2 workload (six perturbed circles, eps 0.05) run adaptively to
+    t = 0.01 at sigma_tol 1e-5 from k_first = 1e-9: the device-controlled
+    attempts accept the same steps as the oracle's steppers driven by the
+    oracle's own AM3 estimate and Sec. 3.2 controller, and end on the same
+    state."""
+    log("adaptive 512^2 step sequence vs the oracle controller")
+    kw, u0 = inputs.workload("c2")
+    ens = F.Ensemble([kw], adapt=F.AdaptOpts(sigma_tol=1e-5), t_end=0.01, max_steps=100000,
+                     k_first=1e-9)
+    ens.load(0, torch.from_numpy(u0).cuda())
+    ens.run(max_attempts=100000, sync_every=100, use_graph=True)
+    uh, klog, mi = ens.member(0)
+    m = orc.Model(**kw)
+    prev = orc.r2c(u0)
+    cur = orc.imex_step(m, prev, None, 1e-9, -1.0)
+    Fm, Fn = orc.F(m, prev), orc.F(m, cur)
+    ks, t, kn, kt = [1e-9], 1e-9, 1e-9, 1e-9
+    while t < 0.01 * (1 - 1e-14):
+        kt = min(kt, 0.01 - t)
+        trial = orc.imex_step(m, cur, prev, kt, kn)
+        Ft = orc.F(m, trial)
+        e = orc.am3_error(m, trial, cur, Ft, Fn, Fm, kt, kn)
+        ok, knext = orc.adapt_decide(e, kt, 1e-5, 1e-9, float("inf"))
+        if ok:
+            prev, cur, Fm, Fn = cur, trial, Fn, Ft
+            t, kn = t + kt, kt
+            ks.append(kt)
+        kt = knext
+    assert mi["accepted"] == len(ks) and len(klog) == len(ks)
+    assert np.allclose(klog, ks, rtol=1e-9, atol=0)
+    assert abs(mi["t"] - t) < 1e-12
+    assert rel(uh.cpu().numpy().T, cur) < 1e-8
