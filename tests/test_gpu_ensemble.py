@@ -439,36 +439,57 @@ def test_new_workspace_needs_reloaded_members(F):
         assert ma == mb and np.array_equal(ka, kb) and torch.equal(a, b), i
 
 
-def test_adaptive_512_step_sequence_matches_oracle_controller(F, orc):
+@pytest.mark.parametrize("scheme", ["imex", "sav"])
+def test_adaptive_512_step_sequence_matches_oracle_controller(F, orc, scheme):
     """The 512^2 workload (six perturbed circles, eps 0.05) run adaptively to
     t = 0.01 at sigma_tol 1e-5 from k_first = 1e-9: the device-controlled
     attempts accept the same steps as the oracle's steppers driven by the
     oracle's own AM3 estimate and Sec. 3.2 controller, and end on the same
-    state."""
-    log("adaptive 512^2 step sequence vs the oracle controller")
+    state (and, for SAV, the same r)."""
+    log("adaptive 512^2 %s step sequence vs the oracle controller" % scheme)
     kw, u0 = inputs.workload("c2")
     ens = F.Ensemble([kw], adapt=F.AdaptOpts(sigma_tol=1e-5), t_end=0.01, max_steps=100000,
-                     k_first=1e-9)
+                     k_first=1e-9, scheme=scheme)
     ens.load(0, torch.from_numpy(u0).cuda())
     ens.run(max_attempts=100000, sync_every=100, use_graph=True)
     uh, klog, mi = ens.member(0)
-    m = orc.Model(**kw)
+    z, d0 = F.sav_constants(F.fch_params(*[dict(kw, p=kw.get("p", 1), q=kw.get("q", 0.0),
+                                                gamma_w=kw.get("gamma_w", 0.3),
+                                                b_minus=-1.0, b_plus=1.0, beta1=2.0,
+                                                beta2=1.0, zeta=0.0, D0=0.0)[k]
+                                           for k, _ in F.fch_params._fields_]))
+    m = orc.Model(**dict(kw, zeta=z, D0=d0))
     prev = orc.r2c(u0)
-    cur = orc.imex_step(m, prev, None, 1e-9, -1.0)
+    if scheme == "sav":
+        r_prev = float(np.sqrt(orc.E1(m, prev) + m.D0))
+        cur, r_cur = orc.sav_step(m, prev, None, r_prev, r_prev, 1e-9, -1.0)
+    else:
+        cur = orc.imex_step(m, prev, None, 1e-9, -1.0)
     Fm, Fn = orc.F(m, prev), orc.F(m, cur)
     ks, t, kn, kt = [1e-9], 1e-9, 1e-9, 1e-9
     while t < 0.01 * (1 - 1e-14):
         kt = min(kt, 0.01 - t)
-        trial = orc.imex_step(m, cur, prev, kt, kn)
+        if scheme == "sav":
+            trial, r_trial = orc.sav_step(m, cur, prev, r_cur, r_prev, kt, kn)
+        else:
+            trial = orc.imex_step(m, cur, prev, kt, kn)
         Ft = orc.F(m, trial)
         e = orc.am3_error(m, trial, cur, Ft, Fn, Fm, kt, kn)
         ok, knext = orc.adapt_decide(e, kt, 1e-5, 1e-9, float("inf"))
         if ok:
             prev, cur, Fm, Fn = cur, trial, Fn, Ft
+            if scheme == "sav":
+                r_prev, r_cur = r_cur, r_trial
             t, kn = t + kt, kt
             ks.append(kt)
         kt = knext
     assert mi["accepted"] == len(ks) and len(klog) == len(ks)
-    assert np.allclose(klog, ks, rtol=1e-9, atol=0)
+    # k_next ~ e^(-1/3), and the estimate e (about sigma_tol) is a difference
+    # of nearby states: a state difference of 1e-12 relative moves k by about
+    # 1e-12 / (3 sigma_tol) ~ 3e-8
+    assert np.allclose(klog, ks, rtol=1e-6, atol=0), np.max(np.abs(klog / ks - 1))
     assert abs(mi["t"] - t) < 1e-12
     assert rel(uh.cpu().numpy().T, cur) < 1e-8
+    if scheme == "sav":
+        assert abs(mi["r_n"] - r_cur) < 1e-9 * abs(r_cur)
+        assert abs(mi["r_nm1"] - r_prev) < 1e-9 * abs(r_prev)
