@@ -193,6 +193,24 @@ fch_status fch_chem_potential(fch_plan_t plan, const fch_c128* uh, fch_c128* muh
 fch_status fch_step_imex(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
                          double k_np1, double k_n, fch_c128* uh_np1);
 
+/* The same BDF2-IMEX step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It needs no fch_plan_set_workspace: its two intermediate half
+ * spectra live in a library-owned device array of 2 * 16 * N_max * (N_max/2+1)
+ * bytes (4.02 MiB at N_max = FCH_STATIC_MAX_N = 512), which each GPU the
+ * library runs on holds until the process ends.  It calls no hipMalloc,
+ * hipFree or allocating library routine; the plan (created beforehand, on
+ * this device) supplies twiddles and the control block.  Results equal
+ * fch_step_imex's bit for bit under the same launch configuration.
+ * FCH_E_UNSUPPORTED if the plan's N exceeds FCH_STATIC_MAX_N; other argument
+ * rules as fch_step_imex.  Every call on one GPU shares that GPU's array and
+ * leaves its contents behind (nothing in it has to start at zero): calls
+ * that overlap on one GPU, from any plan, stream or thread, race and must be
+ * serialized by the caller. */
+#define FCH_STATIC_MAX_N 512
+fch_status fch_step_imex_static(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                                double k_np1, double k_n, fch_c128* uh_np1);
+
 /* BDF2-SAV (eqs. 4.7, 4.8) with L_0, L_1 of eqs. e:SAV-L0, e:SAV-L1:
  * u^{n+1} = p + r^{n+1} q, (a + |k|^2 L_0) p = -b u^n - c u^{n-1} - |k|^2 L_1 u*,
  * (a + |k|^2 L_0) q = -|k|^2 X, X = V(u*)/sqrt(E_1(u*) + D_0), V = mu - L_SAV u,

@@ -8,6 +8,7 @@
 #include <utility>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "fch.h"
@@ -163,9 +164,13 @@ fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
   return FCH_OK;
 }
 
-fch_status row_mu(fch_plan_s* p, double* partial) {
+fch_status row_mu(fch_plan_s* p, double* partial, cd* pair0 = nullptr, cd* pair1 = nullptr) {
   RowArgs a = row_args(p);
   a.partial = partial;
+  if (pair0) {
+    a.P0 = pair0;
+    a.P1 = pair1;
+  }
   const int r = prof_begin(p, 0);
   HIPCHK(p->rv->row(fch::ROW_MU, a, p->stream, nullptr, nullptr));
   prof_end(p, r);
@@ -221,18 +226,23 @@ fch_status psd_iterations(fch_plan_s* p, const ColArgs& a, int done_before, int 
 }
 
 
-// one chemical-potential evaluation of the field already column-inverted in
-// the pair buffer, ending in the given epilogue
+// one BDF2-IMEX step: inverse column pass of (u*, Lap u*), row pass, forward
+// column pass with the IMEX epilogue.  pair0/pair1 (nullable) replace the
+// workspace's pair buffer.
 fch_status imex_attempt(fch_plan_s* p, const cd* un, const cd* um, double k_np1, double k_n,
-                        cd* out) {
+                        cd* out, cd* pair0 = nullptr, cd* pair1 = nullptr) {
   StepCtl v = ctl_zero();
   set_bdf2(v, k_np1, k_n);
   CHK(ctl_set(p, v));
   ColArgs a = col_args(p);
+  if (pair0) {
+    a.P0 = pair0;
+    a.P1 = pair1;
+  }
   a.s0 = un;
   a.s1 = um ? um : un;
   CHK(col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a));
-  CHK(row_mu(p, nullptr));
+  CHK(row_mu(p, nullptr, pair0, pair1));
   a.out = out;
   CHK(col(p, fch::EPI_IMEX, fch::PRO_NONE, a));
   p->stats.fft_calls += 4;
@@ -281,6 +291,45 @@ fch_status validate_params_internal(const fch_params* p) { return validate_param
 }  // namespace fch
 
 static fch_status copy_spec(fch_plan_t p, cd* dst, const cd* src);
+
+// ---- scratch of the no-allocation IMEX step ----------------------------------
+// fch_step_imex_static keeps its pair buffer (the two half spectra that the
+// row and column passes hand to each other) in this file-scope device array
+// instead of the caller's workspace.  Each GPU holds its own copy for the
+// life of the process.  In host code `scratch` names a host-side stand-in, not
+// a device address: the device address is taken once per device with
+// hipGetSymbolAddress (scratch_resolve) and only that pointer is ever handed
+// to kernels.
+namespace {
+constexpr int kStaticMaxN = FCH_STATIC_MAX_N;
+constexpr size_t kStaticSpec = (size_t)(kStaticMaxN / 2 + 1) * kStaticMaxN * sizeof(cd);
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) char scratch[2 * kStaticSpec];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// device address of `scratch` on device dev, resolved on first use with that
+// device current (the caller's current device is restored)
+fch_status scratch_resolve(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return FCH_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != dev) HIPCHK(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return FCH_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return FCH_OK;
+}
+}  // namespace
 
 // ===========================================================================
 extern "C" {
@@ -360,6 +409,11 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
     return FCH_E_HIP;
   }
   std::memset(p->hctl, 0, sizeof(StepCtl));
+  char* sp = nullptr;
+  if (scratch_resolve(p->device, &sp) != FCH_OK) {
+    fch_plan_destroy(p);
+    return FCH_E_HIP;
+  }
   *out = p;
   return FCH_OK;
 }
@@ -732,6 +786,21 @@ fch_status fch_step_imex(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_
   CHK(check_step(p, uh_n, uh_nm1, k_np1, k_n, uh_np1));
   const cd* um = (k_n > 0.0) ? (const cd*)uh_nm1 : (const cd*)uh_n;
   return imex_attempt(p, (const cd*)uh_n, um, k_np1, k_n, (cd*)uh_np1);
+}
+
+fch_status fch_step_imex_static(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_nm1,
+                                double k_np1, double k_n, fch_c128* uh_np1) {
+  if (!p || !uh_n || !uh_np1) return FCH_E_INVALID;
+  if (p->N > kStaticMaxN) return FCH_E_UNSUPPORTED;
+  if (!finite_pos(k_np1) || !std::isfinite(k_n)) return FCH_E_INVALID;
+  if (k_n > 0.0 && !uh_nm1) return FCH_E_INVALID;
+  if ((const void*)uh_np1 == (const void*)uh_n) return FCH_E_INVALID;
+  char* sp = nullptr;
+  CHK(scratch_resolve(p->device, &sp));
+  cd* pair0 = (cd*)sp;
+  cd* pair1 = (cd*)(sp + align256(spec_bytes(p->N)));
+  const cd* um = (k_n > 0.0) ? (const cd*)uh_nm1 : (const cd*)uh_n;
+  return imex_attempt(p, (const cd*)uh_n, um, k_np1, k_n, (cd*)uh_np1, pair0, pair1);
 }
 
 fch_status fch_sav_r(fch_plan_t p, const fch_c128* uh, double* r) {

@@ -21,6 +21,8 @@ _lib = None
 FCH_OK, FCH_E_INVALID, FCH_E_UNSUPPORTED, FCH_E_HIP, FCH_E_NOMEM, FCH_E_NOCONV, FCH_E_NONFINITE = \
     0, -1, -2, -3, -4, -5, -6
 FCH_IMEX, FCH_SAV, FCH_PSD, FCH_ETD = 0, 1, 2, 3
+# largest N of fch_step_imex_static (FCH_STATIC_MAX_N)
+STATIC_MAX_N = 512
 # the ETDRK2 split constants used for every simulation of Sec. 3.6
 ETD_KAPPA0, ETD_KAPPA2 = 1e-2, 15.0
 
@@ -139,6 +141,7 @@ _SIGS = {
     "fch_inverse": (_I, [_V, _V, _V]),
     "fch_chem_potential": (_I, [_V, _V, _V, _PD]),
     "fch_step_imex": (_I, [_V, _V, _V, _D, _D, _V]),
+    "fch_step_imex_static": (_I, [_V, _V, _V, _D, _D, _V]),
     "fch_step_etd": (_I, [_V, _V, _V, _D, C.POINTER(fch_etd_opts), _V]),
     "fch_step_etd_dev": (_I, [_V, _V, _V, _V, C.POINTER(fch_etd_opts), _V, _V]),
     "fch_step_sav": (_I, [_V, _V, _V, _D, _D, _D, _D, _V, _PD]),
@@ -413,6 +416,15 @@ class Plan:
         out = self.spec() if out is None else out
         self._sync_stream()
         _check(lib().fch_step_imex(self.h, _p(uh_n), _p(uh_nm1), k_np1, k_n, _p(out)))
+        return out
+
+    def step_imex_static(self, uh_n, uh_nm1, k_np1, k_n, out=None):
+        """fch_step_imex_static: the IMEX step with the library's own scratch
+        (N <= STATIC_MAX_N); needs no workspace and allocates nothing."""
+        self._chk_spec(uh_n, uh_nm1)
+        out = self.spec() if out is None else out
+        self._sync_stream()
+        _check(lib().fch_step_imex_static(self.h, _p(uh_n), _p(uh_nm1), k_np1, k_n, _p(out)))
         return out
 
     def step_etd(self, uh_n, k, F_n=None, kappa0=ETD_KAPPA0, kappa2=ETD_KAPPA2, out=None):
