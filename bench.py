@@ -9,10 +9,14 @@ launch chain (row pass, column pass) of the library.
 
 The same JSON line carries:
   roofline     -- the dominant kernel's algorithmic bytes per launch over its
-                  average duration (HIP events on the plan's stream during a
-                  second, instrumented pass of the same steps), against 8 TB/s;
-                  traffic from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-                  summary when it was taken on the current kernel source;
+                  average duration in the timed steps (each launch records its
+                  start on the device clock; a kernel's time is the interval to
+                  the next launch's start in the back-to-back chain), against
+                  8 TB/s; traffic from the committed rocprofv3 FETCH_SIZE /
+                  WRITE_SIZE summary when it was taken on the current kernel
+                  source;
+  roofline_streaming -- the same for the 2048^2 adaptive PSD run (working set
+                  beyond the 256 MB Infinity Cache);
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
   extra        -- SAV steps/s, adaptive IMEX accepted steps/s, PSD iterations/s
                   and FFT calls per PSD step, 2D FFT GB/s on a 32-field batch.
@@ -60,6 +64,34 @@ def read_traffic(kernel_class):
         return None
     key = "%s_bytes_per_launch" % kernel_class
     return float(kv[key]) if key in kv else None
+
+
+def hbm_roofline(kernels, label, extra=None):
+    """Roofline object of the dominant kernel (largest total time) among
+    kernels = {name: (algorithmic bytes per launch, avg seconds, launches)}."""
+    dom = max(kernels, key=lambda kk: kernels[kk][1] * kernels[kk][2])
+    nbytes, avg, count = kernels[dom]
+    achieved = nbytes / avg / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+           "kernel": dom, "workload": label, "bytes_per_launch": nbytes,
+           "avg_us": round(avg * 1e6, 3),
+           "timing": "device clock in the timed region: start of each launch to the next "
+                     "launch's start in the back-to-back chain, %d launches" % count,
+           "other_kernels": {kk: {"avg_us": round(v[1] * 1e6, 3), "bytes_per_launch": v[0],
+                                  "GBps": round(v[0] / v[1] / 1e9, 1), "launches": v[2]}
+                             for kk, v in kernels.items()}}
+    out.update(extra or {})
+    return out
+
+
+def prof_kernels(prof, row_bytes, col_bytes, col_name):
+    """(bytes, avg seconds, launches) of the row pass and the fused column pass
+    from a plan's mode-2 kernel timing (fch_plan_profile_read)."""
+    rn, rms = prof["row_mu"]
+    cn, cms = prof["col_fused"]
+    return {"row_mu": (row_bytes, rms * 1e-3 / max(rn, 1), rn),
+            col_name: (col_bytes, cms * 1e-3 / max(cn, 1), cn)}
 
 
 def main():
@@ -114,49 +146,37 @@ def main():
     plan.run(a, b, scheme="imex", nsteps=args.warmup, k=k, k_prev=k, startup=False)
     torch.cuda.synchronize()
 
+    # the timed steps also carry the kernel timing (each launch's start on the
+    # device clock; nothing is added to the stream)
     log("timed %d steps" % args.steps)
+    plan.profile(2)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record()
     plan.run(a, b, scheme="imex", nsteps=args.steps, k=k, k_prev=k, startup=False)
+    ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile(False)
     dt = t1 - t0
     steps_per_s = args.steps / dt
     ms_per_step = 1e3 * dt / args.steps
     if not torch.isfinite(a).all():
         raise RuntimeError("non-finite state after the timed run")
 
-    # ---- roofline: per-kernel durations from HIP events -----------------
-    log("instrumented pass (HIP events per launch)")
-    nprof = min(args.steps, 4000)
-    plan.profile(True)
-    plan.run(a, b, scheme="imex", nsteps=nprof, k=k, k_prev=k, startup=False)
-    prof = plan.profile_read()
-    plan.profile(False)
-    row_n, row_ms = prof["row_mu"]
-    col_n, col_ms = prof["col_fused"]
-    row_avg = row_ms / max(row_n, 1) * 1e-3
-    col_avg = col_ms / max(col_n, 1) * 1e-3
-    kernels = {
-        # algorithmic bytes per launch (each half spectrum S = 16 N (N/2+1) B)
-        "row_mu": {"bytes": 4 * S, "avg_s": row_avg, "count": row_n},
-        "col_imex_fused": {"bytes": 7 * S, "avg_s": col_avg, "count": col_n},
-    }
-    dom = max(kernels, key=lambda kk: kernels[kk]["avg_s"] * max(kernels[kk]["count"], 1))
-    kd = kernels[dom]
-    achieved = kd["bytes"] / kd["avg_s"] / 1e9
-    traffic = read_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": traffic, "kernel": dom,
-                "bytes_per_launch": kd["bytes"], "avg_us": round(kd["avg_s"] * 1e6, 3),
-                "other_kernels": {kk: {"avg_us": round(v["avg_s"] * 1e6, 3),
-                                       "bytes_per_launch": v["bytes"],
-                                       "GBps": round(v["bytes"] / v["avg_s"] / 1e9, 1)}
-                                  for kk, v in kernels.items()},
-                "step_bytes": 11 * S,
-                "step_GBps": round(11 * S * steps_per_s / 1e9, 1)}
+    # ---- roofline: the dominant kernel of the timed steps -------------------
+    kern = prof_kernels(prof, 4 * S, 7 * S, "col_imex_fused")
+    roofline = hbm_roofline(kern, "m1 1024^2 fixed-step BDF2-IMEX", {
+        "step_bytes": 11 * S,
+        "step_us_events": round(ev0.elapsed_time(ev1) * 1e3 / args.steps, 3),
+        "step_GBps": round(11 * S * steps_per_s / 1e9, 1),
+        "step_frac": round(11 * S * steps_per_s / 1e9 / PEAK_HBM_GBS, 4)})
+    roofline["traffic"] = read_traffic(roofline["kernel"])
 
     extra = {}
+    roofline_streaming = None
     if not args.no_extra and not args.ensemble_only:
         # SAV, fixed step
         log("SAV fixed step")
@@ -260,6 +280,7 @@ def main():
         a3 = plan3.forward(torch.from_numpy(u3).to(dev))
         b3 = torch.empty_like(a3)
         plan3.reset_stats()
+        plan3.profile(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info3 = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
@@ -267,6 +288,8 @@ def main():
                           adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
         torch.cuda.synchronize()
         el3 = time.perf_counter() - t0
+        prof3 = plan3.profile_read()
+        plan3.profile(False)
         S3 = spec_bytes(kw3["N"])
         acc3 = info3["accepted"]
         extra["c3_psd_adaptive_2048"] = {
@@ -277,6 +300,17 @@ def main():
             "ms_per_step": round(1e3 * el3 / acc3, 3),
             "psd_iteration_GBps": round(11 * S3 * info3["psd_iters"] / el3 / 1e9, 1),
             "bytes_per_psd_iteration": 11 * S3}
+        # streaming roofline: the same run's kernels (working set: u^n, u^{n-1},
+        # the iterate, b u^n + c u^{n-1}, the pair buffer and three F caches,
+        # 9S = 302 MB, beyond the 256 MB Infinity Cache); row passes of the PSD
+        # iterations and of the error estimate, PSD column passes
+        kern3 = prof_kernels(prof3, 4 * S3, 7 * S3, "col_psd_fused")
+        roofline_streaming = hbm_roofline(
+            kern3, "c3 2048^2 adaptive BDF2-PSD, first 100 accepted steps (40 loops + random "
+                   "field, working set 9S = %.0f MB)" % (9 * S3 / 1e6),
+            {"iteration_bytes": 11 * S3,
+             "iteration_frac": round(11 * S3 / (kern3["row_mu"][1] + kern3["col_psd_fused"][1])
+                                     / 1e9 / PEAK_HBM_GBS, 4)})
         del plan3, a3, b3
         # 2D FFT bandwidth, streaming regime: R2C then C2R over a 32-field batch
         # (269 MB physical + 269 MB spectral + 269 MB staging, beyond the 256 MB
@@ -327,19 +361,12 @@ def main():
                 "accepted_steps_per_s": round(sum(sw["accepted"]) / sw["seconds"], 1)}
         # batched ensemble: 64 adaptive IMEX runs of mixed size in captured graphs
         log("ensemble of 64 mixed-size adaptive runs")
-        rng = np.random.default_rng(2024)
-        mem = []
-        for i in range(64):
-            Ni = int(rng.choice([128, 256, 512, 1024]))
-            Li = Ni * 4 * np.pi / 256
-            mem.append(dict(N=Ni, L=Li, eps=0.1, eta1=float(rng.uniform(1.2, 1.6)),
-                            eta2=float(rng.uniform(1.5, 2.5))))
+        mem = inputs.c4_members()
         ens_steps = 600
         ens = fch.Ensemble(mem, adapt=fch.AdaptOpts(sigma_tol=1e-5), t_end=1e9,
                            max_steps=ens_steps)
         for i, mi in enumerate(mem):
-            ens.load(i, torch.from_numpy(inputs.circle_bilayer(
-                mi["N"], mi["L"], 0.1, seed=100 + i)).to(dev))
+            ens.load(i, torch.from_numpy(inputs.c4_initial(mi, i)).to(dev))
         ens.autotune(reps=3)
         ens.run(max_attempts=20, sync_every=20, use_graph=True)     # warm-up attempts
         torch.cuda.synchronize()
@@ -358,6 +385,7 @@ def main():
         # launch per stage covers all of them, so the row and column passes
         # overlap across members instead of draining per field
         log("ensemble of 16 adaptive 1024^2 runs")
+        rng = np.random.default_rng(2025)
         mem = [dict(N=1024, L=1024 * 4 * np.pi / 256, eps=0.1,
                     eta1=float(rng.uniform(1.2, 1.6)), eta2=float(rng.uniform(1.5, 2.5)))
                for _ in range(16)]
@@ -447,6 +475,7 @@ def main():
                                              plan.get_config())),
                    "autotuned": not args.config, "graph_steps": args.graph},
         "roofline": roofline,
+        "roofline_streaming": roofline_streaming,
         "cpu_baseline": cpu,
         "extra": extra,
     }

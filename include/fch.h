@@ -126,14 +126,22 @@ typedef struct {
 fch_status fch_plan_stats(fch_plan_t plan, fch_stats* out);   /* host out */
 fch_status fch_plan_reset_stats(fch_plan_t plan);
 
-/* Kernel timing.  While enabled, every row-pass and column-pass launch is
- * bracketed by HIP events recorded on the plan's stream (up to 16384
- * launches; later launches are not timed); an interval includes the
- * dispatch of its kernel.  fch_plan_profile_read waits for the stream, sums
+/* Kernel timing.  While enabled, every row-pass and column-pass launch of the
+ * steppers is timed (up to 16384 launches; later launches are not timed).
+ * enable = 1: HIP events are recorded on the plan's stream before and after
+ * each launch, so an interval also holds the dispatch of its kernel.
+ * enable = 2: nothing enters the stream; each launch writes its start (the
+ * earliest of its first eight workgroups on the device's constant wall
+ * clock) to a device slot, and
+ * a launch's time is the interval to the next launch's start, counted only
+ * when that launch follows it directly on the stream (no other kernel, copy
+ * or host wait in between): the kernel's share of a back-to-back chain.
+ * Enabling mode 2 the first time allocates its slots (128 KiB of device
+ * memory).  fch_plan_profile_read waits for the stream, sums
  * the elapsed times per kernel class and clears the records.  Classes:
  * 0 row pass (pointwise chemical potential), 1 column pass (forward FFT +
  * epilogue + inverse FFT), 2 column pass (one direction only),
- * 3 single-field transforms (fch_forward / fch_inverse passes). */
+ * 3 single-field transforms (fch_forward / fch_inverse passes; mode 1 only). */
 typedef struct { int64_t count[4]; double ms[4]; } fch_profile;
 fch_status fch_plan_profile(fch_plan_t plan, int32_t enable);
 fch_status fch_plan_profile_read(fch_plan_t plan, fch_profile* out);

@@ -128,13 +128,18 @@ ColArgs col_args(fch_plan_s* p) {
 
 fch_status need_ws(fch_plan_s* p) { return p->ws ? FCH_OK : FCH_E_NOMEM; }
 
+// kernel timing (mode 2, below): the stream gets work that is not a timed launch
+void prof_break(fch_plan_s* p) { p->prof_last = -1; }
+
 fch_status ctl_set(fch_plan_s* p, const StepCtl& v) {
+  prof_break(p);
   HIPCHK(fch::launch_ctl_set(p->ctl, v, p->stream));
   p->stats.launches += 1;
   return FCH_OK;
 }
 
 fch_status readback(fch_plan_s* p) {
+  prof_break(p);
   HIPCHK(hipMemcpyAsync(p->hctl, p->ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return FCH_OK;
@@ -144,21 +149,36 @@ constexpr int kProfCap = 16384;
 
 // kernel timing: an event pair recorded on the plan's stream around the
 // next launch when timing is on
+// Kernel timing of the row and column passes.  prof_on = 1: event records
+// bracket each launch on the stream.  prof_on = 2: nothing enters the stream;
+// each launch folds its earliest workgroup start (device wall clock) into its
+// own slot of prof_ts, and its time is the interval to the next launch's
+// start, counted only when that next launch follows it directly on the stream
+// (prof_break marks any other work: small kernels, copies, host waits, a new
+// call).  In a back-to-back chain that interval is the kernel's share of the
+// chain, start to start.
 int prof_begin(fch_plan_s* p, int kind) {
   if (!p->prof_on || p->prof_n >= kProfCap) return -1;
   const int i = p->prof_n++;
   p->prof_kind[i] = kind;
-  (void)hipEventRecord(p->prof_ev[2 * i], p->stream);
+  p->prof_prev[i] = p->prof_last;
+  p->prof_last = i;
+  if (p->prof_on == 1) (void)hipEventRecord(p->prof_ev[2 * i], p->stream);
   return i;
 }
 void prof_end(fch_plan_s* p, int i) {
-  if (i >= 0) (void)hipEventRecord(p->prof_ev[2 * i + 1], p->stream);
+  if (i >= 0 && p->prof_on == 1) (void)hipEventRecord(p->prof_ev[2 * i + 1], p->stream);
+}
+unsigned long long* prof_slot(fch_plan_s* p, int i) {
+  return (i >= 0 && p->prof_on == 2) ? p->prof_ts + i : nullptr;
 }
 
 fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
   const int kind = (epi != fch::EPI_NONE && pro != fch::PRO_NONE) ? 1 : 2;
   const int r = prof_begin(p, kind);
-  HIPCHK(p->cv->col(epi, pro, a, p->stream, nullptr, nullptr));
+  ColArgs b = a;
+  b.tstart = prof_slot(p, r);
+  HIPCHK(p->cv->col(epi, pro, b, p->stream, nullptr, nullptr));
   prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
@@ -172,6 +192,7 @@ fch_status row_mu(fch_plan_s* p, double* partial, cd* pair0 = nullptr, cd* pair1
     a.P1 = pair1;
   }
   const int r = prof_begin(p, 0);
+  a.tstart = prof_slot(p, r);
   HIPCHK(p->rv->row(fch::ROW_MU, a, p->stream, nullptr, nullptr));
   prof_end(p, r);
   p->stats.launches += 1;
@@ -196,6 +217,7 @@ fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
   f.ncol = p->H;
   f.ctl = p->ctl;
   f.mode = mode;
+  prof_break(p);
   HIPCHK(fch::launch_finalize(f, p->stream));
   p->stats.launches += 1;
   return FCH_OK;
@@ -216,6 +238,7 @@ fch_status psd_iterations(fch_plan_s* p, const ColArgs& a, int done_before, int 
       r.psd_iter = done_before + i;
     }
     const int pr = prof_begin(p, 0);
+    r.tstart = prof_slot(p, pr);
     HIPCHK(p->rv->row(fch::ROW_MU, r, p->stream, nullptr, nullptr));
     prof_end(p, pr);
     p->stats.launches += 1;
@@ -423,10 +446,16 @@ fch_status fch_plan_profile(fch_plan_t p, int32_t enable) {
   if (enable && !p->prof_ev) {
     p->prof_ev = new (std::nothrow) hipEvent_t[2 * kProfCap];
     p->prof_kind = new (std::nothrow) int[kProfCap];
-    if (!p->prof_ev || !p->prof_kind) return FCH_E_NOMEM;
+    p->prof_prev = new (std::nothrow) int[kProfCap];
+    if (!p->prof_ev || !p->prof_kind || !p->prof_prev) return FCH_E_NOMEM;
     for (int i = 0; i < 2 * kProfCap; ++i) HIPCHK(hipEventCreate(&p->prof_ev[i]));
   }
-  p->prof_on = enable ? 1 : 0;
+  if (enable == 2 && !p->prof_ts) {
+    HIPCHK(hipMalloc((void**)&p->prof_ts, sizeof(unsigned long long) * kProfCap));
+    HIPCHK(hipMemsetAsync(p->prof_ts, 0xff, sizeof(unsigned long long) * kProfCap, p->stream));
+  }
+  p->prof_on = (enable == 2) ? 2 : (enable ? 1 : 0);
+  p->prof_last = -1;
   return FCH_OK;
 }
 
@@ -434,13 +463,35 @@ fch_status fch_plan_profile_read(fch_plan_t p, fch_profile* out) {
   if (!p || !out) return FCH_E_INVALID;
   std::memset(out, 0, sizeof(*out));
   HIPCHK(hipStreamSynchronize(p->stream));
-  for (int i = 0; i < p->prof_n; ++i) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]));
-    out->count[p->prof_kind[i]] += 1;
-    out->ms[p->prof_kind[i]] += ms;
+  if (p->prof_on == 2) {
+    const int n = p->prof_n;
+    unsigned long long* ts = new (std::nothrow) unsigned long long[n > 0 ? n : 1];
+    if (!ts) return FCH_E_NOMEM;
+    int khz = 0;
+    if (hipMemcpy(ts, p->prof_ts, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess ||
+        khz <= 0) {
+      delete[] ts;
+      return FCH_E_HIP;
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+      if (p->prof_prev[i + 1] != i || ts[i + 1] < ts[i] || ts[i + 1] == ~0ULL) continue;
+      out->count[p->prof_kind[i]] += 1;
+      out->ms[p->prof_kind[i]] += (double)(ts[i + 1] - ts[i]) / (double)khz;
+    }
+    delete[] ts;
+    HIPCHK(hipMemsetAsync(p->prof_ts, 0xff, sizeof(unsigned long long) * kProfCap, p->stream));
+  } else {
+    for (int i = 0; i < p->prof_n; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]));
+      out->count[p->prof_kind[i]] += 1;
+      out->ms[p->prof_kind[i]] += ms;
+    }
   }
   p->prof_n = 0;
+  p->prof_last = -1;
   return FCH_OK;
 }
 
@@ -481,6 +532,10 @@ fch_status fch_plan_destroy(fch_plan_t p) {
     for (int i = 0; i < 2 * kProfCap; ++i) (void)hipEventDestroy(p->prof_ev[i]);
     delete[] p->prof_ev;
     delete[] p->prof_kind;
+    delete[] p->prof_prev;
+  }
+  if (p->prof_ts) {
+    (void)hipFree(p->prof_ts);
   }
   if (p->tw) (void)hipFree(p->tw);
   if (p->ctl) (void)hipFree(p->ctl);
@@ -659,6 +714,7 @@ fch_status fch_plan_reset_stats(fch_plan_t p) {
 fch_status fch_forward(fch_plan_t p, const double* u, fch_c128* uh) {
   if (!p || !u || !uh) return FCH_E_INVALID;
   CHK(need_ws(p));
+  prof_break(p);
   RowArgs r = row_args(p);
   r.u_in = u;
   r.X_out = p->P0;
@@ -679,6 +735,7 @@ fch_status fch_forward(fch_plan_t p, const double* u, fch_c128* uh) {
 fch_status fch_inverse(fch_plan_t p, const fch_c128* uh, double* u) {
   if (!p || !u || !uh) return FCH_E_INVALID;
   CHK(need_ws(p));
+  prof_break(p);
   ColArgs a = col_args(p);
   a.X_in = (const cd*)uh;
   a.X_out = p->P0;
@@ -840,6 +897,7 @@ fch_status fch_step_sav(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   a.sav_rpart = p->rpart;
   a.sav_nrow = p->N / p->rv->R;
   CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, a));
+  prof_break(p);
   HIPCHK(fch::launch_sav_combine((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->cpart, p->H,
                                  p->c.pars, p->stream));
   p->stats.launches += 1;
@@ -1040,11 +1098,13 @@ fch_status fch_adapt_dt(fch_plan_t p, const fch_c128* uh_trial, const fch_c128* 
 namespace {
 fch_status ctl_dev(fch_plan_s* p, const StepCtl& v, const double* k_dev, const double* r_dev,
                    int flags) {
+  prof_break(p);
   HIPCHK(fch::launch_ctl_dev(p->ctl, v, k_dev, r_dev, p->prm.q, flags, p->stream));
   p->stats.launches += 1;
   return FCH_OK;
 }
 fch_status ctl_out(fch_plan_s* p, int what, double* d_out, int32_t* i_out, int32_t* status) {
+  prof_break(p);
   if (!d_out && !i_out && !status) return FCH_OK;
   HIPCHK(fch::launch_ctl_out(p->ctl, what, d_out, i_out, status, p->stream));
   p->stats.launches += 1;
@@ -1091,6 +1151,7 @@ fch_status fch_step_sav_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   a.sav_rpart = p->rpart;
   a.sav_nrow = p->N / p->rv->R;
   CHK(col(p, fch::EPI_SAV, fch::PRO_NONE, a));
+  prof_break(p);
   HIPCHK(fch::launch_sav_combine((cd*)uh_np1, p->aux, p->ctl, (size_t)p->H * p->N, p->cpart, p->H,
                                  p->c.pars, p->stream));
   p->stats.launches += 1;
@@ -1181,6 +1242,7 @@ fch_status fch_adapt_dt_dev(fch_plan_t p, const fch_c128* uh_trial, const fch_c1
 // ---- trajectories ---------------------------------------------------------
 static fch_status copy_spec(fch_plan_t p, cd* dst, const cd* src) {
   if (dst == src) return FCH_OK;
+  prof_break(p);
   HIPCHK(hipMemcpyAsync(dst, src, spec_bytes(p->N), hipMemcpyDeviceToDevice, p->stream));
   return FCH_OK;
 }

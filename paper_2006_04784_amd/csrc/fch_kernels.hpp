@@ -60,6 +60,9 @@ struct RowArgs {
   const double* psd_part;
   int psd_ncol;
   int psd_iter;
+  // kernel timing (nullable): the earliest workgroup start, in ticks of the
+  // device's constant wall clock, is folded in with an atomic minimum
+  unsigned long long* tstart;
 };
 
 struct ColArgs {
@@ -89,6 +92,7 @@ struct ColArgs {
   const double* sav_cpart;
   int sav_ncol;
   int rslot;
+  unsigned long long* tstart;  // kernel timing (nullable), as in RowArgs
 };
 
 struct FinArgs {

@@ -878,13 +878,24 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
   }
 }
 
+// kernel timing: the launch's start on the device's constant clock.  The
+// dispatcher hands out workgroups in index order, one per XCD in turn, so the
+// first eight hold the earliest start; only they fold theirs in (a minimum
+// over every workgroup would queue hundreds of atomics on one address).
+__device__ __forceinline__ void stamp_start(unsigned long long* t) {
+  if (t && threadIdx.x == 0 && blockIdx.x < 8 && blockIdx.y == 0)
+    atomicMin(t, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+}
+
 template <int N, int R, int E, int MODE, int TWL>
 __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
+  stamp_start(a.tstart);
   row_body<N, R, E, MODE, TWL>(a, done);
 }
 
 template <int N, int E, int EPI, int PRO, int TWL>
 __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
+  stamp_start(a.tstart);
   col_body<N, E, EPI, PRO, TWL>(a, done);
 }
 
@@ -910,6 +921,7 @@ __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
   a.sav_cpart = nullptr;
   a.sav_ncol = 0;
   a.rslot = 0;
+  a.tstart = nullptr;
 }
 
 template <int N, int R, int E, int TWL, bool UMAX>
@@ -929,6 +941,7 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
   a.psd_part = nullptr;
   a.psd_ncol = 0;
   a.psd_iter = 0;
+  a.tstart = nullptr;
   row_body<N, R, E, ROW_MU, TWL, UMAX>(a, &m->ctl.done, m->umaxpart);
 }
 

@@ -29,6 +29,9 @@ struct fch_plan_s {
   // kernel timing (fch_plan_profile)
   int prof_on;
   int prof_n;
+  int* prof_prev;   // index of the timed launch just before on the stream, or -1
+  int prof_last;    // last timed launch, -1 after any other stream work
+  unsigned long long* prof_ts;  // mode 2: earliest workgroup start per launch (device)
   hipEvent_t* prof_ev;    // 2 per record
   int* prof_kind;
   // HIP-graph replay of the fixed-step fused IMEX chain (fch_plan_set_graph)

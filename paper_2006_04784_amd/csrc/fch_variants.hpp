@@ -5,11 +5,11 @@
 
 #include "fch_kernels_impl.hpp"
 
-// launch, optionally with start/stop events attached to the dispatch itself
-// (kernel execution time, as a profiler's kernel trace reports it)
+// launch, optionally with start and/or stop events attached to the dispatch
+// itself (either may be null)
 #define FCH_LAUNCH(K, GRID, BLOCK, S, E0, E1, ...)                                   \
   do {                                                                                \
-    if (E0)                                                                           \
+    if ((E0) || (E1))                                                                 \
       hipExtLaunchKernelGGL(K, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__);            \
     else                                                                              \
       hipLaunchKernelGGL(K, GRID, BLOCK, 0, S, __VA_ARGS__);                          \

@@ -225,6 +225,37 @@ def paper_initial_data(name: str, N: int = None, eps: float = 0.1, physical_k: b
 
 
 # ---- named workloads -------------------------------------------------------
+def c4_members(count: int = 64, seed: int = 2024):
+    """Model keyword arguments of the mixed-size ensemble's members: N drawn
+    from {128, 256, 512, 1024}, L = N 4 pi / 256 (h/eps = 0.49), eps 0.1,
+    eta1 ~ U[1.2, 1.6], eta2 ~ U[1.5, 2.5] (times eps^p)."""
+    rng = np.random.default_rng(seed)
+    mem = []
+    for _ in range(count):
+        Ni = int(rng.choice([128, 256, 512, 1024]))
+        Li = Ni * 4 * np.pi / 256
+        mem.append(dict(N=Ni, L=Li, eps=0.1, eta1=float(rng.uniform(1.2, 1.6)),
+                        eta2=float(rng.uniform(1.5, 2.5))))
+    return mem
+
+
+def c4_initial(member: dict, index: int):
+    """Initial state of ensemble member `index`: one circle of radius 0.3 L,
+    noise seed 100 + index."""
+    return circle_bilayer(member["N"], member["L"], member["eps"], seed=100 + index)
+
+
+def psd_mix(N: int = 256, seed: int = 0):
+    """The 2048^2 PSD workload's kind of initial data at a smaller size: three
+    perturbed circles on a -0.99 background plus a Gaussian random field
+    (l = 4 eps, std 1e-3), eps 0.05 and the same h = 16 pi / 2048."""
+    eps = 0.05
+    L = N * 16 * np.pi / 2048
+    kw = dict(N=N, L=L, eps=eps, eta1=1.45, eta2=2.0)
+    u = perturbed_circles(N, L, eps, 3, seed=seed, u_bg=-0.99, noise=0.0, r_range=(0.3, 0.6))
+    return kw, u + gaussian_random_field(N, L, 4 * eps, 1e-3, seed=seed + 1)
+
+
 def workload(name: str, seed: int = 0):
     """(model keyword arguments, physical initial state) of a named workload.
 

@@ -486,10 +486,15 @@ def test_adaptive_512_step_sequence_matches_oracle_controller(F, orc, scheme):
     assert mi["accepted"] == len(ks) and len(klog) == len(ks)
     # k_next ~ e^(-1/3), and the estimate e (about sigma_tol) is a difference
     # of nearby states: a state difference of 1e-12 relative moves k by about
-    # 1e-12 / (3 sigma_tol) ~ 3e-8
-    assert np.allclose(klog, ks, rtol=1e-6, atol=0), np.max(np.abs(klog / ks - 1))
+    # 1e-12 / (3 sigma_tol) ~ 3e-8.  Measured over the 181 steps: 3.0e-10
+    # (IMEX) and 1.2e-8 (SAV).
+    dk = float(np.max(np.abs(np.asarray(klog) / np.asarray(ks) - 1)))
+    e_state = rel(uh.cpu().numpy().T, cur)
+    log("  %d accepted steps; max |k_gpu/k_oracle - 1| = %.3e, state rel %.3e"
+        % (len(ks), dk, e_state))
+    assert dk < 1e-7, dk
     assert abs(mi["t"] - t) < 1e-12
-    assert rel(uh.cpu().numpy().T, cur) < 1e-8
+    assert e_state < 1e-8
     if scheme == "sav":
         assert abs(mi["r_n"] - r_cur) < 1e-9 * abs(r_cur)
         assert abs(mi["r_nm1"] - r_prev) < 1e-9 * abs(r_prev)

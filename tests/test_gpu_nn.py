@@ -62,10 +62,14 @@ def test_conv_forward_both_launch_shapes(F, orc, B, H, W):
     assert rel(o.cpu().numpy(), orc.nn_conv_fwd(x, w16, bias[:16], True)) < 1e-5
 
 
-def test_conv_kernels(F, orc):
+# (2, 16, 32): one column chunk in k_conv_bwd_w, 4 weight-gradient partials.
+# (4, 64, 256): 8 chunks (interior chunk boundaries and their halos), 32
+# partials, so every group of the two-stage reduction sums two.
+@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (4, 64, 256)])
+def test_conv_kernels(F, orc, B, H, W):
     L = F.lib()
     rng = np.random.default_rng(3)
-    B, H, W = 2, 16, 32
+    errs = {}
     x = orc.bf16(rng.normal(size=(B, H, W, 32)))
     w = orc.bf16(rng.normal(0, 0.1, size=(9, 32, 32)))
     bias = rng.normal(0, 0.1, size=32).astype(np.float32).astype(np.float64)
@@ -74,8 +78,11 @@ def test_conv_kernels(F, orc):
     assert L.fch_nn_conv_fwd(B, H, W, 32, P(tb(x)), P(tb(w)), P(tf(bias)), P(z), P(y), None,
                              None) == 0
     zr, yr = orc.nn_conv_fwd(x, w, bias, True)
-    assert rel(z.float().cpu().numpy(), zr) < 2e-3
-    assert rel(y.float().cpu().numpy(), yr) < 2e-3
+    errs["z"] = rel(z.float().cpu().numpy(), zr)
+    errs["y"] = rel(y.float().cpu().numpy(), yr)
+    # measured (2,16,32) / (4,64,256): z 1.0e-7 / 2.3e-5, y 7.8e-8 / 2.5e-5 (single
+    # bf16 rounding flips where FP32 and FP64 sums straddle a rounding boundary)
+    assert errs["z"] < 1e-4 and errs["y"] < 1e-4
     # inference form: no z, the same y bit for bit
     y2 = torch.zeros_like(y)
     assert L.fch_nn_conv_fwd(B, H, W, 32, P(tb(x)), P(tb(w)), P(tf(bias)), None, P(y2), None,
@@ -86,7 +93,8 @@ def test_conv_kernels(F, orc):
     o = torch.zeros((B, H, W), dtype=torch.float32, device="cuda")
     assert L.fch_nn_conv_fwd(B, H, W, 16, P(tb(x)), P(tb(w16)), P(tf(bias[:16])), None, None,
                              P(o), None) == 0
-    assert rel(o.cpu().numpy(), orc.nn_conv_fwd(x, w16, bias[:16], True)) < 1e-5
+    errs["o"] = rel(o.cpu().numpy(), orc.nn_conv_fwd(x, w16, bias[:16], True))
+    assert errs["o"] < 1e-6   # measured 9.5e-8 (FP32 output, no bf16 rounding)
     # backward data, both weight shapes
     dz = orc.bf16(rng.normal(size=(B, H, W, 32)))
     zp = orc.bf16(rng.normal(size=(B, H, W, 32)))
@@ -98,7 +106,9 @@ def test_conv_kernels(F, orc):
         out = torch.zeros((B, H, W, 32), dtype=torch.bfloat16, device="cuda")
         assert L.fch_nn_conv_bwd_data(B, H, W, ww.shape[1], P(tb(dzz)), P(tb(ww)), P(tb(zp)),
                                       P(out), P(wt), None) == 0
-        assert rel(out.float().cpu().numpy(), orc.nn_conv_bwd_data(dzz, ww, zp, True)) < 2e-3
+        errs["dz_prev/%d" % ww.shape[1]] = rel(out.float().cpu().numpy(),
+                                               orc.nn_conv_bwd_data(dzz, ww, zp, True))
+        assert errs["dz_prev/%d" % ww.shape[1]] < 1e-4   # measured <= 2.1e-5
     # backward weights
     for cout in (32, 16):
         dzz = dz.copy()
@@ -109,14 +119,20 @@ def test_conv_kernels(F, orc):
         assert L.fch_nn_conv_bwd_w(B, H, W, cout, P(tb(dzz)), P(tb(x)), P(g), P(scr), None) == 0
         dw, db = orc.nn_conv_bwd_w(dzz, x, cout)
         gg = g.cpu().numpy()
-        assert rel(gg[:9 * cout * 32], dw.ravel()) < 1e-5
-        assert rel(gg[9 * cout * 32:], db) < 1e-5
+        errs["dw/%d" % cout] = rel(gg[:9 * cout * 32], dw.ravel())
+        errs["db/%d" % cout] = rel(gg[9 * cout * 32:], db)
+        # measured <= 2.9e-7 (FP32 accumulation of exact bf16 products)
+        assert errs["dw/%d" % cout] < 2e-6 and errs["db/%d" % cout] < 2e-6
+    print("conv kernels B=%d H=%d W=%d rel L2: %s" % (B, H, W, {k: "%.2e" % v for k, v in
+                                                               errs.items()}), flush=True)
 
 
-def test_training_step_matches_oracle(F, orc):
+# (8, 64, 256): the 4-wave forward path (512 tiles), 8 column chunks and 64
+# weight-gradient partials (four per reduction group), as in training.
+@pytest.mark.parametrize("B,H,W", [(2, 16, 32), (8, 64, 256)])
+def test_training_step_matches_oracle(F, orc, B, H, W):
     from paper_2006_04784_amd import nn
     rng = np.random.default_rng(4)
-    B, H, W = 2, 16, 32
     net = nn.WarmStartNet(H, W, B, seed=5)
     params = net.init_params(5)
     params[-1] = (rng.normal(0, 0.05, size=(9, 16, 32)), rng.normal(0, 0.05, size=16))
@@ -126,7 +142,7 @@ def test_training_step_matches_oracle(F, orc):
     un = torch.from_numpy(rng.normal(size=(B, H, W))).cuda()
     um = un + 0.01 * torch.from_numpy(rng.normal(size=(B, H, W))).cuda()
     up = un + 0.012 * torch.from_numpy(rng.normal(size=(B, H, W))).cuda()
-    k = torch.tensor([[2e-3, 1e-3], [1e-3, 1e-3]], dtype=torch.float64).cuda()
+    k = torch.tensor([[2e-3, 1e-3], [1e-3, 1e-3]] * (B // 2), dtype=torch.float64).cuda()
     net.features(un, um, k, up)
     x = net.x.float().cpu().numpy().astype(np.float64)
     t = net.target.cpu().numpy().astype(np.float64)
@@ -140,11 +156,20 @@ def test_training_step_matches_oracle(F, orc):
     loss = float(net.backward(B).cpu()[0])
     q = [(orc.bf16(w), b.astype(np.float32).astype(np.float64)) for w, b in params]
     lref, gref, oref = orc.nn_loss_and_grads(x, q, t, True)
-    assert rel(net.o.cpu().numpy(), oref) < 1e-3
-    assert abs(loss - lref) < 1e-3 * lref
-    for (gw, gb), (rw, rb) in zip(net.get_grads(), gref):
-        assert rel(gw, rw) < 1e-2
-        assert rel(gb, rb) < 1e-2
+    e_o = rel(net.o.cpu().numpy(), oref)
+    e_loss = abs(loss - lref) / lref
+    e_g = [(rel(gw, rw), rel(gb, rb)) for (gw, gb), (rw, rb) in zip(net.get_grads(), gref)]
+    print("training step B=%d H=%d W=%d: output %.2e, loss %.2e, (dw, db) per layer %s"
+          % (B, H, W, e_o, e_loss, ["(%.2e, %.2e)" % g for g in e_g]), flush=True)
+    # measured at (2,16,32) / (8,64,256): output 2.8e-5 / 3.7e-4, loss 3.8e-7 /
+    # 2.3e-7, gradients per tensor at most 4.1e-4 / 9.2e-5 (the first layer's
+    # weights, whose gradient collects the bf16 rounding flips of all later
+    # layers); the bound is the per-tensor 1e-3 of the learned net's pin
+    assert e_o < 1e-3
+    assert e_loss < 1e-5
+    for ew, eb in e_g:
+        assert ew < 1e-3
+        assert eb < 1e-3
     # Adam: the first bias-corrected step from zero moments is
     # lr * g / (|g| + eps) against the gradient
     before = net.P.clone()
