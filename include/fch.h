@@ -106,14 +106,18 @@ fch_status fch_plan_get_config(fch_plan_t plan, fch_launch_cfg* cfg);
 int32_t    fch_row_config_count(int32_t N);
 int32_t    fch_col_config_count(int32_t N);
 fch_status fch_config_get(int32_t N, int32_t row_i, int32_t col_i, fch_launch_cfg* cfg);
-/* Autotuner: times every compiled row-pass and column-pass variant on the
- * fused BDF2-IMEX step (row pass, then column pass with the next step's
- * prologue) of the given state, reps launches each with HIP events, and
- * makes the fastest of each family the plan's configuration.  uh_n, uh_nm1
- * are read only (copied into the workspace); k is the step used.  best (host
- * out, nullable) receives the choice; us (host out, nullable, 2 doubles) the
- * average microseconds per launch of the chosen row and column variants.
- * Synchronizes the plan's stream. */
+/* Autotuner: runs the fused BDF2-IMEX chain (row pass, then column pass with
+ * the next step's prologue, back to back) for every pair of compiled row-pass
+ * and column-pass variants on scratch copies of the given state, reps steps
+ * per chain (at least 2, at most N-1), in three timed sweeps after a warm-up
+ * sweep, and keeps the pair with the shortest chain time per step (HIP events
+ * around the chain; best of the sweeps).  Pairs within 1% of the fastest are
+ * ties, resolved by list order, so the choice does not follow timing noise.
+ * uh_n, uh_nm1 are read only (copied into the workspace); k is the step used.
+ * best (host out, nullable) receives the choice; us (host out, nullable, 2
+ * doubles) the chosen row and column passes' average shares of the chain in
+ * microseconds (device clock, launch start to launch start).  Synchronizes
+ * the plan's stream. */
 fch_status fch_autotune(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1, double k,
                         int32_t reps, fch_launch_cfg* best, double* us);
 
@@ -405,8 +409,10 @@ fch_status fch_ensemble_set_workspace(fch_ensemble_t ens, void* dptr, size_t byt
 fch_status fch_ensemble_load(fch_ensemble_t ens, int32_t member, const double* u0);
 /* Autotunes each size class's launch variants on the batched work itself:
  * every compiled (row, column) variant pair runs 1 + reps whole attempts of
- * all the class's members, each pair from the same member memory, and the
- * fastest pair is kept.  Member states, times and counters are restored
+ * all the class's members, each pair from the same member memory, in three
+ * sweeps (best time of the three).  Pairs within 3% of the fastest are ties;
+ * among them the first in list order whose row variant takes at most 4 rows
+ * per workgroup is kept.  Member states, times and counters are restored
  * afterwards, so tuning changes no result beyond rounding.  Needs every
  * member loaded (FCH_E_INVALID) and the workspace (FCH_E_NOMEM); holds a
  * temporary device copy of one class's member memory (hipMalloc) while it

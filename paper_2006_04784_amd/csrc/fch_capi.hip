@@ -620,81 +620,123 @@ fch_status fch_autotune(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   if (!p || !uh_n || !uh_nm1 || !finite_pos(k) || reps < 1) return FCH_E_INVALID;
   CHK(need_ws(p));
   const int nr = fch::row_variant_count(p->N), nc = fch::col_variant_count(p->N);
-  const int rounds = (nr > nc ? nr : nc) * reps;
-  double* rsum = new (std::nothrow) double[nr + nc];
-  if (!rsum) return FCH_E_NOMEM;
-  double* csum = rsum + nr;
-  for (int i = 0; i < nr + nc; ++i) rsum[i] = 0.0;
-  hipEvent_t ev[4];
-  for (int i = 0; i < 4; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) { delete[] rsum; return FCH_E_HIP; }
+  const int npair = nr * nc;
+  // per pair: the best chain time per step over the sweeps, and the row and
+  // column shares of that chain (device clock, launch start to launch start)
+  double* tbest = new (std::nothrow) double[3 * npair];
+  if (!tbest) return FCH_E_NOMEM;
+  double* rbest = tbest + npair;
+  double* cbest = rbest + npair;
+  for (int i = 0; i < npair; ++i) tbest[i] = rbest[i] = cbest[i] = 1e30;
+  // steps per timed chain; the launch starts land in the row partial-sum
+  // area of the workspace (2N doubles: one slot per launch)
+  const int K = std::max(2, std::min(reps, p->N - 1));
+  const int nslot = 2 * K + 1;
+  unsigned long long* slots = (unsigned long long*)p->rpart;
+  unsigned long long* hs = new (std::nothrow) unsigned long long[nslot];
+  if (!hs) { delete[] tbest; return FCH_E_NOMEM; }
+  int khz = 0;
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) { delete[] tbest; delete[] hs; return FCH_E_HIP; }
   const fch::RowVT* keep_r = p->rv;
   const fch::ColVT* keep_c = p->cv;
+  const int keep_prof = p->prof_on;
+  p->prof_on = 0;
   fch_status st = FCH_OK;
-  // scratch copies of the state: the fused chain runs on Fc[0..2]
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess ||
+      khz <= 0)
+    st = FCH_E_HIP;
+  // scratch copies of the state: the fused chain runs on Fc[0..1]
   cd *cur = p->Fc[0], *prev = p->Fc[1];
-  if (copy_spec(p, cur, (const cd*)uh_n) != FCH_OK || copy_spec(p, prev, (const cd*)uh_nm1) != FCH_OK)
+  if (st == FCH_OK && (copy_spec(p, cur, (const cd*)uh_n) != FCH_OK ||
+                       copy_spec(p, prev, (const cd*)uh_nm1) != FCH_OK))
     st = FCH_E_HIP;
   StepCtl v = ctl_zero();
   set_bdf2(v, k, k);
   if (st == FCH_OK) st = ctl_set(p, v);
-  ColArgs a = col_args(p);
-  a.s0 = cur;
-  a.s1 = prev;
-  if (st == FCH_OK) st = col(p, fch::EPI_NONE, fch::PRO_EXTRAP, a);
-  for (int it = 0; it < rounds + 2 && st == FCH_OK; ++it) {
-    const int ri = it % nr, ci = it % nc;
-    p->rv = fch::row_variant(p->N, ri);
-    p->cv = fch::col_variant(p->N, ci);
-    RowArgs r = row_args(p);
-    a.s0 = cur;
-    a.s1 = prev;
-    a.out = prev;
-    if (hipEventRecord(ev[0], p->stream) != hipSuccess ||
-        p->rv->row(fch::ROW_MU, r, p->stream, nullptr, nullptr) != hipSuccess ||
-        hipEventRecord(ev[1], p->stream) != hipSuccess ||
-        p->cv->col(fch::EPI_IMEX, fch::PRO_NEXT_EXTRAP, a, p->stream, nullptr, nullptr) !=
-            hipSuccess ||
-        hipEventRecord(ev[2], p->stream) != hipSuccess ||
-        hipEventSynchronize(ev[2]) != hipSuccess) {
-      st = FCH_E_HIP;
-      break;
-    }
-    std::swap(cur, prev);
-    float t_row = 0.f, t_col = 0.f;
-    (void)hipEventElapsedTime(&t_row, ev[0], ev[1]);
-    (void)hipEventElapsedTime(&t_col, ev[1], ev[2]);
-    if (it >= 2) {  // the first rounds warm caches and code objects
-      rsum[ri] += t_row;
-      csum[ci] += t_col;
+  // sweep 0 warms code objects and caches; sweeps 1..3 are timed
+  for (int sweep = 0; sweep < 4 && st == FCH_OK; ++sweep) {
+    for (int pi = 0; pi < npair && st == FCH_OK; ++pi) {
+      p->rv = fch::row_variant(p->N, pi / nc);
+      p->cv = fch::col_variant(p->N, pi % nc);
+      if (hipMemsetAsync(slots, 0xff, sizeof(unsigned long long) * nslot, p->stream) !=
+          hipSuccess) {
+        st = FCH_E_HIP;
+        break;
+      }
+      ColArgs a = col_args(p);
+      a.s0 = cur;
+      a.s1 = prev;
+      a.tstart = slots;
+      if (p->cv->col(fch::EPI_NONE, fch::PRO_EXTRAP, a, p->stream, nullptr, nullptr) !=
+              hipSuccess ||
+          hipEventRecord(ev[0], p->stream) != hipSuccess) {
+        st = FCH_E_HIP;
+        break;
+      }
+      for (int s = 0; s < K && st == FCH_OK; ++s) {
+        RowArgs r = row_args(p);
+        r.tstart = slots + 1 + 2 * s;
+        a.s0 = cur;
+        a.s1 = prev;
+        a.out = prev;
+        a.tstart = slots + 2 + 2 * s;
+        if (p->rv->row(fch::ROW_MU, r, p->stream, nullptr, nullptr) != hipSuccess ||
+            p->cv->col(fch::EPI_IMEX, s + 1 < K ? fch::PRO_NEXT_EXTRAP : fch::PRO_NONE, a,
+                       p->stream, nullptr, nullptr) != hipSuccess)
+          st = FCH_E_HIP;
+        std::swap(cur, prev);
+      }
+      if (st != FCH_OK || hipEventRecord(ev[1], p->stream) != hipSuccess ||
+          hipMemcpyAsync(hs, slots, sizeof(unsigned long long) * nslot, hipMemcpyDeviceToHost,
+                         p->stream) != hipSuccess ||
+          hipStreamSynchronize(p->stream) != hipSuccess) {
+        st = FCH_E_HIP;
+        break;
+      }
+      if (sweep == 0) continue;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+      const double per_step = 1e3 * ms / K;  // microseconds
+      if (per_step < tbest[pi]) {
+        // row s spans slots 1+2s -> 2+2s, its column pass 2+2s -> 3+2s (the
+        // last column pass has no successor and is left out)
+        double rs = 0.0, cs = 0.0;
+        for (int s = 0; s < K; ++s) rs += (double)(hs[2 + 2 * s] - hs[1 + 2 * s]);
+        for (int s = 0; s + 1 < K; ++s) cs += (double)(hs[3 + 2 * s] - hs[2 + 2 * s]);
+        tbest[pi] = per_step;
+        rbest[pi] = 1e3 * rs / K / khz;
+        cbest[pi] = 1e3 * cs / (K - 1) / khz;
+      }
     }
   }
-  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
+  delete[] hs;
+  p->prof_on = keep_prof;
   if (st != FCH_OK) {
     p->rv = keep_r;
     p->cv = keep_c;
-    delete[] rsum;
+    delete[] tbest;
     return st;
   }
-  int br = 0, bc = 0;
-  for (int i = 1; i < nr; ++i)
-    if (rsum[i] < rsum[br]) br = i;
-  for (int i = 1; i < nc; ++i)
-    if (csum[i] < csum[bc]) bc = i;
-  // every variant ran rounds/n times; average per launch in microseconds
-  auto count = [&](int i, int n) {
-    int c = 0;
-    for (int it = 2; it < rounds + 2; ++it) c += (it % n == i);
-    return c > 0 ? c : 1;
-  };
-  p->rv = fch::row_variant(p->N, br);
-  p->cv = fch::col_variant(p->N, bc);
+  // the fastest pair; pairs within 1% of it count as ties, resolved by list
+  // order (the first listed variants are the defaults), so that timing noise
+  // does not change the choice between near-equal variants from run to run
+  int bp = 0;
+  for (int i = 1; i < npair; ++i)
+    if (tbest[i] < tbest[bp]) bp = i;
+  const double tmin = tbest[bp];
+  for (int i = 0; i < npair; ++i)
+    if (tbest[i] <= 1.01 * tmin) { bp = i; break; }
+  p->rv = fch::row_variant(p->N, bp / nc);
+  p->cv = fch::col_variant(p->N, bp % nc);
   if (best) fill_cfg(p->rv, p->cv, best);
   if (us) {
-    us[0] = 1e3 * rsum[br] / count(br, nr);
-    us[1] = 1e3 * csum[bc] / count(bc, nc);
+    us[0] = rbest[bp];
+    us[1] = cbest[bp];
   }
-  delete[] rsum;
+  delete[] tbest;
   return FCH_OK;
 }
 
