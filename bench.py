@@ -66,7 +66,7 @@ def read_traffic(kernel_class):
     return float(kv[key]) if key in kv else None
 
 
-def hbm_roofline(kernels, label, extra=None):
+def hbm_roofline(kernels, label, extra=None, where="the timed region"):
     """Roofline object of the dominant kernel (largest total time) among
     kernels = {name: (algorithmic bytes per launch, avg seconds, launches)}."""
     dom = max(kernels, key=lambda kk: kernels[kk][1] * kernels[kk][2])
@@ -76,8 +76,8 @@ def hbm_roofline(kernels, label, extra=None):
            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
            "kernel": dom, "workload": label, "bytes_per_launch": nbytes,
            "avg_us": round(avg * 1e6, 3),
-           "timing": "device clock in the timed region: start of each launch to the next "
-                     "launch's start in the back-to-back chain, %d launches" % count,
+           "timing": "device clock in %s: start of each launch to the next launch's start "
+                     "in the back-to-back chain, %d launches" % (where, count),
            "other_kernels": {kk: {"avg_us": round(v[1] * 1e6, 3), "bytes_per_launch": v[0],
                                   "GBps": round(v[0] / v[1] / 1e9, 1), "launches": v[2]}
                              for kk, v in kernels.items()}}
@@ -279,8 +279,8 @@ def main():
         plan3 = fch.Plan(**kw3, device=dev)
         a3 = plan3.forward(torch.from_numpy(u3).to(dev))
         b3 = torch.empty_like(a3)
+        u3d = a3.clone()
         plan3.reset_stats()
-        plan3.profile(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info3 = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
@@ -288,19 +288,35 @@ def main():
                           adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
         torch.cuda.synchronize()
         el3 = time.perf_counter() - t0
-        prof3 = plan3.profile_read()
-        plan3.profile(False)
         S3 = spec_bytes(kw3["N"])
         acc3 = info3["accepted"]
+        launches3 = plan3.stats()["launches"]
+        # the same run with kernel timing on (each row and column pass records
+        # its start on the device clock; attempts then run from the host loop,
+        # one host wait per chunk of PSD iterations and per error estimate)
+        a3.copy_(u3d)
+        plan3.profile(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info3h = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
+                           nsteps=101, k_first=1e-6,
+                           adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
+        torch.cuda.synchronize()
+        el3h = time.perf_counter() - t0
+        prof3 = plan3.profile_read()
+        plan3.profile(False)
         extra["c3_psd_adaptive_2048"] = {
             "accepted_steps": acc3, "rejected": info3["rejected"], "t": round(info3["t"], 6),
             "psd_iters_per_step": round(info3["psd_iters"] / acc3, 2),
             "psd_fft_calls_per_step": round(4.0 * info3["psd_iters"] / acc3, 2),
             "total_fft_calls_per_step": round(info3["fft_calls"] / acc3, 2),
             "ms_per_step": round(1e3 * el3 / acc3, 3),
+            "launches_per_step": round(launches3 / acc3, 2),
+            "control": "device (queued rounds, one host wait per 8 rounds)",
+            "ms_per_step_host_loop_timed": round(1e3 * el3h / info3h["accepted"], 3),
             "psd_iteration_GBps": round(11 * S3 * info3["psd_iters"] / el3 / 1e9, 1),
             "bytes_per_psd_iteration": 11 * S3}
-        # streaming roofline: the same run's kernels (working set: u^n, u^{n-1},
+        # streaming roofline: the kernels of the timed rerun (working set: u^n, u^{n-1},
         # the iterate, b u^n + c u^{n-1}, the pair buffer and three F caches,
         # 9S = 302 MB, beyond the 256 MB Infinity Cache); row passes of the PSD
         # iterations and of the error estimate, PSD column passes
@@ -310,7 +326,8 @@ def main():
                    "field, working set 9S = %.0f MB)" % (9 * S3 / 1e6),
             {"iteration_bytes": 11 * S3,
              "iteration_frac": round(11 * S3 / (kern3["row_mu"][1] + kern3["col_psd_fused"][1])
-                                     / 1e9 / PEAK_HBM_GBS, 4)})
+                                     / 1e9 / PEAK_HBM_GBS, 4)},
+            where="the run's rerun with kernel timing on")
         del plan3, a3, b3
         # 2D FFT bandwidth, streaming regime: R2C then C2R over a 32-field batch
         # (269 MB physical + 269 MB spectral + 269 MB staging, beyond the 256 MB

@@ -302,8 +302,11 @@ fch_status fch_rhs(fch_plan_t plan, const fch_c128* uh, fch_c128* Fh);
  *                   FCH_E_NONFINITE.
  * All pointers are device pointers.  The host return value covers only the
  * host-side checks (null pointers, aliasing, options).  fch_step_psd_dev
- * launches opts->max_iter (or fixed_iters) iterations; once converged the
- * remaining launches return at once. */
+ * launches opts->max_iter (or fixed_iters) iterations, a number fixed when
+ * the calls are captured (the graph API of this HIP has no conditional
+ * nodes); once converged the remaining launches return at once, so a caller
+ * capturing it sets max_iter near the expected count.  fch_run's adaptive
+ * PSD needs no such bound: it queues rounds sized from the latest attempt. */
 fch_status fch_step_imex_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
                              const double* k_dev, fch_c128* uh_np1, int32_t* status_dev);
 fch_status fch_step_sav_dev(fch_plan_t plan, const fch_c128* uh_n, const fch_c128* uh_nm1,
@@ -338,7 +341,20 @@ fch_status fch_adapt_dt_dev(fch_plan_t plan, const fch_c128* uh_trial, const fch
  * ETD runs take the startup step as one ETDRK2 step of k_first without error
  * control (the estimate needs F^{n-1}), then follow Sec. 3.2 with the ETDRK2
  * result as the primary approximation of Step 1; each attempt starts from
- * the cached F(u^n) (8 FFT calls, as for IMEX). */
+ * the cached F(u^n) (8 FFT calls, as for IMEX).
+ * Adaptive attempts run under device control: a controller kernel accepts or
+ * rejects, rotates the buffers and sets the next trial step, and the host
+ * waits only between chunks of queued attempts.  Adaptive PSD attempts are
+ * queued as rounds (the initial iterate; a number of iterations, each row pass
+ * first evaluating the previous iteration's stopping test; the F(u~)
+ * evaluation with the error estimate, starting from the final iterate's
+ * column transform that the last iteration left; the controller), each stage running
+ * only in its phase of the attempt, so an attempt that outruns its round
+ * continues in the next; the iterations per round follow the latest
+ * attempt's count.  A solve that reaches max_iter stops the run with
+ * FCH_E_NOCONV, the last accepted state in uh_n.  With kernel timing on
+ * (fch_plan_profile) the attempts run from a host loop instead, with the same
+ * results. */
 typedef enum { FCH_IMEX = 0, FCH_SAV = 1, FCH_PSD = 2, FCH_ETD = 3 } fch_scheme;
 typedef struct {
     int32_t scheme, adaptive, startup;

@@ -1556,6 +1556,9 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   CHK(check_adapt(&o->adapt));
   const fch_adapt_opts* ad = &o->adapt;
   if (!(o->t_end > 0.0)) return FCH_E_INVALID;
+  if (o->scheme == FCH_PSD &&
+      (o->psd.max_iter < 1 || !(o->psd.tol > 0.0 || o->psd.fixed_iters > 0)))
+    return FCH_E_INVALID;
   cd* Fn = p->Fc[0];
   cd* Fm = p->Fc[1];
   cd* Ft = p->Fc[2];
@@ -1591,7 +1594,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   }
   const double t_end = o->t_end;
   const int64_t max_acc = o->nsteps > 0 ? o->nsteps : INT64_MAX;
-  if ((o->scheme == FCH_IMEX || o->scheme == FCH_ETD || o->scheme == FCH_SAV) && !p->prof_on) {
+  if (!p->prof_on) {
     // Attempts under device control: the run is described as one ensemble
     // member (state and F slots, time, step scalars) and each attempt is the
     // batched kernels' sequence with the per-member controller, which accepts
@@ -1618,6 +1621,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     m.rpart = p->rpart;
     m.umaxpart = p->rpart;
     m.sav = (o->scheme == FCH_SAV) ? 1 : 0;
+    m.psd = (o->scheme == FCH_PSD) ? 1 : 0;
     m.rslot = 0;
     m.nrow = p->N / p->rv->R;
     m.umax = -INFINITY;
@@ -1650,21 +1654,65 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     }
     v.done = (t >= t_end * (1.0 - 1e-14) || inf.accepted >= max_acc) ? 1 : 0;
     const bool etd = (o->scheme == FCH_ETD);
+    if (m.psd) {
+      // the solve's options; the first attempt's control block and stages
+      m.sctl = ctl_zero();
+      m.sctl.tol = o->psd.tol;
+      m.sctl.max_iter = o->psd.max_iter;
+      m.sctl.fixed_iters = o->psd.fixed_iters;
+      m.psd_lambda = o->psd.lambda;
+      if (!fch::psd_arm(&m)) return FCH_E_INVALID;
+      if (v.done) {
+        m.psd_init_skip = 1;
+        m.psd_eval_skip = 1;
+        m.sctl.done = 4;
+      }
+    }
     HIPCHK(hipMemcpyAsync(p->dmem, &m, sizeof(m), hipMemcpyHostToDevice, p->stream));
     int64_t before = m.accepted + m.rejected;
+    // PSD: iterations queued per round, from the iterations per attempt so far
+    int psd_c = std::max(2, std::min(64, p->psd_hint + 1));
     while (!m.ctl.done) {
       const int64_t left = max_acc - m.accepted;
+      if (m.psd) {
+        // rounds of PSD_INIT, psd_c iterations, the F(u~) evaluation (row pass
+        // and AM3 column pass) and the controller; each stage runs only in its
+        // phase of the attempt
+        const int rounds = (int)std::max<int64_t>(1, std::min<int64_t>(8, left));
+        for (int i = 0; i < rounds; ++i) {
+          HIPCHK(p->cv->col_ens(fch::ENS_PSD_INIT, p->dmem, 0, 1, p->stream));
+          for (int j = 0; j < psd_c; ++j) {
+            HIPCHK(p->rv->row_ens(p->dmem, 0, 1, fch::ENS_ROW_PSD, p->stream));
+            HIPCHK(p->cv->col_ens(fch::ENS_PSD, p->dmem, 0, 1, p->stream));
+          }
+          // the row pass that stopped the solve left the column-inverted
+          // (u, Lap u) of the final iterate in the pair buffer: F(u~) starts there
+          HIPCHK(p->rv->row_ens(p->dmem, 0, 1, fch::ENS_ROW_TRACK, p->stream));
+          HIPCHK(p->cv->col_ens(fch::ENS_AM3, p->dmem, 0, 1, p->stream));
+          HIPCHK(fch::launch_ens_control(p->dmem, 0, 1, p->stream));
+        }
+        p->stats.launches += (4LL + 2LL * psd_c) * rounds;
+        HIPCHK(hipMemcpyAsync(&m, p->dmem, sizeof(m), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        if (m.ctl.nonfinite) return FCH_E_NONFINITE;
+        if (m.ctl.invalid) return FCH_E_INVALID;
+        // the next rounds queue as many iterations as the latest attempt took,
+        // plus one: counts change slowly from attempt to attempt, and an
+        // attempt that needs more continues in the next round
+        if (m.psd_last_iters > 0) psd_c = std::max(2, std::min(64, m.psd_last_iters + 1));
+        continue;
+      }
       const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(32, left));
       for (int i = 0; i < chunk; ++i) {
         HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD_PRO : fch::ENS_PRO, p->dmem, 0, 1, p->stream));
-        HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 0, p->stream));
+        HIPCHK(p->rv->row_ens(p->dmem, 0, 1, fch::ENS_ROW, p->stream));
         if (m.sav) {
           HIPCHK(p->cv->col_ens(fch::ENS_SAV, p->dmem, 0, 1, p->stream));
           HIPCHK(p->cv->col_ens(fch::ENS_SAV_FIELD, p->dmem, 0, 1, p->stream));
         } else {
           HIPCHK(p->cv->col_ens(etd ? fch::ENS_ETD2 : fch::ENS_IMEX, p->dmem, 0, 1, p->stream));
         }
-        HIPCHK(p->rv->row_ens(p->dmem, 0, 1, 1, p->stream));
+        HIPCHK(p->rv->row_ens(p->dmem, 0, 1, fch::ENS_ROW_TRACK, p->stream));
         HIPCHK(p->cv->col_ens(fch::ENS_AM3, p->dmem, 0, 1, p->stream));
         HIPCHK(fch::launch_ens_control(p->dmem, 0, 1, p->stream));
       }
@@ -1679,7 +1727,15 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
       rs[1] = m.ctl.rring[(m.rslot + 2) % 3];
     }
     const int64_t attempts = m.accepted + m.rejected - before;
-    p->stats.fft_calls += 8 * attempts;
+    if (m.psd) {
+      // 4 FFT calls per PSD iteration and per F(u~) evaluation
+      p->stats.fft_calls += 4 * (m.psd_iters + attempts);
+      p->stats.psd_iters += m.psd_iters;
+      inf.psd_iters += m.psd_iters;
+      if (attempts > 0) p->psd_hint = (int)((m.psd_iters + attempts - 1) / attempts);
+    } else {
+      p->stats.fft_calls += 8 * attempts;
+    }
     p->stats.rejected += m.rejected;
     cur = m.ring[m.cur];
     prev = m.ring[m.prev];
@@ -1693,7 +1749,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
       inf.fft_calls = p->stats.fft_calls;
       *info = inf;
     }
-    return FCH_OK;
+    return m.psd_noconv ? FCH_E_NOCONV : FCH_OK;
   }
   while (t < t_end * (1.0 - 1e-14) && inf.accepted < max_acc) {
     if (kt > t_end - t) kt = t_end - t;

@@ -105,4 +105,26 @@ __host__ __device__ inline int psd_done_code(const StepCtl& v, double ratio, int
   return 0;
 }
 
+// Device-controlled adaptive BDF2-PSD: the solve's control block for the
+// attempt at the run's current trial step (the BDF2 coefficients of the
+// run's control block, lambda fixed or from Table SearchSize), and the
+// stages of the new attempt armed.  False when there is no lambda.
+__host__ __device__ inline bool psd_arm(EnsMember* m) {
+  StepCtl& s = m->sctl;
+  const StepCtl& c = m->ctl;
+  s.k_np1 = c.k_np1;
+  s.k_n = c.k_n;
+  s.a = c.a;
+  s.b = c.b;
+  s.c = c.c;
+  s.gamma = c.gamma;
+  s.lambda = m->psd_lambda > 0.0 ? m->psd_lambda : lambda_table(m->c.q, c.k_np1);
+  s.iters = 0;
+  s.done = 0;
+  s.ratio = 0.0;
+  m->psd_init_skip = 0;
+  m->psd_eval_skip = 1;
+  return s.lambda > 0.0;
+}
+
 }  // namespace fch

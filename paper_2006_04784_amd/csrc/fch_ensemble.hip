@@ -120,14 +120,14 @@ fch_status enqueue_class(fch_ensemble_s* e, const EnsClass& c, hipStream_t s) {
   const fch::ColVT* cv = c.plan->cv;
   const int sch = e->opts.scheme;
   HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD_PRO : fch::ENS_PRO, e->dmem, c.first, c.count, s));
-  HCHK(rv->row_ens(e->dmem, c.first, c.count, 0, s));
+  HCHK(rv->row_ens(e->dmem, c.first, c.count, fch::ENS_ROW, s));
   if (sch == FCH_SAV) {
     HCHK(cv->col_ens(fch::ENS_SAV, e->dmem, c.first, c.count, s));
     HCHK(cv->col_ens(fch::ENS_SAV_FIELD, e->dmem, c.first, c.count, s));
   } else {
     HCHK(cv->col_ens(sch == FCH_ETD ? fch::ENS_ETD2 : fch::ENS_IMEX, e->dmem, c.first, c.count, s));
   }
-  HCHK(rv->row_ens(e->dmem, c.first, c.count, 1, s));
+  HCHK(rv->row_ens(e->dmem, c.first, c.count, fch::ENS_ROW_TRACK, s));
   HCHK(cv->col_ens(fch::ENS_AM3, e->dmem, c.first, c.count, s));
   HCHK(fch::launch_ens_control(e->dmem, c.first, c.count, s));
   return FCH_OK;

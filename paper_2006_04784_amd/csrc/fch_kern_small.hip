@@ -109,10 +109,19 @@ __global__ __launch_bounds__(256) void k_sav_combine(cd* out, const cd* q, StepC
 // Steps 3-4 and Step 0 of the next step): relative AM3 error from the
 // column partial sums, accept / reject, the next trial step, slot rotation,
 // and the BDF2 / AM3 scalars of the next attempt.
+// the run has ended: every stage of a PSD member stands still from now on
+__device__ __forceinline__ void ens_finish(EnsMember* m) {
+  m->ctl.done = 1;
+  m->psd_init_skip = 1;
+  m->psd_eval_skip = 1;
+  m->sctl.done = 4;
+}
+
 __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) {
   __shared__ double red[256];
   EnsMember* m = mem + first + blockIdx.x;
   if (m->ctl.done) return;
+  if (m->psd && m->psd_eval_skip) return;  // the PSD solve of the attempt still runs
   const double c0 = sum_strided(m->cpart, m->H, 2, 0, red);
   const double c1 = sum_strided(m->cpart, m->H, 2, 1, red);
   // largest u of the trial state: one value per workgroup of the trial
@@ -132,13 +141,24 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
   if (threadIdx.x != 0) return;
   um = red[0];
   StepCtl& ctl = m->ctl;
+  if (m->psd) {
+    // the solve stopped: converged (1), at max_iter (2) or non-finite (3)
+    m->psd_iters += m->sctl.iters;
+    m->psd_last_iters = m->sctl.iters;
+    if (m->sctl.done == 2) m->psd_noconv = 1;
+    if (m->sctl.done == 3 || m->sctl.nonfinite) ctl.nonfinite = 1;
+    if (m->sctl.done != 1) {
+      ens_finish(m);
+      return;
+    }
+  }
   const double kt = ctl.k_np1;
   const double e = sqrt(c0 / c1);
   const int accept = am3_decide(ctl, e);
   const double kn = ctl.k_next;
   if (!isfinite(e) || ctl.invalid) {  // invalid: SAV's E_1 + D_0 <= 0
     if (!ctl.invalid) ctl.nonfinite = 1;
-    ctl.done = 1;
+    ens_finish(m);
     return;
   }
   if (accept) {
@@ -160,7 +180,7 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
     m->rejected += 1;
   }
   if (m->t >= m->t_end * (1.0 - 1e-14) || m->accepted >= m->max_accepted) {
-    ctl.done = 1;
+    ens_finish(m);
     return;
   }
   double k1 = kn;
@@ -168,6 +188,10 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
   const double k0 = ctl.k_n;
   set_bdf2(ctl, k1, k0);
   set_am3(ctl, k1, k0);
+  if (m->psd && !psd_arm(m)) {  // no lambda for this q
+    ctl.invalid = 1;
+    ens_finish(m);
+  }
 }
 
 hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s) {

@@ -60,6 +60,11 @@ struct RowArgs {
   const double* psd_part;
   int psd_ncol;
   int psd_iter;
+  // device-controlled PSD rounds (nullable): workgroup 0 sets *psd_init_skip
+  // (the initial iterate is consumed) and, when the test stops the solve,
+  // clears *psd_eval_skip
+  int* psd_init_skip;
+  int* psd_eval_skip;
   // kernel timing (nullable): the earliest workgroup start, in ticks of the
   // device's constant wall clock, is folded in with an atomic minimum
   unsigned long long* tstart;
@@ -132,10 +137,25 @@ struct EnsMember {
   double t, t_end;
   long long accepted, rejected, max_accepted;
   int H;
-  int pad;
+  // adaptive BDF2-PSD under device control (psd = 1): sctl is the solve's
+  // control block (BDF2 coefficients, lambda, tolerance, completed iterations,
+  // stop code in sctl.done); the attempt's stages run while their flag is 0:
+  // psd_init_skip (the initial iterate, cleared by the controller for a new
+  // attempt), sctl.done (the iterations) and psd_eval_skip (the F(u~)
+  // evaluation and the controller, cleared when the solve stops)
+  int psd;
+  StepCtl sctl;
+  int psd_init_skip, psd_eval_skip;
+  int psd_noconv;      // a solve reached max_iter: the run stops
+  int psd_last_iters;  // iterations of the latest attempt
+  double psd_lambda;   // > 0: fixed search step, else Table SearchSize at the trial step
+  long long psd_iters; // iterations of all attempts
 };
 // IMEX attempt: PRO, row, IMEX, row, AM3; ETDRK2 attempt: ETD_PRO, row, ETD2, row, AM3;
-// SAV attempt: PRO, row (E_1 partials), SAV, SAV_FIELD, row, AM3
+// SAV attempt: PRO, row (E_1 partials), SAV, SAV_FIELD, row, AM3; PSD round:
+// PSD_INIT, c x (row with the stopping test, PSD), row, AM3 (the row pass
+// that stops the solve leaves the final iterate's column-inverted (u, Lap u)
+// in the pair buffer for the evaluation of F(u~))
 enum EnsStage {
   ENS_PRO = 0,
   ENS_IMEX = 1,
@@ -143,8 +163,13 @@ enum EnsStage {
   ENS_ETD_PRO = 3,
   ENS_ETD2 = 4,
   ENS_SAV = 5,
-  ENS_SAV_FIELD = 6
+  ENS_SAV_FIELD = 6,
+  ENS_PSD_INIT = 7,
+  ENS_PSD = 8
 };
+// row_ens modes: the first evaluation of an attempt, the trial's evaluation
+// (tracking the largest u), a PSD iteration (stopping test of the previous one)
+enum EnsRow { ENS_ROW = 0, ENS_ROW_TRACK = 1, ENS_ROW_PSD = 2 };
 
 // Launch tables of the compiled variants of one grid size.  Row-pass and
 // column-pass variants are chosen independently.
@@ -153,8 +178,9 @@ struct RowVT {
   // e0/e1 (nullable): events attached to the dispatch (kernel execution time)
   hipError_t (*row)(int mode, const RowArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   // batched row pass (chemical-potential pieces) over members [first, first+count);
-  // track: also the largest u per workgroup (into each member's umaxpart)
-  hipError_t (*row_ens)(EnsMember* m, int first, int count, int track, hipStream_t s);
+  // mode (EnsRow): ENS_ROW_TRACK also records the largest u per workgroup
+  // (into each member's umaxpart); ENS_ROW_PSD is a PSD iteration
+  hipError_t (*row_ens)(EnsMember* m, int first, int count, int mode, hipStream_t s);
   // ROW_FWD / ROW_INV over `batch` fields stored back to back
   hipError_t (*row_batch)(int mode, const RowArgs& a, int batch, size_t pstride, size_t sstride,
                           hipStream_t s);

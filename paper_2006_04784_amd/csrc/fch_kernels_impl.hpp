@@ -196,6 +196,7 @@ __device__ __forceinline__ int psd_check(const RowArgs& a) {
       a.ctl->iters = a.psd_iter;
       if (code) a.ctl->done = code;
       if (code == 3) a.ctl->nonfinite = 1;
+      if (code && a.psd_eval_skip) *a.psd_eval_skip = 0;
     }
   }
   __syncthreads();
@@ -224,6 +225,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done,
   __shared__ double red[2 * ((NT + 63) / 64)];
   if (done && *done) return;
   if constexpr (MODE == ROW_MU) {
+    if (a.psd_init_skip && blockIdx.x == 0 && threadIdx.x == 0) *a.psd_init_skip = 1;
     if (a.psd_part && psd_check<NT>(a)) return;
   }
 
@@ -900,10 +902,31 @@ __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
 }
 
 // ---- batched ensemble entry points (member = blockIdx.y) --------------------
+// Member fields that no kernel changes while it runs (the model constants, the
+// buffer pointers, the slot indices and flags, which only the controller
+// kernel rotates) are read through the constant address space: scalar loads,
+// issued together at the start of every workgroup.  Control blocks and the
+// stage flags, which workgroup 0 of some stages writes, are read directly.
+template <class T>
+__device__ __forceinline__ T ldc(const T& x) {
+  if constexpr (std::is_scalar<T>::value) {
+    return *(const __attribute__((address_space(4))) T*)(&x);
+  } else {  // a struct of 8-byte words (the model constants)
+    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "struct of 8-byte words");
+    using W = unsigned long long;
+    const __attribute__((address_space(4))) W* p = (const __attribute__((address_space(4))) W*)(&x);
+    T r;
+    W* q = reinterpret_cast<W*>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) q[i] = p[i];
+    return r;
+  }
+}
+
 __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
-  a.c = m->c;
-  a.P0 = m->P0;
-  a.P1 = m->P1;
+  a.c = ldc(m->c);
+  a.P0 = ldc(m->P0);
+  a.P1 = ldc(m->P1);
   a.s0 = nullptr;
   a.s1 = nullptr;
   a.out = nullptr;
@@ -915,7 +938,7 @@ __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
   a.X_out = nullptr;
   a.partial = nullptr;
   a.ctl = const_cast<StepCtl*>(&m->ctl);
-  a.tw = m->tw;
+  a.tw = ldc(m->tw);
   a.sav_rpart = nullptr;
   a.sav_nrow = 0;
   a.sav_cpart = nullptr;
@@ -924,87 +947,132 @@ __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
   a.tstart = nullptr;
 }
 
-template <int N, int R, int E, int TWL, bool UMAX>
+// the buffers of the member's state and F slots
+__device__ __forceinline__ cd* ring_at(const EnsMember* m, int slot) { return ldc(m->ring[slot]); }
+__device__ __forceinline__ cd* fring_at(const EnsMember* m, int slot) { return ldc(m->fring[slot]); }
+
+template <int N, int R, int E, int TWL, int ROWMODE>
 __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first) {
   EnsMember* m = mem + first + blockIdx.y;
+  constexpr bool UMAX = (ROWMODE == ENS_ROW_TRACK);
+  const int psd = ldc(m->psd);
   RowArgs a;
-  a.c = m->c;
-  a.P0 = m->P0;
-  a.P1 = m->P1;
+  a.c = ldc(m->c);
+  a.P0 = ldc(m->P0);
+  a.P1 = ldc(m->P1);
   a.u_in = nullptr;
   a.u_out = nullptr;
   a.X_in = nullptr;
   a.X_out = nullptr;
-  a.partial = (!UMAX && m->sav) ? m->rpart : nullptr;  // SAV: E_1 partials of u*
+  a.partial = (ROWMODE == ENS_ROW && ldc(m->sav)) ? ldc(m->rpart) : nullptr;  // SAV: E_1 of u*
   a.ctl = &m->ctl;
-  a.tw = m->tw;
+  a.tw = ldc(m->tw);
   a.psd_part = nullptr;
   a.psd_ncol = 0;
   a.psd_iter = 0;
+  a.psd_init_skip = nullptr;
+  a.psd_eval_skip = nullptr;
   a.tstart = nullptr;
-  row_body<N, R, E, ROW_MU, TWL, UMAX>(a, &m->ctl.done, m->umaxpart);
+  const int* done = &m->ctl.done;
+  if constexpr (ROWMODE == ENS_ROW_PSD) {
+    // a PSD iteration of the solve whose control block is sctl: first the
+    // stopping test of the previous iteration (none before the first)
+    a.ctl = &m->sctl;
+    const int it = m->sctl.iters;
+    a.psd_part = (it > 0) ? ldc(m->cpart) : nullptr;
+    a.psd_ncol = ldc(m->H);
+    a.psd_iter = it;
+    a.psd_init_skip = &m->psd_init_skip;
+    a.psd_eval_skip = &m->psd_eval_skip;
+    done = &m->sctl.done;
+  } else {
+    if (psd) done = &m->psd_eval_skip;  // the F(u~) evaluation of a PSD attempt
+  }
+  row_body<N, R, E, ROW_MU, TWL, UMAX>(a, done, ldc(m->umaxpart));
 }
 
 // one attempt of adaptive BDF2-IMEX: PRO (u* and Lap u* of the step),
 // IMEX (the step, then u~ and Lap u~ for F(u~)), AM3 (F(u~) and the error sums);
 // of adaptive ETDRK2: ETD_PRO (first stage from the cached F(u^n)), ETD2 (the
 // step, then the trial's (u, Lap u)), AM3; of adaptive SAV: PRO, SAV (p, q and
-// the r-solve sums), SAV_FIELD (r^{n+1}, the trial and its (u, Lap u)), AM3
+// the r-solve sums), SAV_FIELD (r^{n+1}, the trial and its (u, Lap u)), AM3;
+// of adaptive PSD (rounds): PSD_INIT, PSD iterations, AM3
 template <int N, int E, int TWL, int STAGE>
 __global__ __launch_bounds__(N / E) void k_col_ens(EnsMember* mem, int first) {
   EnsMember* m = mem + first + blockIdx.y;
   ColArgs a;
   ens_col_args(m, a);
+  const int cur = ldc(m->cur), prev = ldc(m->prev), trial = ldc(m->trial);
   if constexpr (STAGE == ENS_PRO) {
-    a.s0 = m->ring[m->cur];
-    a.s1 = m->ring[m->prev];
+    a.s0 = ring_at(m, cur);
+    a.s1 = ring_at(m, prev);
     col_body<N, E, EPI_NONE, PRO_EXTRAP, TWL>(a, &m->ctl.done);
   } else if constexpr (STAGE == ENS_IMEX) {
-    a.s0 = m->ring[m->cur];
-    a.s1 = m->ring[m->prev];
-    a.out = m->ring[m->trial];
+    a.s0 = ring_at(m, cur);
+    a.s1 = ring_at(m, prev);
+    a.out = ring_at(m, trial);
     col_body<N, E, EPI_IMEX, PRO_NEXT_FIELD, TWL>(a, &m->ctl.done);
   } else if constexpr (STAGE == ENS_ETD_PRO) {
     // u~ and w from u^n and the cached F(u^n); u~ goes to the F slot that the
     // attempt's AM3 stage overwrites last
-    a.s0 = m->ring[m->cur];
-    a.f_n = m->fring[m->fn];
-    a.out = m->fring[m->ft];
-    a.aux = m->aux;
+    a.s0 = ring_at(m, cur);
+    a.f_n = fring_at(m, ldc(m->fn));
+    a.out = fring_at(m, ldc(m->ft));
+    a.aux = ldc(m->aux);
     col_body<N, E, EPI_NONE, PRO_ETD1, TWL>(a, &m->ctl.done);
   } else if constexpr (STAGE == ENS_ETD2) {
-    a.s0 = m->fring[m->ft];
-    a.s1 = m->aux;
-    a.out = m->ring[m->trial];
+    a.s0 = fring_at(m, ldc(m->ft));
+    a.s1 = ldc(m->aux);
+    a.out = ring_at(m, trial);
     col_body<N, E, EPI_ETD2, PRO_NEXT_FIELD, TWL>(a, &m->ctl.done);
   } else if constexpr (STAGE == ENS_SAV) {
     // p into the trial slot, q into aux, the (g_p, g_q) partials; s* from the
     // first row pass's E_1 partials
-    a.s0 = m->ring[m->cur];
-    a.s1 = m->ring[m->prev];
-    a.out = m->ring[m->trial];
-    a.aux = m->aux;
-    a.partial = m->cpart;
-    a.sav_rpart = m->rpart;
-    a.sav_nrow = m->nrow;
+    a.s0 = ring_at(m, cur);
+    a.s1 = ring_at(m, prev);
+    a.out = ring_at(m, trial);
+    a.aux = ldc(m->aux);
+    a.partial = ldc(m->cpart);
+    a.sav_rpart = ldc(m->rpart);
+    a.sav_nrow = ldc(m->nrow);
     col_body<N, E, EPI_SAV, PRO_NONE, TWL>(a, &m->ctl.done);
+  } else if constexpr (STAGE == ENS_PSD_INIT) {
+    // a new attempt's initial iterate u^n + gamma (u^n - u^{n-1}) (eq.
+    // recurrence) into the trial slot, b u^n + c u^{n-1} into aux, and the
+    // iterate's (u, Lap u) for the first iteration
+    a.ctl = &m->sctl;
+    a.s0 = ring_at(m, cur);
+    a.s1 = ring_at(m, prev);
+    a.out = ring_at(m, trial);
+    a.aux = ldc(m->aux);
+    col_body<N, E, EPI_NONE, PRO_PSD_INIT, TWL>(a, &m->psd_init_skip);
+  } else if constexpr (STAGE == ENS_PSD) {
+    // one iteration (the direction, the update in place, the stopping sums)
+    // and the next iterate's (u, Lap u); workgroup 0 counts the iteration
+    if (m->sctl.done) return;
+    a.ctl = &m->sctl;
+    a.out = ring_at(m, trial);
+    a.aux = ldc(m->aux);
+    a.partial = ldc(m->cpart);
+    col_body<N, E, EPI_PSD, PRO_NEXT_FIELD, TWL>(a, &m->sctl.done);
+    if (blockIdx.x == 0 && threadIdx.x == 0) m->sctl.iters += 1;
   } else if constexpr (STAGE == ENS_SAV_FIELD) {
     // r^{n+1}, u^{n+1} = p + r^{n+1} q over p, and its (u, Lap u) for F
-    a.s0 = m->ring[m->cur];
-    a.out = m->ring[m->trial];
-    a.aux = m->aux;
-    a.sav_cpart = m->cpart;
-    a.sav_ncol = m->H;
-    a.rslot = m->rslot;
+    a.s0 = ring_at(m, cur);
+    a.out = ring_at(m, trial);
+    a.aux = ldc(m->aux);
+    a.sav_cpart = ldc(m->cpart);
+    a.sav_ncol = ldc(m->H);
+    a.rslot = ldc(m->rslot);
     col_body<N, E, EPI_NONE, PRO_SAV_FIELD, TWL>(a, &m->ctl.done);
   } else {
-    a.s0 = m->ring[m->trial];
-    a.s1 = m->ring[m->cur];
-    a.f_n = m->fring[m->fn];
-    a.f_nm1 = m->fring[m->fm];
-    a.out = m->fring[m->ft];
-    a.partial = m->cpart;
-    col_body<N, E, EPI_AM3, PRO_NONE, TWL>(a, &m->ctl.done);
+    a.s0 = ring_at(m, trial);
+    a.s1 = ring_at(m, cur);
+    a.f_n = fring_at(m, ldc(m->fn));
+    a.f_nm1 = fring_at(m, ldc(m->fm));
+    a.out = fring_at(m, ldc(m->ft));
+    a.partial = ldc(m->cpart);
+    col_body<N, E, EPI_AM3, PRO_NONE, TWL>(a, ldc(m->psd) ? &m->psd_eval_skip : &m->ctl.done);
   }
 }
 

@@ -41,13 +41,23 @@ struct RowImpl {
     }
     return hipGetLastError();
   }
-  static hipError_t row_ens(EnsMember* m, int first, int count, int track, hipStream_t s) {
-    if (track)
-      hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, true>), dim3(N / R, count), dim3(NT), 0, s, m,
-                         first);
-    else
-      hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, false>), dim3(N / R, count), dim3(NT), 0, s, m,
-                         first);
+  static hipError_t row_ens(EnsMember* m, int first, int count, int mode, hipStream_t s) {
+    switch (mode) {
+      case ENS_ROW:
+        hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, ENS_ROW>), dim3(N / R, count), dim3(NT), 0, s,
+                           m, first);
+        break;
+      case ENS_ROW_TRACK:
+        hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, ENS_ROW_TRACK>), dim3(N / R, count), dim3(NT),
+                           0, s, m, first);
+        break;
+      case ENS_ROW_PSD:
+        hipLaunchKernelGGL((k_row_ens<N, R, E, TWL, ENS_ROW_PSD>), dim3(N / R, count), dim3(NT), 0,
+                           s, m, first);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   static hipError_t row_batch(int mode, const RowArgs& a, int batch, size_t pstride,
@@ -135,6 +145,12 @@ struct ColImpl {
         break;
       case ENS_SAV_FIELD:
         hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_SAV_FIELD>), grid, dim3(CT), 0, s, m, first);
+        break;
+      case ENS_PSD_INIT:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_PSD_INIT>), grid, dim3(CT), 0, s, m, first);
+        break;
+      case ENS_PSD:
+        hipLaunchKernelGGL((k_col_ens<N, E, TWL, ENS_PSD>), grid, dim3(CT), 0, s, m, first);
         break;
       default:
         return hipErrorInvalidValue;

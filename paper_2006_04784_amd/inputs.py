@@ -164,13 +164,17 @@ def paper_strip_indicator(N0: int = PAPER_N0, eps: float = 0.1, R: float = PAPER
     offset curves Gamma_+- (the points within distance R of Gamma, R being far
     below Gamma's smallest radius of curvature), -1 outside, each mesh value
     being the average of the indicator over its cell (sub x sub points; only
-    cells the strip's edge crosses need more than their centre)."""
+    cells the strip's edge crosses need more than their centre).  sub = 1
+    samples the indicator at the mesh points instead."""
     X, Y = grid(N0, L)
     h = L / N0
     phi = -np.ones((N0, N0))
     r = np.hypot(X - L / 2, Y - L / 2)
     ci, cj = np.nonzero(np.abs(r - 3.0) < 0.45)
     d = _curve_distance(X[ci, cj], Y[ci, cj], eps, L)
+    if sub == 1:
+        phi[ci[d < R], cj[d < R]] = 1.0
+        return phi
     inner = d < R - h
     phi[ci[inner], cj[inner]] = 1.0
     edge = np.abs(d - R) <= h
@@ -185,29 +189,38 @@ def paper_strip_indicator(N0: int = PAPER_N0, eps: float = 0.1, R: float = PAPER
 
 
 def paper_initial_data(name: str, N: int = None, eps: float = 0.1, physical_k: bool = False,
-                       d: float = None):
+                       d: float = None, sampling: str = "cell", n0: int = PAPER_N0):
     """u^0_N = phi_256 + eps d / alpha_m(0)^2 (eq. dcoef) for a benchmark of
     Table t:Benchmark.  phi_256 = F[phi_Gamma]: the DFT of the strip indicator
     on the 256 mesh times exp(-lambda0 (k1^2 + k2^2)), summed as a
     trigonometric polynomial and evaluated on the N x N grid (N >= 256).  The
     filter takes the integer mode indices k1, k2 literally; physical_k uses the
     wavenumbers 2 pi k / L instead.  d overrides the benchmark's background
-    parameter.  Returns (model keyword arguments, u0)."""
+    parameter.  Readings of the indicator's "interpolation" to the mesh:
+    sampling = "cell" (cell averages) or "point" (values at the mesh points);
+    n0: the mesh of the indicator and its DFT (256 in the text; 512 resolves
+    the strip's edge better; the filter leaves no weight beyond |k| = 128).
+    Returns (model keyword arguments, u0)."""
     b = PAPER_BENCHMARKS[name]
     d = b["d"] if d is None else d
     N = N or b["N"]
-    N0 = PAPER_N0
-    if N < N0 or N % N0:
-        raise ValueError("N must be a multiple of %d" % N0)
-    phi = paper_strip_indicator(N0, eps)
+    N0 = n0
+    if sampling not in ("cell", "point"):
+        raise ValueError(sampling)
+    if N < PAPER_N0 or N % PAPER_N0 or N0 % PAPER_N0:
+        raise ValueError("N and n0 must be multiples of %d" % PAPER_N0)
+    phi = paper_strip_indicator(N0, eps, sub=8 if sampling == "cell" else 1)
     ph = np.fft.fft2(phi)
     k = np.fft.fftfreq(N0, d=1.0 / N0)           # integer indices -N0/2 .. N0/2-1
     if physical_k:
         k = k * 2 * np.pi / PAPER_L
     ph *= np.exp(-PAPER_LAMBDA0 * (k[:, None] ** 2 + k[None, :] ** 2))
-    # zero-pad to N (the Nyquist row and column split evenly between +-N0/2)
+    # carry the modes |k| < M/2 over to the N grid (M = min(N, N0)); the
+    # Nyquist row and column (+-M/2) split evenly when padding, and are
+    # dropped when truncating (their weight, exp(-lambda0 M^2/4) < 1e-49)
+    M = min(N, N0)
     big = np.zeros((N, N), complex)
-    h = N0 // 2
+    h = M // 2
     idx = np.concatenate([np.arange(h), np.arange(N - h, N)])
     src = np.concatenate([np.arange(h), np.arange(N0 - h, N0)])
     big[np.ix_(idx, idx)] = ph[np.ix_(src, src)]
@@ -218,6 +231,9 @@ def paper_initial_data(name: str, N: int = None, eps: float = 0.1, physical_k: b
         nx = big[:, N - h].copy()
         big[:, N - h] = 0.5 * nx
         big[:, h] = 0.5 * nx
+    elif N < N0:
+        big[N - h, :] = 0.0
+        big[:, N - h] = 0.0
     phiN = np.real(np.fft.ifft2(big)) * (N / N0) ** 2
     u0 = phiN + eps * d / PAPER_ALPHA0 ** 2
     kw = dict(N=N, L=PAPER_L, eps=eps, eta1=b["eta1"], eta2=b["eta2"], q=b["q"])

@@ -38,15 +38,17 @@ def onset(ds, umax, threshold=DEFECT_THRESHOLD):
 
 def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_THRESHOLD,
                      N=256, physical_k=False, max_steps=1000000, device="cuda:0", log=None,
-                     chunk=5000, scheme="imex"):
+                     chunk=5000, scheme="imex", sampling="cell", n0=inputs.PAPER_N0):
     """Runs one ensemble member per d with one scheme (imex, sav or etd) and
     returns a dict with the per-member running max of u, accepted / rejected
     steps, end times, the critical d (None when no member crosses the
-    threshold) and the wall time."""
+    threshold) and the wall time.  physical_k, sampling and n0 select a
+    reading of the initial data (inputs.paper_initial_data)."""
     ds = [float(d) for d in ds]
     members, u0s = [], []
     for d in ds:
-        kw, u0 = inputs.paper_initial_data("critical", N=N, d=d, physical_k=physical_k)
+        kw, u0 = inputs.paper_initial_data("critical", N=N, d=d, physical_k=physical_k,
+                                           sampling=sampling, n0=n0)
         members.append(kw)
         u0s.append(u0)
     ens = fch.Ensemble(members, adapt=fch.AdaptOpts(sigma_tol=sigma_tol), t_end=t_end,
@@ -310,6 +312,110 @@ def grid_refinement(benchmarks=None, sigma_tol=1e-5, pairs=None, device="cuda:0"
     return out
 
 
+# ---- global error against cost ("dollars per digit", Sec. 5.2) ---------------
+# local error targets of the sweep and the reference runs of Sec. 5.2: PSD at
+# sigma_tol 1e-9 (q = 0) and 3e-8 (q = 0.2), IMEX at 3e-9 (q = 0.5)
+DPD_SIGMAS = (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7)
+DPD_REFERENCE = {0.0: ("psd", 1e-9), 0.2: ("psd", 3e-8), 0.5: ("imex", 3e-9)}
+
+
+def adaptive_final(plan, uh0, scheme, sigma_tol, t_end, q, max_steps=20000000):
+    """One adaptive run from uh0 to t_end at sigma_tol (PSD: i_tol = nu sigma_tol
+    and k_max of Table tolPSD); returns (physical final state, run info with the
+    FFT calls of the run)."""
+    nu, kmax = PSD_SETTINGS[q]
+    a, b = uh0.clone(), torch.empty_like(uh0)
+    plan.reset_stats()
+    t1 = time.perf_counter()
+    info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=t_end,
+                    k_first=1e-9, nsteps=max_steps, psd_tol=nu * sigma_tol, psd_max_iter=20000,
+                    adapt=fch.AdaptOpts(sigma_tol=sigma_tol,
+                                        k_max=kmax if scheme == "psd" else float("inf")))
+    info["fft_calls"] = plan.stats()["fft_calls"]
+    info["seconds"] = round(time.perf_counter() - t1, 2)
+    return plan.inverse(a), info
+
+
+def cost_at_error(rows, target):
+    """FFT calls at which each scheme's global error first falls to target, going
+    down its sigma_tol sweep: log-log interpolation between the last run above
+    and the first at or below the target (None if no run reaches it; the first
+    run's calls, flagged, if the coarsest already does)."""
+    out = {}
+    for sch in sorted({r["scheme"] for r in rows}):
+        rs = sorted([r for r in rows if r["scheme"] == sch and "error" in r],
+                    key=lambda r: -r["sigma_tol"])
+        hit = None
+        for i, r in enumerate(rs):
+            if r["error"] <= target:
+                if i == 0:
+                    hit = {"fft_calls": r["fft_calls"], "sigma_tol": r["sigma_tol"],
+                           "coarsest_run": True}
+                else:
+                    p = rs[i - 1]
+                    w = (np.log(target) - np.log(p["error"])) / (np.log(r["error"]) -
+                                                                  np.log(p["error"]))
+                    calls = np.exp(np.log(p["fft_calls"]) +
+                                   w * (np.log(r["fft_calls"]) - np.log(p["fft_calls"])))
+                    hit = {"fft_calls": float(calls),
+                           "between_sigma_tol": (p["sigma_tol"], r["sigma_tol"])}
+                break
+        out[sch] = hit
+    return out
+
+
+def cost_vs_error(name="super-critical", sigmas=DPD_SIGMAS, schemes=("imex", "sav", "psd", "etd"),
+                  reference=None, etd_min_sigma=1e-6, psd_min_sigma=None, device="cuda:0",
+                  log=None, targets=(2.5e-3, 7e-4)):
+    """Global relative L2 error at the benchmark's final time (Table
+    t:Comp-error) against the total FFT calls of each scheme over a sweep of
+    sigma_tol, measured against the reference run of Sec. 5.2 (DPD_REFERENCE;
+    ETDRK2 only for q = 0, as in the paper).  Returns the runs and, per target
+    error, each scheme's interpolated FFT calls (cost_at_error)."""
+    kw, u0 = inputs.paper_initial_data(name)
+    q = kw["q"]
+    T = COMP_T[name]
+    plan = fch.Plan(**kw, device=device)
+    uh0 = plan.forward(torch.from_numpy(np.ascontiguousarray(u0)).to(plan.device))
+    ref_scheme, ref_sigma = reference or DPD_REFERENCE[q]
+    tw = time.perf_counter()
+    u_ref, info = adaptive_final(plan, uh0, ref_scheme, ref_sigma, T, q)
+    nref = float(torch.linalg.norm(u_ref))
+    if log:
+        log("%s reference %s sigma %.0e: %d steps, %d FFT calls, %.1f s" %
+            (name, ref_scheme, ref_sigma, info["accepted"], info["fft_calls"],
+             time.perf_counter() - tw))
+    rows = []
+    for sch in schemes:
+        if sch == "etd" and q != 0.0:
+            continue
+        for sg in sigmas:
+            if sch == "etd" and sg < etd_min_sigma:
+                continue
+            if sch == "psd" and psd_min_sigma is not None and sg < psd_min_sigma:
+                continue
+            row = {"scheme": sch, "sigma_tol": sg}
+            try:
+                u, inf_ = adaptive_final(plan, uh0, sch, sg, T, q)
+                row.update(error=float(torch.linalg.norm(u - u_ref)) / nref,
+                           fft_calls=int(inf_["fft_calls"]), accepted=int(inf_["accepted"]),
+                           rejected=int(inf_["rejected"]), psd_iters=int(inf_["psd_iters"]),
+                           seconds=inf_["seconds"])
+            except fch.FchError as ex:   # e.g. a PSD solve that missed its tolerance
+                row["failed"] = str(ex)
+            rows.append(row)
+            if log:
+                log("%s %s sigma %.0e: %s (%.1f s)" % (
+                    name, sch, sg, {k: row[k] for k in ("error", "fft_calls", "accepted")
+                                    if k in row} or row.get("failed"),
+                    time.perf_counter() - tw))
+    plan.close()
+    return {"benchmark": name, "T": T, "N": kw["N"], "q": q,
+            "reference": {"scheme": ref_scheme, "sigma_tol": ref_sigma,
+                          "accepted": int(info["accepted"]), "fft_calls": int(info["fft_calls"])},
+            "runs": rows, "cost_at": {str(t): cost_at_error(rows, t) for t in targets}}
+
+
 def paper_d_values():
     """The paper's sweep: d = 0.7523, 0.7524, ..., 0.7728."""
     return [round(0.7523 + 1e-4 * i, 4) for i in range(206)]
@@ -342,7 +448,41 @@ if __name__ == "__main__":
                     help="all schemes on the five benchmarks to their final times instead")
     ap.add_argument("--rates", action="store_true",
                     help="fixed-step errors at T = 0.32 against a fine PSD reference instead")
+    ap.add_argument("--cost", default="",
+                    help="global error against FFT calls over a sigma_tol sweep (Sec. 5.2) for "
+                         "the named benchmark instead")
+    ap.add_argument("--sigmas", default="", help="comma-separated sigma_tol values for --cost")
+    ap.add_argument("--schemes", default="imex,sav,psd,etd", help="schemes for --cost")
+    ap.add_argument("--readings", action="store_true",
+                    help="critical d of each initial-data reading (filter wavenumbers, sampling "
+                         "of the strip, its mesh) at each --sigmas value instead")
     args = ap.parse_args()
+    if args.readings:
+        sig = tuple(float(x) for x in args.sigmas.split(",")) if args.sigmas else (1e-5, 1e-6, 1e-7)
+        err = lambda m: print(m, file=sys.stderr, flush=True)
+        readings = {"cell-average, integer k": {}, "point sampling": {"sampling": "point"},
+                    "512 indicator mesh": {"n0": 512}, "physical k": {"physical_k": True}}
+        out = []
+        for label, kwr in readings.items():
+            for sg in sig:
+                r = critical_d_sweep(paper_d_values(), sigma_tol=sg, t_end=args.t_end, t0=args.t0,
+                                     log=err, **kwr)
+                row = {"reading": label, "sigma_tol": sg, "d_critical": r["d_critical"],
+                       "d_max_without_defect": r["d_max_without_defect"],
+                       "umax_range_no_defect": max([u for u in r["umax"] if not u > DEFECT_THRESHOLD],
+                                                   default=None),
+                       "umax_min_defect": min([u for u in r["umax"] if u > DEFECT_THRESHOLD],
+                                              default=None),
+                       "seconds": round(r["seconds"], 1)}
+                err(json.dumps(row))
+                out.append(row)
+        print(json.dumps(out))
+        sys.exit(0)
+    if args.cost:
+        sig = tuple(float(x) for x in args.sigmas.split(",")) if args.sigmas else DPD_SIGMAS
+        print(json.dumps(cost_vs_error(args.cost, sigmas=sig, schemes=tuple(args.schemes.split(",")),
+                                       log=lambda m: print(m, file=sys.stderr, flush=True))))
+        sys.exit(0)
     if args.rates:
         print(json.dumps(temporal_convergence()))
         sys.exit(0)

@@ -788,31 +788,44 @@ def test_temporal_convergence_on_paper_data(F):
         assert r["etd"][i] > 2.0 * r["imex"][i]
 
 
-@pytest.mark.parametrize("scheme", ["imex", "etd", "sav"])
+@pytest.mark.parametrize("scheme", ["imex", "etd", "sav", "psd"])
 def test_adaptive_device_control_matches_host_loop(F, orc, scheme):
-    """fch_run's adaptive IMEX, ETDRK2 and SAV run their attempts under
-    device control (the ensemble's batched kernels and per-member controller
-    on a one-member view of the plan; SAV's r history rotates on the device);
+    """fch_run's adaptive runs take their attempts under device control (the
+    ensemble's batched kernels and per-member controller on a one-member view
+    of the plan; SAV's r history rotates on the device; PSD solves run in
+    queued rounds whose stages each run only in their phase of the attempt);
     with kernel timing on they fall back to the host loop.  Both take the
-    same decisions and reach the same state (and SAV scalars); the step limit
-    and the final time are honoured exactly."""
+    same decisions and reach the same state (and SAV scalars, PSD iteration
+    counts); the step limit and the final time are honoured exactly."""
     log("adaptive %s: device control vs host loop" % scheme)
     N, L = 256, 4 * np.pi
     plan, m = pair(F, orc, **model_kw(N, L))
     uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=4))
-    opts = F.AdaptOpts(sigma_tol=1e-5)
+    opts = F.AdaptOpts(sigma_tol=1e-5, k_max=0.05 if scheme == "psd" else float("inf"))
     res = []
     for prof in (False, True):
         plan.profile(prof)
+        plan.reset_stats()
         a, b = dev(uh0), torch.zeros_like(dev(uh0))
         info = plan.run(a, b, scheme=scheme, adaptive=True, startup=True, t_end=0.05,
                         nsteps=100000, adapt=opts)
+        info["launches"] = plan.stats()["launches"]
         res.append((host(a), host(b), info))
         if prof:
             plan.profile_read()
             plan.profile(False)
     (a0, b0, i0), (a1, b1, i1) = res
+    log("  device: %s" % {k: i0[k] for k in ("accepted", "rejected", "psd_iters", "launches")})
+    log("  host:   %s" % {k: i1[k] for k in ("accepted", "rejected", "psd_iters", "launches")})
     assert i0["accepted"] == i1["accepted"] and i0["rejected"] == i1["rejected"]
+    if scheme == "psd":
+        assert i0["psd_iters"] == i1["psd_iters"] and i0["fft_calls"] == i1["fft_calls"]
+        # two launches per iteration plus a few per attempt: the initial
+        # iterate, the F(u~) evaluation and the controller (5), iterations
+        # queued after the solve stopped, a second round when an attempt
+        # outruns its queued iterations; and the rounds queued after the end
+        attempts = i0["accepted"] + i0["rejected"]
+        assert i0["launches"] <= 2 * i0["psd_iters"] + 16 * attempts + 400
     assert abs(i0["t"] - 0.05) < 1e-15 and abs(i1["t"] - 0.05) < 1e-15
     # the error estimate is a small difference of states, so rounding differences
     # between the two kernel sets (FMA contraction) reach it at about 1e-11

@@ -71,3 +71,28 @@ def test_defect_onset_from_running_maxima():
     assert sweeps.onset(ds, [0.358] * len(ds)) == (None, 0.7728)
     assert sweeps.onset(ds, [float("nan")] * len(ds)) == (None, 0.7728)
     assert sweeps.onset(ds, [0.9] * len(ds)) == (0.7523, None)
+
+
+def test_cost_at_error_interpolation():
+    """Sec. 5.2's cost at a global error target: going down a scheme's
+    sigma_tol sweep, the FFT calls where the error first reaches the target,
+    interpolated log-log between the runs on either side of it."""
+    from paper_2006_04784_amd import sweeps
+    # error = 10 * calls^-1 exactly (a power law): interpolation is exact
+    rows = [{"scheme": "imex", "sigma_tol": s, "fft_calls": c, "error": 10.0 / c}
+            for s, c in ((1e-4, 1e3), (1e-5, 1e4), (1e-6, 1e5))]
+    hit = sweeps.cost_at_error(rows, 2.5e-4)["imex"]
+    assert abs(hit["fft_calls"] - 4e4) < 1e-6 * 4e4 and hit["between_sigma_tol"] == (1e-5, 1e-6)
+    # the coarsest run already meets the target: its calls, flagged
+    assert sweeps.cost_at_error(rows, 2e-2)["imex"]["coarsest_run"]
+    # never reached; failed runs (no error) are skipped
+    rows.append({"scheme": "psd", "sigma_tol": 1e-3, "failed": "no convergence"})
+    rows.append({"scheme": "psd", "sigma_tol": 1e-4, "fft_calls": 10, "error": 0.5})
+    res = sweeps.cost_at_error(rows, 1e-6)
+    assert res["imex"] is None and res["psd"] is None
+    # a non-monotone error curve: the first crossing in sweep order counts
+    rows = [{"scheme": "sav", "sigma_tol": s, "fft_calls": c, "error": e}
+            for s, c, e in ((1e-4, 100, 1e-2), (1e-5, 200, 1e-3), (1e-6, 400, 2e-3),
+                            (1e-7, 800, 1e-4))]
+    hit = sweeps.cost_at_error(rows, 5e-3)["sav"]
+    assert hit["between_sigma_tol"] == (1e-4, 1e-5) and 100 < hit["fft_calls"] < 200
