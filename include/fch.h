@@ -363,6 +363,18 @@ typedef struct {
     fch_adapt_opts adapt;
     fch_psd_opts psd;
     fch_etd_opts etd;
+    /* dyadic = 1 (adaptive runs): nested factor-of-two step sizes, the
+     * adaptive strategy the paper pairs with SAV's fixed-step energy law
+     * (Sec. 1, Sec. 5.2): every step is k_first 2^j (the first trial when
+     * startup = 0, k); a rejected step is halved (or cut to the largest such
+     * size not above the step law's proposal); after an accepted step the
+     * size doubles only when the proposal allows it and the new time lies on
+     * the grid of the doubled size (so coarse steps nest over fine ones),
+     * stays when the proposal allows it, and otherwise drops to the largest
+     * ladder size not above the proposal; always within [k_min, k_max] on the
+     * ladder, the last step clamped to t_end.  Attempts then run from the host
+     * loop.  0: the step law of Sec. 3.2. */
+    int32_t dyadic;
 } fch_run_opts;
 typedef struct {
     int64_t accepted, rejected, psd_iters, fft_calls;

@@ -21,19 +21,35 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fch_oracle.c")
 _SRC_NN = os.path.join(_HERE, "nn_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_DEFAULT = os.path.join(_HERE, "liboracle.so")
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+# FCH_ORACLE_LIB selects another build of the same sources (the sanitized one)
+_LIB_PATH = os.environ.get("FCH_ORACLE_LIB", _LIB_DEFAULT)
 _lib = None
+_CLANG = "/opt/rocm/llvm/bin/clang"
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O3, OpenMP over independent lines)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O3, OpenMP over independent lines).
+    sanitize: a separate liboracle_san.so with AddressSanitizer and
+    UndefinedBehaviorSanitizer, built with the ROCm clang so that it shares
+    one sanitizer runtime with the sanitized host code of the HIP library
+    (no OpenMP)."""
+    if sanitize:
+        tmp = _LIB_SAN + ".tmp%d" % os.getpid()
+        cmd = [_CLANG, "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined", "-shared-libsan", "-fPIC", "-shared",
+               "-std=c11", "-Wall", "-o", tmp, _SRC, _SRC_NN, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_SAN)
+        return _LIB_SAN
+    if force or not os.path.exists(_LIB_DEFAULT):
+        tmp = _LIB_DEFAULT + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared",
                "-std=c11", "-Wall", "-o", tmp, _SRC, _SRC_NN, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, _LIB_DEFAULT)
+    return _LIB_DEFAULT
 
 
 class Params(C.Structure):

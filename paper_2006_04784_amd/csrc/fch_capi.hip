@@ -112,6 +112,7 @@ RowArgs row_args(fch_plan_s* p) {
   a.P1 = p->P1;
   a.ctl = p->ctl;
   a.tw = p->tw;
+  a.check_done = p->check_done;
   return a;
 }
 
@@ -123,8 +124,17 @@ ColArgs col_args(fch_plan_s* p) {
   a.P1 = p->P1;
   a.ctl = p->ctl;
   a.tw = p->tw;
+  a.check_done = p->check_done;
   return a;
 }
+
+// the launches made while it lives read the control block's done code
+struct CheckDone {
+  fch_plan_s* p;
+  int keep;
+  explicit CheckDone(fch_plan_s* q) : p(q), keep(q->check_done) { p->check_done = 1; }
+  ~CheckDone() { p->check_done = keep; }
+};
 
 fch_status need_ws(fch_plan_s* p) { return p->ws ? FCH_OK : FCH_E_NOMEM; }
 
@@ -232,6 +242,7 @@ fch_status finalize(fch_plan_s* p, int mode, bool rows, bool cols) {
 fch_status psd_iterations(fch_plan_s* p, const ColArgs& a, int done_before, int n) {
   for (int i = 0; i < n; ++i) {
     RowArgs r = row_args(p);
+    r.check_done = 1;  // a stopped solve's remaining launches return at once
     if (i > 0) {
       r.psd_part = p->cpart;
       r.psd_ncol = p->H;
@@ -969,6 +980,7 @@ fch_status fch_step_psd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   v.max_iter = opts->max_iter;
   v.fixed_iters = opts->fixed_iters;
   CHK(ctl_set(p, v));
+  CheckDone cd_guard(p);
   ColArgs a = col_args(p);
   a.s0 = un;
   a.s1 = um;
@@ -1164,6 +1176,7 @@ fch_status fch_step_imex_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128*
                              const double* k_dev, fch_c128* uh_np1, int32_t* status_dev) {
   CHK(check_step_dev(p, uh_n, uh_nm1, k_dev, uh_np1));
   CHK(ctl_dev(p, ctl_zero(), k_dev, nullptr, 0));
+  CheckDone cd_guard(p);
   ColArgs a = col_args(p);
   a.s0 = (const cd*)uh_n;
   a.s1 = (const cd*)uh_nm1;
@@ -1182,6 +1195,7 @@ fch_status fch_step_sav_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   CHK(check_step_dev(p, uh_n, uh_nm1, k_dev, uh_np1));
   if (!r_dev || !r_np1_dev) return FCH_E_INVALID;
   CHK(ctl_dev(p, ctl_zero(), k_dev, r_dev, fch::CTL_SAV));
+  CheckDone cd_guard(p);
   ColArgs a = col_args(p);
   a.s0 = (const cd*)uh_n;
   a.s1 = (const cd*)uh_nm1;
@@ -1222,6 +1236,7 @@ fch_status fch_step_psd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   v.max_iter = opts->max_iter;
   v.fixed_iters = opts->fixed_iters;
   CHK(ctl_dev(p, v, k_dev, nullptr, flags));
+  CheckDone cd_guard(p);
   ColArgs a = col_args(p);
   a.s0 = (const cd*)uh_n;
   a.s1 = (const cd*)uh_nm1;
@@ -1249,6 +1264,7 @@ fch_status fch_step_etd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   v.kappa0 = k0;
   v.kappa2 = k2;
   CHK(ctl_dev(p, v, k_dev, nullptr, fch::CTL_K1_ONLY));
+  CheckDone cd_guard(p);
   CHK(etd_step_launch(p, uh_n, F_n, uh_np1));
   return ctl_out(p, fch::OUT_STATUS, nullptr, nullptr, status_dev);
 }
@@ -1266,6 +1282,7 @@ fch_status fch_adapt_dt_dev(fch_plan_t p, const fch_c128* uh_trial, const fch_c1
   StepCtl v = ctl_zero();
   set_adapt(v, opts);
   CHK(ctl_dev(p, v, k_dev, nullptr, fch::CTL_AM3));
+  CheckDone cd_guard(p);
   ColArgs a = col_args(p);
   a.s0 = (const cd*)uh_trial;
   CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
@@ -1594,7 +1611,7 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
   }
   const double t_end = o->t_end;
   const int64_t max_acc = o->nsteps > 0 ? o->nsteps : INT64_MAX;
-  if (!p->prof_on) {
+  if (!p->prof_on && !o->dyadic) {
     // Attempts under device control: the run is described as one ensemble
     // member (state and F slots, time, step scalars) and each attempt is the
     // batched kernels' sequence with the per-member controller, which accepts
@@ -1751,7 +1768,20 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
     }
     return m.psd_noconv ? FCH_E_NOCONV : FCH_OK;
   }
+  // nested factor-of-two steps (o->dyadic): the trial is kb 2^jt; the accepted
+  // time is tu units of kb 2^kJmin (exact, so that alignment with the grid of
+  // a doubled step is an integer test)
+  constexpr int kJmin = -24, kJmax = 38;
+  const double kb = kt;
+  int jt = 0;
+  long long tu = 0;
+  auto ladder = [&](int j) { return std::ldexp(kb, j); };
+  if (o->dyadic) {
+    if (o->startup) tu = 1LL << (0 - kJmin);  // the startup step is kb
+    while (jt > kJmin && ladder(jt) > ad->k_max) --jt;
+  }
   while (t < t_end * (1.0 - 1e-14) && inf.accepted < max_acc) {
+    if (o->dyadic) kt = ladder(jt);
     if (kt > t_end - t) kt = t_end - t;
     double r_new = 0.0;
     int64_t it = 0;
@@ -1813,7 +1843,29 @@ fch_status fch_run(fch_plan_t p, const fch_run_opts* o, fch_c128* uh_n, fch_c128
                        (const fch_c128*)Fm, kt, k_n, ad, (fch_c128*)Ft, &acc, &kn, &e));
     }
     const bool accept = p->hctl->accept != 0;
-    const double k_next = p->hctl->k_next;
+    double k_next = p->hctl->k_next;
+    if (o->dyadic) {
+      // the step law's proposal k_next (capped and clamped) picks the next
+      // ladder size: halve (or lower) after a rejection; after an acceptance
+      // double only on the doubled grid, keep, or lower
+      const bool clamped = kt < ladder(jt);  // the final step to t_end
+      int jn = jt;
+      if (accept && !clamped) {
+        tu += 1LL << (jt - kJmin);
+        const long long coarse = 1LL << (jt + 1 - kJmin);
+        if (k_next >= 2.0 * kt && jt < kJmax && tu % coarse == 0)
+          jn = jt + 1;
+        else if (k_next < kt)
+          while (jn > kJmin && ladder(jn) > k_next) --jn;
+      } else if (!accept) {
+        jn = jt - 1;
+        while (jn > kJmin && ladder(jn) > k_next) --jn;
+      }
+      while (jn > kJmin && ladder(jn) > ad->k_max) --jn;
+      while (jn < jt && ladder(jn) < ad->k_min) ++jn;
+      jt = jn;
+      k_next = ladder(jt);
+    }
     if (accept) {
       cd* old_prev = prev;
       prev = cur;

@@ -65,6 +65,9 @@ struct RowArgs {
   // clears *psd_eval_skip
   int* psd_init_skip;
   int* psd_eval_skip;
+  // ROW_MU launches of a PSD solve: the pass returns at once when the
+  // control block's done code is set (other launches never read it)
+  int check_done;
   // kernel timing (nullable): the earliest workgroup start, in ticks of the
   // device's constant wall clock, is folded in with an atomic minimum
   unsigned long long* tstart;
@@ -98,6 +101,7 @@ struct ColArgs {
   int sav_ncol;
   int rslot;
   unsigned long long* tstart;  // kernel timing (nullable), as in RowArgs
+  int check_done;              // as in RowArgs (the launches of a PSD solve)
 };
 
 struct FinArgs {

@@ -22,6 +22,9 @@ struct fch_plan_s {
   double *rpart, *cpart;
   fch_stats stats;
   int psd_hint;
+  // launches read the control block's done code (PSD solves, and the
+  // device-scalar calls, whose invalid scalars stop every kernel)
+  int check_done;
   // device-controlled adaptive IMEX (fch_run): the run described as one
   // ensemble member, in device memory, with a pinned mirror
   fch::EnsMember* dmem;

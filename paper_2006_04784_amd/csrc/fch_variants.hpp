@@ -22,7 +22,7 @@ struct RowImpl {
   static constexpr int NT = R * (N / E);
   static hipError_t row(int mode, const RowArgs& a, hipStream_t s, hipEvent_t e0,
                         hipEvent_t e1) {
-    const int* done = (mode == ROW_MU) ? &a.ctl->done : nullptr;
+    const int* done = (mode == ROW_MU && a.check_done) ? &a.ctl->done : nullptr;
     const int* nodone = nullptr;
     switch (mode) {
       case ROW_MU:
@@ -86,7 +86,7 @@ struct ColImpl {
 
   template <int EPI, int PRO>
   static hipError_t lc(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const int* done = &a.ctl->done;
+    const int* done = a.check_done ? &a.ctl->done : nullptr;
     FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL>), dim3(N / 2), dim3(CT), s, e0, e1, a, done);
     return hipGetLastError();
   }

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfch.so")
+# FCH_LIB selects another build of the same sources (the host-sanitized one)
+LIB_PATH = os.environ.get("FCH_LIB", os.path.join(HERE, "libfch.so"))
 _lib = None
 
 FCH_OK, FCH_E_INVALID, FCH_E_UNSUPPORTED, FCH_E_HIP, FCH_E_NOMEM, FCH_E_NOCONV, FCH_E_NONFINITE = \
@@ -77,7 +78,7 @@ class fch_run_opts(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("adaptive", C.c_int32), ("startup", C.c_int32),
                 ("nsteps", C.c_int64), ("k", C.c_double), ("k_prev", C.c_double),
                 ("k_first", C.c_double), ("t_end", C.c_double), ("adapt", fch_adapt_opts),
-                ("psd", fch_psd_opts), ("etd", fch_etd_opts)]
+                ("psd", fch_psd_opts), ("etd", fch_etd_opts), ("dyadic", C.c_int32)]
 
 
 class fch_run_info(C.Structure):
@@ -547,13 +548,15 @@ class Plan:
 
     def run(self, uh_n, uh_nm1, scheme="imex", adaptive=False, startup=True, nsteps=0, k=1e-3,
             k_prev=0.0, k_first=0.0, t_end=0.0, adapt: AdaptOpts = None, psd_tol=1e-10,
-            psd_max_iter=1000, psd_lambda=0.0, rs=None, kappa0=ETD_KAPPA0, kappa2=ETD_KAPPA2):
+            psd_max_iter=1000, psd_lambda=0.0, rs=None, kappa0=ETD_KAPPA0, kappa2=ETD_KAPPA2,
+            dyadic=False):
+        """fch_run; dyadic: nested factor-of-two step sizes (adaptive runs)."""
         self._chk_spec(uh_n, uh_nm1)
         sch = {"imex": FCH_IMEX, "sav": FCH_SAV, "psd": FCH_PSD, "etd": FCH_ETD}[scheme]
         o = fch_run_opts(sch, int(adaptive), int(startup), nsteps, k, k_prev, k_first, t_end,
                          (adapt or AdaptOpts()).c(),
                          fch_psd_opts(psd_tol, psd_max_iter, psd_lambda, 0),
-                         fch_etd_opts(kappa0, kappa2))
+                         fch_etd_opts(kappa0, kappa2), int(dyadic))
         r = (C.c_double * 2)(*(rs if rs is not None else (0.0, 0.0)))
         info = fch_run_info()
         self._sync_stream()

@@ -213,3 +213,88 @@ def test_c4_1024_member_replayed_by_oracle(F, orc_mt):
         log("  member %d (N=%d): steps %s, state rel %.3e"
             % (i, mem[j]["N"], ["%.3g" % k for k in klog], e_state))
         assert e_state < 1e-8
+
+
+def dyadic_next(accept, e_next, kt, jt, tu, kb, kmin, kmax, clamped, jmin=-24, jmax=38):
+    """The nested factor-of-two rule: (next ladder index, accepted time in units
+    of kb 2^jmin) from the step law's proposal e_next after an attempt of kt."""
+    lad = lambda j: kb * 2.0 ** j
+    jn = jt
+    if accept and not clamped:
+        tu += 1 << (jt - jmin)
+        if e_next >= 2 * kt and jt < jmax and tu % (1 << (jt + 1 - jmin)) == 0:
+            jn = jt + 1
+        elif e_next < kt:
+            while jn > jmin and lad(jn) > e_next:
+                jn -= 1
+    elif not accept:
+        jn = jt - 1
+        while jn > jmin and lad(jn) > e_next:
+            jn -= 1
+    while jn > jmin and lad(jn) > kmax:
+        jn -= 1
+    while jn < jt and lad(jn) < kmin:
+        jn += 1
+    return jn, tu
+
+
+def test_nested_dyadic_sav_follows_the_oracle_controller(F, orc_mt):
+    """Adaptive SAV with nested factor-of-two steps (fch_run dyadic) on a 128^2
+    circle: the oracle's SAV steps and AM3 estimate driven by the same ladder
+    rule accept the same number of steps, reach the same time and the same
+    state and r; the ladder costs more FFT calls than the plain step law."""
+    orc = orc_mt
+    N, L, T = 128, 2 * np.pi, 0.02
+    kw = dict(N=N, L=L, eps=0.1, eta1=1.45, eta2=2.0, p=1, q=0.0, zeta=1.1, D0=L * L * 1.05)
+    plan = F.Plan(**kw)
+    m = orc.Model(**kw)
+    uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=7))
+    sigma, kmin, kb = 1e-5, 1e-9, 1e-9
+    opts = F.AdaptOpts(sigma_tol=sigma, k_min=kmin)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.reset_stats()
+    info = plan.run(a, b, scheme="sav", adaptive=True, startup=True, t_end=T, k_first=kb,
+                    adapt=opts, nsteps=10 ** 7, dyadic=True)
+    calls_dyadic = plan.stats()["fft_calls"]
+    a2, b2 = dev(uh0), torch.zeros_like(dev(uh0))
+    plan.reset_stats()
+    info2 = plan.run(a2, b2, scheme="sav", adaptive=True, startup=True, t_end=T, k_first=kb,
+                     adapt=opts, nsteps=10 ** 7)
+    calls_plain = plan.stats()["fft_calls"]
+    log("nested dyadic SAV: %d accepted, %d rejected, %d FFT calls; step law: %d accepted, "
+        "%d FFT calls (ratio %.2f)" % (info["accepted"], info["rejected"], calls_dyadic,
+                                       info2["accepted"], calls_plain, calls_dyadic / calls_plain))
+    # the oracle with the same rule
+    r0 = float(np.sqrt(orc.E1(m, uh0) + m.D0))
+    prev = uh0
+    cur, r_cur = orc.sav_step(m, prev, None, r0, r0, kb, -1.0)
+    r_prev = r0
+    Fm, Fn = orc.F(m, prev), orc.F(m, cur)
+    t, kn, jt, tu = kb, kb, 0, 1 << 24
+    acc_n, rej_n = 1, 0
+    while t < T * (1 - 1e-14):
+        kt = kb * 2.0 ** jt
+        clamped = kt > T - t
+        if clamped:
+            kt = T - t
+        trial, r_trial = orc.sav_step(m, cur, prev, r_cur, r_prev, kt, kn)
+        Ft = orc.F(m, trial)
+        e = orc.am3_error(m, trial, cur, Ft, Fn, Fm, kt, kn)
+        ok, knext = orc.adapt_decide(e, kt, sigma, kmin, np.inf)
+        assert abs(e - sigma) / sigma > 1e-9   # outside the tie zone
+        jt, tu = dyadic_next(ok, knext, kt, jt, tu, kb, kmin, np.inf, clamped)
+        if ok:
+            prev, cur, Fm, Fn = cur, trial, Fn, Ft
+            r_prev, r_cur = r_cur, r_trial
+            t, kn = t + kt, kt
+            acc_n += 1
+        else:
+            rej_n += 1
+    e_state = rel(host(a), cur)
+    log("  oracle: %d accepted, %d rejected; state rel %.3e, r rel %.3e"
+        % (acc_n, rej_n, e_state, abs(info["rs"][0] - r_cur) / abs(r_cur)))
+    assert info["accepted"] == acc_n and info["rejected"] == rej_n
+    assert abs(info["t"] - t) < 1e-12
+    assert e_state < 1e-8
+    assert abs(info["rs"][0] - r_cur) < 1e-10 * abs(r_cur)
+    assert calls_dyadic > calls_plain
