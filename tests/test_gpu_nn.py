@@ -184,16 +184,20 @@ def test_training_step_matches_oracle(F, orc, B, H, W):
 def test_learned_warm_start_gain(F):
     """Trained on PSD step pairs of the 256^2 three-bilayer workload, the
     network's guess needs fewer PSD iterations than the extrapolated guess on
-    held-out trajectories, at the same stopping tolerance and to the same
-    solution; the untrained network (zero output layer) is the extrapolation."""
+    two held-out trajectories, by a margin on the mean, at the same stopping
+    tolerance and to the same solution; the untrained network (zero output
+    layer) is the extrapolation."""
     from paper_2006_04784_amd import learned, nn
     plan = F.Plan(**learned.c5_model())
     te = [learned.psd_trajectory(plan, learned.c5_initial(200), 25)]
     net0 = nn.WarmStartNet(256, 256, 8, seed=0)
     ev0 = learned.evaluate(plan, net0, te)
     assert all(r[0] == r[1] for r in ev0["per_step"])
-    ev, net, _ = learned.run_experiment(range(6), [200], nsteps=40, epochs=10, batch=8)
+    ev, net, _ = learned.run_experiment(range(10), [200, 201], nsteps=60, epochs=15, batch=8)
     print({k: v for k, v in ev.items() if k != "per_step"}, flush=True)
     assert ev["loss_last"] < 0.3 * ev["loss_first"]
-    assert ev["iters_learned"] < ev["iters_plain"]
+    # at least half an iteration per step fewer on the mean over both trajectories
+    assert ev["iters_learned"] <= ev["iters_plain"] - 0.5
+    # and fewer FFT calls, counting the transform of the guess
+    assert ev["fft_calls_per_step_learned"] < ev["fft_calls_per_step_plain"]
     assert ev["max_rel_diff_solutions"] < 1e-8

@@ -96,3 +96,11 @@ def test_cost_at_error_interpolation():
                             (1e-7, 800, 1e-4))]
     hit = sweeps.cost_at_error(rows, 5e-3)["sav"]
     assert hit["between_sigma_tol"] == (1e-4, 1e-5) and 100 < hit["fft_calls"] < 200
+    assert hit["cheapest_run"] == {"fft_calls": 200, "sigma_tol": 1e-5}
+    # cost falling down the sweep: the coarsest run reaches the target, a
+    # finer one is cheaper
+    rows = [{"scheme": "psd", "sigma_tol": s, "fft_calls": c, "error": e}
+            for s, c, e in ((1e-3, 900, 1e-4), (1e-4, 500, 5e-5), (1e-5, 700, 1e-5))]
+    hit = sweeps.cost_at_error(rows, 7e-4)["psd"]
+    assert hit["coarsest_run"] and hit["fft_calls"] == 900
+    assert hit["cheapest_run"] == {"fft_calls": 500, "sigma_tol": 1e-4}
