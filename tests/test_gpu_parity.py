@@ -471,7 +471,8 @@ def test_long_trajectory_256_stays_on_oracle(F, orc):
 @pytest.mark.parametrize("N", [16, 64, 256, 512, 1024, 2048])
 def test_every_launch_variant(F, orc, N):
     """Each compiled row-pass and column-pass variant gives the oracle's
-    transforms, IMEX step and ETDRK2 step."""
+    transforms, IMEX step, ETDRK2 step, SAV step (row partial sums) and PSD
+    solve (the row pass's stopping test; the oracle replays the iteration count)."""
     log("launch variants N=%d" % N)
     rows, cols = F.config_list(N)
     L = N * 4 * np.pi / 256
@@ -482,6 +483,9 @@ def test_every_launch_variant(F, orc, N):
     u1 = orc.imex_step(m, uh0, None, 1e-3, -1.0)
     ref = orc.imex_step(m, u1, uh0, 1e-3, 1e-3)
     ref_etd = orc.etd_step(m, u1, 1e-3)
+    r0 = float(np.sqrt(orc.E1(m, uh0) + m.D0))
+    ref_sav, ref_r = orc.sav_step(m, u1, uh0, r0, r0, 1e-3, 1e-3)
+    psd_ref = {}
     for i in range(max(len(rows), len(cols))):
         r, c = rows[i % len(rows)], cols[i % len(cols)]
         plan.set_config((r[0], r[1], r[2], c[0], c[1]))
@@ -495,6 +499,13 @@ def test_every_launch_variant(F, orc, N):
         plan.run(a, b, scheme="imex", nsteps=1, k=1e-3, k_prev=1e-3, startup=False)
         assert rel(host(a), ref) < 1e-10, (r, c)
         assert rel(host(plan.step_etd(dev(u1), 1e-3)), ref_etd) < 1e-10, (r, c)
+        out, r1 = plan.step_sav(dev(u1), dev(uh0), r0, r0, 1e-3, 1e-3)
+        assert rel(host(out), ref_sav) < 1e-10 and abs(r1 - ref_r) < 1e-12 * abs(ref_r), (r, c)
+        out, st = plan.step_psd(dev(u1), dev(uh0), 1e-3, 1e-3, tol=1e-10)
+        it = st["iters"]
+        if it not in psd_ref:
+            psd_ref[it] = orc.psd_step(m, u1, uh0, 1e-3, 1e-3, fixed_iters=it)[0]
+        assert rel(host(out), psd_ref[it]) < 1e-10, (r, c, it)
 
 
 def test_autotune_picks_a_compiled_variant(F, orc):
