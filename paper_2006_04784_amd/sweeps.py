@@ -45,12 +45,13 @@ def critical_d_sweep(ds, sigma_tol=1e-5, t_end=250.0, t0=60.0, threshold=DEFECT_
     threshold) and the wall time.  physical_k, sampling and n0 select a
     reading of the initial data (inputs.paper_initial_data)."""
     ds = [float(d) for d in ds]
-    members, u0s = [], []
-    for d in ds:
-        kw, u0 = inputs.paper_initial_data("critical", N=N, d=d, physical_k=physical_k,
-                                           sampling=sampling, n0=n0)
-        members.append(kw)
-        u0s.append(u0)
+    # d enters eq. dcoef as the constant eps d / alpha_m(0)^2 only: the filtered
+    # strip is built once and shifted per member
+    kw, base = inputs.paper_initial_data("critical", N=N, d=0.0, physical_k=physical_k,
+                                         sampling=sampling, n0=n0)
+    shift = kw["eps"] / inputs.PAPER_ALPHA0 ** 2
+    members = [dict(kw) for _ in ds]
+    u0s = [base + shift * d for d in ds]
     ens = fch.Ensemble(members, adapt=fch.AdaptOpts(sigma_tol=sigma_tol), t_end=t_end,
                        max_steps=max_steps, k_first=1e-9, device=device, umax_t0=t0,
                        scheme=scheme)
