@@ -100,6 +100,28 @@ fch_status fch_plan_set_workspace(fch_plan_t plan, void* dptr, size_t bytes);
  * not compiled. */
 typedef struct { int32_t row_R, row_E, row_twl, col_E, col_twl; } fch_launch_cfg;
 fch_status fch_plan_set_config(fch_plan_t plan, const fch_launch_cfg* cfg);
+/* One-launch PSD solve (Sec. 3.3): the iterations of fch_step_psd and
+ * fch_step_psd_dev run in a single persistent kernel whose workgroups, all
+ * resident at once, alternate the row pass and the column pass with device-
+ * wide barriers and stop on the stopping test evaluated on the device, so a
+ * captured solve is two launches whatever its iteration count or max_iter.
+ * Each barrier costs an agent-scope cache release and acquire per
+ * workgroup, so an iteration takes 1.4-2.2x as long as with separate
+ * launches (256^2: 24 against 16 us; 1024^2: 91 against 42 us): it pays
+ * where a captured solve's max_iter far exceeds its iterations (the separate
+ * launches of a converged solve still cost about 2.4 us each).  Off by
+ * default.  Compiled for N = 256, 512, 1024 and 2048 with one fixed pair of
+ * row and column variants (launch cfg 2,8,0 | 4,0 up to 1024; 2,16,0 | 8,0 at
+ * 2048), independent of fch_plan_set_config; the default grid is one
+ * workgroup per CU (fewer when a phase has fewer tasks).  A barrier that
+ * waits half a second gives up; the solve then returns FCH_E_HIP (status -3
+ * from the _dev call).
+ * set: on = 1 or 0; grid > 0 sets the number of persistent workgroups (at
+ * most what the device holds at once, else FCH_E_INVALID), grid <= 0 the
+ * default; FCH_E_UNSUPPORTED for on = 1 without the solve for N.
+ * get (host out): on, and its grid size (nullable; 0 without it). */
+fch_status fch_plan_set_psd_solve(fch_plan_t plan, int32_t on, int32_t grid);
+fch_status fch_plan_get_psd_solve(fch_plan_t plan, int32_t* on, int32_t* grid);
 fch_status fch_plan_get_config(fch_plan_t plan, fch_launch_cfg* cfg);
 /* Compiled variants for a grid size: row-pass variants (row fields of cfg)
  * and column-pass variants (col fields of cfg). */

@@ -405,6 +405,54 @@ fch_status fch_sav_constants(const fch_params* prm, double* zeta, double* D0) {
   return FCH_OK;
 }
 
+// The one-launch PSD solve needs all of its workgroups resident at once: at
+// most what the occupancy of the kernel allows on this device's CUs, by
+// default one workgroup per CU (or fewer when a phase has fewer tasks: each
+// grid barrier costs one agent-scope release and acquire per workgroup, so
+// fewer, busier workgroups are faster).  It starts switched off; without a
+// compiled pair for N it cannot be switched on.
+static void psd1_setup(fch_plan_s* p) {
+  p->psd1 = nullptr;
+  p->psd1_grid = 0;
+  p->psd1_on = 0;
+  const fch::PsdSolveVT* vt = fch::psd_solve_variant(p->N);
+  if (!vt) return;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, vt->func, vt->threads, 0) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+          hipSuccess ||
+      per_cu < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return;
+  }
+  const int tasks = std::max(p->N / vt->R, p->N / 2);
+  p->psd1 = vt;
+  p->psd1_max_grid = per_cu * cus;
+  p->psd1_def_grid = std::min(cus, tasks);
+  p->psd1_grid = p->psd1_def_grid;
+  p->psd1_on = 0;
+}
+
+// the iterations of a PSD solve after its PRO_PSD_INIT column pass: one
+// k_psd_solve launch (the plan's one-launch pair) or, when that is off or not
+// compiled for N, `limit` row and column passes and the final test
+static fch_status psd_solve_launch(fch_plan_s* p, const ColArgs& a, int limit) {
+  if (!(p->psd1 && p->psd1_on)) {
+    CHK(psd_iterations(p, a, 0, limit));
+    return FCH_OK;
+  }
+  RowArgs ra = row_args(p);
+  ra.check_done = 0;
+  ColArgs ca = a;
+  ca.check_done = 0;
+  ca.partial = p->cpart;
+  prof_break(p);
+  HIPCHK(p->psd1->launch(ra, ca, limit, p->psd1_grid, p->stream));
+  p->stats.launches += 1;
+  return FCH_OK;
+}
+
 fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
   if (!out) return FCH_E_INVALID;
   CHK(validate_params(prm));
@@ -448,6 +496,7 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
     fch_plan_destroy(p);
     return FCH_E_HIP;
   }
+  psd1_setup(p);
   *out = p;
   return FCH_OK;
 }
@@ -617,6 +666,26 @@ fch_status fch_plan_set_config(fch_plan_t p, const fch_launch_cfg* cfg) {
   if (!r || !c) return FCH_E_UNSUPPORTED;
   p->rv = r;
   p->cv = c;
+  return FCH_OK;
+}
+
+fch_status fch_plan_set_psd_solve(fch_plan_t p, int32_t on, int32_t grid) {
+  if (!p || (on != 0 && on != 1)) return FCH_E_INVALID;
+  if (on && !p->psd1) return FCH_E_UNSUPPORTED;
+  if (on && grid > 0) {
+    if (grid > p->psd1_max_grid) return FCH_E_INVALID;
+    p->psd1_grid = grid;
+  } else if (on) {
+    p->psd1_grid = p->psd1_def_grid;
+  }
+  p->psd1_on = on;
+  return FCH_OK;
+}
+
+fch_status fch_plan_get_psd_solve(fch_plan_t p, int32_t* on, int32_t* grid) {
+  if (!p || !on) return FCH_E_INVALID;
+  *on = p->psd1 ? p->psd1_on : 0;
+  if (grid) *grid = p->psd1 ? p->psd1_grid : 0;
   return FCH_OK;
 }
 
@@ -990,16 +1059,22 @@ fch_status fch_step_psd(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
   CHK(col(p, fch::EPI_NONE, fch::PRO_PSD_INIT, a));
   a.partial = p->cpart;
   const int limit = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
-  int queued = 0;
-  int chunk = p->psd_hint > 0 ? p->psd_hint : 4;
-  for (;;) {
-    const int n = (chunk < limit - queued) ? chunk : (limit - queued);
-    CHK(psd_iterations(p, a, queued, n));
-    queued += n;
+  if (p->psd1 && p->psd1_on) {
+    CHK(psd_solve_launch(p, a, limit));
     CHK(readback(p));
-    if (p->hctl->done || queued >= limit) break;
-    chunk = 4;
+  } else {
+    int queued = 0;
+    int chunk = p->psd_hint > 0 ? p->psd_hint : 4;
+    for (;;) {
+      const int n = (chunk < limit - queued) ? chunk : (limit - queued);
+      CHK(psd_iterations(p, a, queued, n));
+      queued += n;
+      CHK(readback(p));
+      if (p->hctl->done || queued >= limit) break;
+      chunk = 4;
+    }
   }
+  if (p->hctl->done == 5) return FCH_E_HIP;
   const int iters = p->hctl->iters;
   p->psd_hint = iters > 0 ? iters : 4;
   p->stats.psd_iters += iters;
@@ -1245,10 +1320,11 @@ fch_status fch_step_psd_dev(fch_plan_t p, const fch_c128* uh_n, const fch_c128* 
   a.aux = p->aux;
   CHK(col(p, fch::EPI_NONE, fch::PRO_PSD_INIT, a));
   a.partial = p->cpart;
-  // every iteration up to the limit is launched; after the device flag is
-  // set (converged, limit, non-finite) the remaining launches return at once
+  // one k_psd_solve launch, or (without it) every iteration up to the limit,
+  // whose launches return at once after the device flag is set (converged,
+  // limit, non-finite)
   const int limit = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
-  CHK(psd_iterations(p, a, 0, limit));
+  CHK(psd_solve_launch(p, a, limit));
   p->stats.steps += 1;
   return ctl_out(p, fch::OUT_PSD, nullptr, iters_dev, status_dev);
 }

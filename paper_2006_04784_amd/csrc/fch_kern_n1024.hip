@@ -5,3 +5,4 @@
 
 FCH_VARIANTS(1024, FCH_LIST(RowImpl<1024, 2, 8, 0>::table(), RowImpl<1024, 4, 16, 1>::table(), RowImpl<1024, 4, 16, 0>::table(), RowImpl<1024, 2, 16, 0>::table(), RowImpl<1024, 4, 8, 0>::table(), RowImpl<1024, 1, 8, 0>::table(), RowImpl<1024, 2, 4, 0>::table(), RowImpl<1024, 8, 16, 0>::table()),
              FCH_LIST(ColImpl<1024, 4, 0>::table(), ColImpl<1024, 4, 1>::table(), ColImpl<1024, 8, 0>::table()))
+FCH_PSD_SOLVE(1024, 2, 8, 0, 4, 0, 2)

@@ -5,3 +5,4 @@
 
 FCH_VARIANTS(2048, FCH_LIST(RowImpl<2048, 2, 8, 0>::table(), RowImpl<2048, 2, 16, 1>::table(), RowImpl<2048, 2, 16, 0>::table(), RowImpl<2048, 1, 16, 0>::table(), RowImpl<2048, 1, 8, 0>::table()),
              FCH_LIST(ColImpl<2048, 8, 0>::table(), ColImpl<2048, 4, 0>::table(), ColImpl<2048, 8, 1>::table()))
+FCH_PSD_SOLVE(2048, 2, 16, 0, 8, 0, 1)

@@ -5,3 +5,4 @@
 
 FCH_VARIANTS(512, FCH_LIST(RowImpl<512, 2, 8, 0>::table(), RowImpl<512, 2, 8, 1>::table(), RowImpl<512, 4, 8, 0>::table(), RowImpl<512, 2, 16, 0>::table(), RowImpl<512, 2, 4, 0>::table(), RowImpl<512, 8, 8, 0>::table()),
              FCH_LIST(ColImpl<512, 4, 0>::table(), ColImpl<512, 4, 1>::table(), ColImpl<512, 8, 0>::table()))
+FCH_PSD_SOLVE(512, 2, 8, 0, 4, 0, 2)

@@ -22,10 +22,12 @@ struct StepCtl {
   double kappa0, kappa2;              // ETDRK2 split constants (eq. ETD-L); step k_np1
   double rring[3];                    // SAV r history of the fused chain, slot n mod 3 = r^n
   int accept, iters, max_iter, fixed_iters;
-  int done;       // PSD: 0 running, 1 converged / fixed count reached, 2 max_iter, 3 non-finite
+  int done;       // PSD: 0 running, 1 converged / fixed count reached, 2 max_iter, 3 non-finite;
+                  // 4 invalid device scalars (every kernel stops); 5 the one-launch
+                  // solve's grid barrier gave up (not every workgroup ran)
   int nonfinite;  // set by any kernel that sees NaN/Inf
   int invalid;    // SAV: E1 + D0 <= 0
-  int pad;
+  unsigned bar;   // arrivals at the one-launch PSD solve's grid barrier (zeroed with the block)
 };
 
 enum RowMode { ROW_MU = 0, ROW_FWD = 1, ROW_INV = 2 };
@@ -199,6 +201,16 @@ struct ColVT {
   // single-field column transforms (dir -1 forward, +1 inverse) over `batch` fields
   hipError_t (*col1_batch)(int dir, const ColArgs& a, int batch, size_t sstride, hipStream_t s);
 };
+
+// One-launch PSD solve of a grid size (k_psd_solve with one fixed pair of
+// row and column variants of equal workgroup size): func is the kernel for
+// occupancy queries; launch runs it on `grid` persistent workgroups.
+struct PsdSolveVT {
+  int N, R, ER, rtwl, EC, ctwl, threads;
+  const void* func;
+  hipError_t (*launch)(const RowArgs& ra, const ColArgs& ca, int limit, int grid, hipStream_t s);
+};
+const PsdSolveVT* psd_solve_variant(int N);  // nullptr: none compiled for N
 
 // registry: the first entry of each list is the default for N
 int row_variant_count(int N);

@@ -182,25 +182,38 @@ __device__ __forceinline__ void fixed_sum2(const double* p, int n, double& s0, d
 // (sum |d|^2, sum |u_{s+1}|^2): every workgroup of the next row pass computes
 // the same verdict; workgroup 0 records it.  Returns the done code in all
 // threads.
+// The stopping test of Sec. 3.3 after `iter` iterations, from the column
+// partial sums (|d|^2, |u|^2 per column): every workgroup forms the same sums
+// in the same order and returns the same code; the recording workgroup
+// (rec) writes the ratio, the count and the code into the control block.
 template <int NT>
-__device__ __forceinline__ int psd_check(const RowArgs& a) {
+__device__ __forceinline__ int psd_verdict(const double* part, int ncol, StepCtl* ctl, int iter,
+                                           bool rec, int* eval_skip) {
   __shared__ int verdict;
   double c0 = 0.0, c1 = 0.0;
-  fixed_sum2<NT>(a.psd_part, a.psd_ncol, c0, c1);
+  fixed_sum2<NT>(part, ncol, c0, c1);
   if (threadIdx.x == 0) {
     const double ratio = sqrt(c0 / c1);
-    const int code = psd_done_code(*a.ctl, ratio, a.psd_iter);
+    const int code = psd_done_code(*ctl, ratio, iter);
     verdict = code;
-    if (blockIdx.x == 0) {
-      a.ctl->ratio = ratio;
-      a.ctl->iters = a.psd_iter;
-      if (code) a.ctl->done = code;
-      if (code == 3) a.ctl->nonfinite = 1;
-      if (code && a.psd_eval_skip) *a.psd_eval_skip = 0;
+    if (rec) {
+      ctl->ratio = ratio;
+      ctl->iters = iter;
+      if (code) ctl->done = code;
+      if (code == 3) ctl->nonfinite = 1;
+      if (code && eval_skip) *eval_skip = 0;
     }
   }
   __syncthreads();
-  return verdict;
+  const int v = verdict;
+  __syncthreads();  // verdict is read before any later test writes it
+  return v;
+}
+
+template <int NT>
+__device__ __forceinline__ int psd_check(const RowArgs& a) {
+  return psd_verdict<NT>(a.psd_part, a.psd_ncol, a.ctl, a.psd_iter, blockIdx.x == 0,
+                         a.psd_eval_skip);
 }
 
 // ===========================================================================
@@ -209,9 +222,12 @@ __device__ __forceinline__ int psd_check(const RowArgs& a) {
 // TWL: twiddle table copied to LDS (1) or read from global memory through
 // the vector caches (0, frees N*16 bytes of LDS per workgroup)
 // UMAX (ROW_MU, ensembles): the workgroup's largest u goes to umax_part[tile]
+// vblk >= 0: the tile of a persistent workgroup (vblk of vgrid tiles) instead
+// of the launch's own block index
 template <int N, int R, int E, int MODE, int TWL, bool UMAX = false>
 __device__ __forceinline__ void row_body(const RowArgs& a, const int* done,
-                                         double* umax_part = nullptr) {
+                                         double* umax_part = nullptr, int vblk = -1,
+                                         int vgrid = 0) {
   constexpr int T = N / E;
   constexpr int NT = R * T;
   constexpr int M = N / 2;
@@ -232,7 +248,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done,
   const int tid = threadIdx.x;
   const int seq = tid / T;
   const int t = tid - seq * T;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = (vblk < 0) ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(vblk, vgrid);
   // ROW_MU: rows y0 .. y0+R-1, one (u, Lap u) pair per row.
   // ROW_FWD/ROW_INV: rows y0 .. y0+2R-1, sequence s pairs rows y0+s, y0+R+s.
   const int y0 = (MODE == ROW_MU) ? tile * R : tile * 2 * R;
@@ -612,8 +628,10 @@ __device__ __forceinline__ cd herm(cd x, cd xr) {
 // so every state it writes is exactly the spectrum of a real field (a
 // non-Hermitian component of these columns would be amplified by the
 // explicit terms of the schemes); the inverse transforms pack the same way.
+// vcol >= 0: the column task of a persistent workgroup instead of the
+// launch's own block index (task 0 is the self-conjugate pair)
 template <int N, int E, int EPI, int PRO, int TWL>
-__device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
+__device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int vcol = -1) {
   constexpr int T = N / E;
   constexpr int M = N / 2;
   __shared__ cd buf[2][lp_size(N)];
@@ -623,7 +641,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
 
   const Consts& c = a.c;
   const int t = threadIdx.x;
-  const int kx = blockIdx.x;
+  const int kx = (vcol < 0) ? (int)blockIdx.x : vcol;
   const bool sc = (kx == 0);  // the self-conjugate pair kx = 0, N/2
   const size_t col = (size_t)kx * N;
   constexpr size_t colM = (size_t)M * N;
@@ -649,7 +667,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
         double sst;
         const int st = sav_sstar(E1, c.D0, sst);
         sh_s = sst;
-        if (blockIdx.x == 0) {
+        if (kx == 0) {
           a.ctl->E1 = E1;
           a.ctl->s_star = sst;
           if (st == 1) a.ctl->nonfinite = 1;
@@ -675,7 +693,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done) {
       const double r = sav_r_solve(*a.ctl, a.ctl->rring[sl], a.ctl->rring[(sl + 2) % 3],
                                    c.pars * c0, c.pars * c1);
       sh_r = r;
-      if (blockIdx.x == 0) {
+      if (kx == 0) {
         a.ctl->rring[(sl + 1) % 3] = r;
         if (!isfinite(r)) a.ctl->nonfinite = 1;
       }
@@ -899,6 +917,94 @@ template <int N, int E, int EPI, int PRO, int TWL>
 __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
   stamp_start(a.tstart);
   col_body<N, E, EPI, PRO, TWL>(a, done);
+}
+
+// ---- one-launch PSD solve (Sec. 3.3) ------------------------------------------
+// Grid barrier of a persistent launch whose G workgroups are all resident at
+// once: thread 0 of each workgroup releases its writes at agent scope, counts
+// its arrival in *bar and polls until `target` arrivals (round r completes at
+// (r + 1) G; *bar is zeroed with the control block).  The wait gives up after
+// half a second of the device's constant clock, which only happens when not
+// every workgroup could run at once; then false.
+__device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned target) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (__builtin_amdgcn_s_memrealtime() - t0 > 50000000ull) {  // 0.5 s at 100 MHz
+        good = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = good;
+  }
+  __syncthreads();
+  const bool r = ok;
+  __syncthreads();  // ok is read before a later barrier writes it
+  return r;
+}
+
+// A whole PSD solve in one launch: G persistent workgroups run the row pass
+// (chemical-potential pieces of the iterate, N/R row tiles) and the column
+// pass (EPI_PSD with the next iterate's prologue, N/2 column tasks) in turn,
+// separated by grid barriers, and before each iteration but the first they
+// all evaluate the stopping test of the iterations done so far from the
+// column partial sums; the solve ends on the test's code (converged, the
+// fixed count, max_iter or non-finite, as psd_done_code decides) or when a
+// barrier gives up (done code 5).  A control block already stopped (invalid
+// device scalars) stops it before any work.  The initial iterate and its column-inverted
+// (u, Lap u) come from a PRO_PSD_INIT column pass launched before; ra and ca
+// are the arguments of the separate passes with no stopping test and no done
+// flag.  The row and column variants must use the same number of threads.
+// The two passes are separate (not inlined) functions, so that each keeps its
+// own register allocation and nothing is held live from one into the other.
+template <int N, int R, int ER, int RTWL>
+__device__ __attribute__((noinline)) void psd_row_task(const RowArgs& ra, int v) {
+  row_body<N, R, ER, ROW_MU, RTWL>(ra, nullptr, nullptr, v, N / R);
+}
+template <int N, int EC, int CTWL>
+__device__ __attribute__((noinline)) void psd_col_task(const ColArgs& ca, int v) {
+  col_body<N, EC, EPI_PSD, PRO_NEXT_FIELD, CTWL>(ca, nullptr, v);
+}
+// WPE: waves per SIMD the launch bound asks for (1 when LDS allows one
+// workgroup per CU anyway)
+template <int N, int R, int ER, int RTWL, int EC, int CTWL, int WPE>
+__global__ __launch_bounds__(N / EC, WPE) void k_psd_solve(RowArgs ra, ColArgs ca, int limit) {
+  constexpr int NT = N / EC;
+  static_assert(R * (N / ER) == NT, "row and column variants of unequal workgroup size");
+  constexpr int NROW = N / R, NCOL = N / 2;
+  const int G = gridDim.x, b = blockIdx.x;
+  StepCtl* ctl = ca.ctl;
+  if (ctl->done) return;
+  unsigned target = 0;
+  for (int it = 0;; ++it) {
+    if (it > 0 && psd_verdict<NT>(ca.partial, NCOL + 1, ctl, it, b == 0, nullptr)) break;
+    if (it >= limit) break;  // not reached: the test stops at the limit
+    for (int v = b; v < NROW; v += G) {
+      psd_row_task<N, R, ER, RTWL>(ra, v);
+      __syncthreads();
+    }
+    target += (unsigned)G;
+    if (!grid_sync(&ctl->bar, target)) {
+      if (threadIdx.x == 0) ctl->done = 5;
+      break;
+    }
+    for (int v = b; v < NCOL; v += G) {
+      psd_col_task<N, EC, CTWL>(ca, v);
+      __syncthreads();
+    }
+    target += (unsigned)G;
+    if (!grid_sync(&ctl->bar, target)) {
+      if (threadIdx.x == 0) ctl->done = 5;
+      break;
+    }
+  }
 }
 
 // ---- batched ensemble entry points (member = blockIdx.y) --------------------

@@ -22,6 +22,12 @@ struct fch_plan_s {
   double *rpart, *cpart;
   fch_stats stats;
   int psd_hint;
+  // one-launch PSD solve (k_psd_solve): the compiled pair for N (nullptr if
+  // none), its grid (every workgroup resident at once) and whether the
+  // fch_step_psd calls use it
+  const fch::PsdSolveVT* psd1;
+  int psd1_grid, psd1_def_grid, psd1_max_grid;
+  int psd1_on;
   // launches read the control block's done code (PSD solves, and the
   // device-scalar calls, whose invalid scalars stop every kernel)
   int check_done;

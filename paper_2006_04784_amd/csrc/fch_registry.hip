@@ -5,7 +5,8 @@ namespace fch {
 
 #define FCH_DECL(N)                                \
   const RowVT* const* row_variants_##N(int* n);    \
-  const ColVT* const* col_variants_##N(int* n);
+  const ColVT* const* col_variants_##N(int* n);    \
+  const PsdSolveVT* psd_solve_##N();
 FCH_DECL(16)
 FCH_DECL(32)
 FCH_DECL(64)
@@ -45,6 +46,16 @@ static const ColVT* const* cols_for(int N, int* n) {
     case 4096: return col_variants_4096(n);
   }
   *n = 0;
+  return nullptr;
+}
+
+const PsdSolveVT* psd_solve_variant(int N) {
+  switch (N) {
+    case 256: return psd_solve_256();
+    case 512: return psd_solve_512();
+    case 1024: return psd_solve_1024();
+    case 2048: return psd_solve_2048();
+  }
   return nullptr;
 }
 

@@ -172,7 +172,33 @@ struct ColImpl {
   }
 };
 
+template <int N, int R, int ER, int RTWL, int EC, int CTWL, int WPE>
+struct PsdSolveImpl {
+  static hipError_t launch(const RowArgs& ra, const ColArgs& ca, int limit, int grid,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_psd_solve<N, R, ER, RTWL, EC, CTWL, WPE>), dim3(grid), dim3(N / EC), 0, s,
+                       ra, ca, limit);
+    return hipGetLastError();
+  }
+  static const PsdSolveVT* table() {
+    static const PsdSolveVT vt = {N,    R,    ER,
+                                  RTWL, EC,   CTWL,
+                                  N / EC, (const void*)&k_psd_solve<N, R, ER, RTWL, EC, CTWL, WPE>,
+                                  &launch};
+    return &vt;
+  }
+};
+
 }  // namespace fch
+
+// The one-launch PSD solve of one grid size:
+//   FCH_PSD_SOLVE(N, R, ER, RTWL, EC, CTWL, waves per SIMD of the launch bound)
+#define FCH_PSD_SOLVE(N, R, ER, RTWL, EC, CTWL, WPE)                  \
+  namespace fch {                                                     \
+  const PsdSolveVT* psd_solve_##N() {                                 \
+    return PsdSolveImpl<N, R, ER, RTWL, EC, CTWL, WPE>::table();      \
+  }                                                                   \
+  }
 
 // Defines the variant lists of one grid size:
 //   FCH_VARIANTS(N, (RowImpl<...>::table(), ...), (ColImpl<...>::table(), ...))

@@ -122,6 +122,8 @@ _SIGS = {
     "fch_plan_set_workspace": (_I, [_V, _V, C.c_size_t]),
     "fch_plan_set_config": (_I, [_V, C.POINTER(fch_launch_cfg)]),
     "fch_plan_get_config": (_I, [_V, C.POINTER(fch_launch_cfg)]),
+    "fch_plan_set_psd_solve": (_I, [_V, _I, _I]),
+    "fch_plan_get_psd_solve": (_I, [_V, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "fch_row_config_count": (_I, [_I]),
     "fch_col_config_count": (_I, [_I]),
     "fch_config_get": (_I, [_I, _I, _I, C.POINTER(fch_launch_cfg)]),
@@ -302,6 +304,17 @@ class Plan:
         """cfg = (row_R, row_E, row_twl, col_E, col_twl), or None for the default."""
         c = None if cfg is None else fch_launch_cfg(*cfg)
         _check(lib().fch_plan_set_config(self.h, None if c is None else C.byref(c)))
+
+    def set_psd_solve(self, on, grid=0):
+        """One-launch PSD solve on (True) or off (separate row and column
+        launches); grid > 0: its number of persistent workgroups."""
+        _check(lib().fch_plan_set_psd_solve(self.h, int(bool(on)), int(grid)))
+
+    def get_psd_solve(self):
+        """(on, grid) of the one-launch PSD solve."""
+        on, grid = C.c_int32(), C.c_int32()
+        _check(lib().fch_plan_get_psd_solve(self.h, C.byref(on), C.byref(grid)))
+        return bool(on.value), grid.value
 
     def get_config(self):
         c = fch_launch_cfg()
