@@ -97,12 +97,16 @@ __host__ __device__ inline double sav_r_solve(const StepCtl& v, double gp, doubl
 // Sec. 3.3 stopping test after `iters` iterations whose last step ratio is
 // ||d|| / ||u_{s+1}||: 0 continue, 1 converged (or the fixed count reached),
 // 2 iteration limit, 3 non-finite
-__host__ __device__ inline int psd_done_code(const StepCtl& v, double ratio, int iters) {
+__host__ __device__ inline int psd_done_code(int fixed_iters, double tol, int max_iter,
+                                             double ratio, int iters) {
   if (!isfinite(ratio)) return 3;
-  if (v.fixed_iters > 0) return iters >= v.fixed_iters ? 1 : 0;
-  if (ratio < v.tol) return 1;
-  if (iters >= v.max_iter) return 2;
+  if (fixed_iters > 0) return iters >= fixed_iters ? 1 : 0;
+  if (ratio < tol) return 1;
+  if (iters >= max_iter) return 2;
   return 0;
+}
+__host__ __device__ inline int psd_done_code(const StepCtl& v, double ratio, int iters) {
+  return psd_done_code(v.fixed_iters, v.tol, v.max_iter, ratio, iters);
 }
 
 // Device-controlled adaptive BDF2-PSD: the solve's control block for the

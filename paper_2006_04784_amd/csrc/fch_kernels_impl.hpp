@@ -131,10 +131,43 @@ __device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, 
 // i = l, l+64, ... each, then a fixed XOR butterfly.  Called by the threads
 // 0..NT-1 of a workgroup; with NT >= 64 the first wavefront computes it,
 // with fewer threads thread 0 reproduces the same additions.  Valid in
-// thread 0.
-template <int NT>
+// thread 0.  NMAX > 0 (a bound on n known at compile time): each lane
+// issues up to 16 of its loads before the first addition, so the sum costs
+// one memory latency per 1024 partials instead of one per 64; the additions
+// and their order are unchanged.
+template <int NT, int NMAX = 0>
 __device__ __forceinline__ void fixed_sum2(const double* p, int n, double& s0, double& s1) {
-  if constexpr (NT >= 64) {
+  if constexpr (NT >= 64 && NMAX > 0) {
+    constexpr int PER = (NMAX + 63) / 64;
+    constexpr int CH = PER < 16 ? PER : 16;
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x;
+      double a = 0.0, b = 0.0;
+      for (int i0 = 0; i0 < n; i0 += 64 * CH) {
+        double xa[CH], xb[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int i = min(i0 + l + 64 * k, n - 1);  // in bounds; unused past n
+          xa[k] = p[2 * i];
+          xb[k] = p[2 * i + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (i0 + l + 64 * k < n) {
+            a += xa[k];
+            b += xb[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+      }
+      s0 = a;
+      s1 = b;
+    }
+  } else if constexpr (NT >= 64) {
     if (threadIdx.x < 64) {
       const int l = threadIdx.x;
       double a = 0.0, b = 0.0;
@@ -186,17 +219,33 @@ __device__ __forceinline__ void fixed_sum2(const double* p, int n, double& s0, d
 // partial sums (|d|^2, |u|^2 per column): every workgroup forms the same sums
 // in the same order and returns the same code; the recording workgroup
 // (rec) writes the ratio, the count and the code into the control block.
-template <int NT>
+// NMAX bounds ncol at compile time (0: none).  done (nullable): the solve's
+// stop flag; when it is already set the test is not taken, nothing is
+// recorded and its code is returned.  iter == 0: there is no previous
+// iteration to test.
+template <int NT, int NMAX = 0>
 __device__ __forceinline__ int psd_verdict(const double* part, int ncol, StepCtl* ctl, int iter,
-                                           bool rec, int* eval_skip) {
+                                           bool rec, int* eval_skip, const int* done = nullptr) {
   __shared__ int verdict;
   double c0 = 0.0, c1 = 0.0;
-  fixed_sum2<NT>(part, ncol, c0, c1);
+  // the stop flag and the control fields are requested before the partial
+  // sums, so all of these loads are in flight together (thread 0 alone
+  // consumes the flag, so no uniform branch waits for it first)
+  int stopped = 0, fixed = 0, maxit = 0;
+  double tol = 0.0;
+  if (threadIdx.x == 0) {
+    stopped = done ? *done : 0;
+    fixed = ctl->fixed_iters;
+    tol = ctl->tol;
+    maxit = ctl->max_iter;
+  }
+  fixed_sum2<NT, NMAX>(part, ncol, c0, c1);
   if (threadIdx.x == 0) {
     const double ratio = sqrt(c0 / c1);
-    const int code = psd_done_code(*ctl, ratio, iter);
+    const int code =
+        stopped ? stopped : (iter > 0 ? psd_done_code(fixed, tol, maxit, ratio, iter) : 0);
     verdict = code;
-    if (rec) {
+    if (rec && !stopped && iter > 0) {
       ctl->ratio = ratio;
       ctl->iters = iter;
       if (code) ctl->done = code;
@@ -210,10 +259,10 @@ __device__ __forceinline__ int psd_verdict(const double* part, int ncol, StepCtl
   return v;
 }
 
-template <int NT>
-__device__ __forceinline__ int psd_check(const RowArgs& a) {
-  return psd_verdict<NT>(a.psd_part, a.psd_ncol, a.ctl, a.psd_iter, blockIdx.x == 0,
-                         a.psd_eval_skip);
+template <int NT, int NMAX>
+__device__ __forceinline__ int psd_check(const RowArgs& a, const int* done) {
+  return psd_verdict<NT, NMAX>(a.psd_part, a.psd_ncol, a.ctl, a.psd_iter, blockIdx.x == 0,
+                               a.psd_eval_skip, done);
 }
 
 // ===========================================================================
@@ -239,10 +288,19 @@ __device__ __forceinline__ void row_body(const RowArgs& a, const int* done,
   __shared__ cd Zs[R * ZS];
   __shared__ cd twl[TWL ? N : 1];
   __shared__ double red[2 * ((NT + 63) / 64)];
-  if (done && *done) return;
   if constexpr (MODE == ROW_MU) {
-    if (a.psd_init_skip && blockIdx.x == 0 && threadIdx.x == 0) *a.psd_init_skip = 1;
-    if (a.psd_part && psd_check<NT>(a)) return;
+    if (a.psd_part) {
+      // the stop flag is read with the stopping test's inputs (its loads all
+      // in flight together), not behind a branch of its own
+      if (a.psd_init_skip && blockIdx.x == 0 && threadIdx.x == 0 && !(done && *done))
+        *a.psd_init_skip = 1;
+      if (psd_check<NT, N / 2 + 1>(a, done)) return;
+    } else {
+      if (done && *done) return;
+      if (a.psd_init_skip && blockIdx.x == 0 && threadIdx.x == 0) *a.psd_init_skip = 1;
+    }
+  } else {
+    if (done && *done) return;
   }
 
   const int tid = threadIdx.x;
@@ -613,6 +671,30 @@ __device__ __forceinline__ cd pro_point(const ColArgs& a, const StepCtl* ctl, si
   }
 }
 
+// Member fields that no kernel changes while it runs (the model constants, the
+// buffer pointers, the slot indices and flags, which only the controller
+// kernel rotates) are read through the constant address space: scalar loads,
+// issued together at the start of every workgroup.  Control blocks and the
+// stage flags, which workgroup 0 of some stages writes, are read directly,
+// except by the column passes, which never write them: there a flag's
+// scalar load joins the others instead of a vector load and a wait of its
+// own.
+template <class T>
+__device__ __forceinline__ T ldc(const T& x) {
+  if constexpr (std::is_scalar<T>::value) {
+    return *(const __attribute__((address_space(4))) T*)(&x);
+  } else {  // a struct of 8-byte words (the model constants)
+    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "struct of 8-byte words");
+    using W = unsigned long long;
+    const __attribute__((address_space(4))) W* p = (const __attribute__((address_space(4))) W*)(&x);
+    T r;
+    W* q = reinterpret_cast<W*>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) q[i] = p[i];
+    return r;
+  }
+}
+
 // Hermitian part of a column of a real field's half spectrum at ky, from its
 // values at ky and N - ky (exactly conjugate at the two points)
 __device__ __forceinline__ cd herm(cd x, cd xr) {
@@ -637,7 +719,21 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
   __shared__ cd buf[2][lp_size(N)];
   __shared__ cd twl[TWL ? N : 1];
   __shared__ double red[2 * ((T + 63) / 64)];
-  if (done && *done) return;
+  // The stop flag (set only by earlier launches) is read as a scalar load.
+  // A pass that writes nothing before its main loads tests it after issuing
+  // them, so the flag's latency and theirs overlap; the others test it first.
+  // Measured: the late test speeds up the E = 4 variants (two or three
+  // workgroups per CU; the fused IMEX pass at 1024^2 by 3%) and slows the
+  // E = 8 ones (one workgroup per CU) by about 2%, and it costs the AM3 pass
+  // a third of its occupancy, so those test first.
+  constexpr bool LATE_STOP = (E <= 4 && EPI != EPI_NONE && EPI != EPI_SAV && EPI != EPI_AM3 &&
+                              PRO != PRO_SAV_NEXT && PRO != PRO_SAV_FIELD);
+  int stopped = 0;
+  if constexpr (LATE_STOP) {
+    stopped = done ? ldc(*done) : 0;
+  } else {
+    if (done && ldc(*done)) return;
+  }
 
   const Consts& c = a.c;
   const int t = threadIdx.x;
@@ -661,7 +757,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
     __shared__ double sh_s;
     if (a.sav_rpart) {
       double r0 = 0.0, r1 = 0.0;
-      fixed_sum2<T>(a.sav_rpart, a.sav_nrow, r0, r1);
+      fixed_sum2<T, N>(a.sav_rpart, a.sav_nrow, r0, r1);  // N / R rows
       if (t == 0) {
         const double E1 = c.h2 * r0;
         double sst;
@@ -687,7 +783,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
   if constexpr (PRO == PRO_SAV_NEXT || PRO == PRO_SAV_FIELD) {
     __shared__ double sh_r;
     double c0 = 0.0, c1 = 0.0;
-    fixed_sum2<T>(a.sav_cpart, a.sav_ncol, c0, c1);
+    fixed_sum2<T, N / 2 + 1>(a.sav_cpart, a.sav_ncol, c0, c1);
     if (t == 0) {
       const int sl = a.rslot;
       const double r = sav_r_solve(*a.ctl, a.ctl->rring[sl], a.ctl->rring[(sl + 2) % 3],
@@ -738,6 +834,17 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
     }
 #pragma unroll
     for (int s = 0; s < E; ++s) load_pre<EPI>(a, col + t + s * T, pre0[s], pre1[s]);
+    if constexpr (LATE_STOP) {
+      if (stopped) {
+        // an empty asm reading the column values: without a use on this
+        // path the compiler would sink their loads behind the test
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int s = 0; s < E; ++s) asm volatile("" ::"v"(v[q][s].x), "v"(v[q][s].y));
+        return;
+      }
+    }
     fft<N, E, 2, -1>(v, base, tw, t);
 
     if (!sc) {
@@ -984,7 +1091,7 @@ __global__ __launch_bounds__(N / EC, WPE) void k_psd_solve(RowArgs ra, ColArgs c
   if (ctl->done) return;
   unsigned target = 0;
   for (int it = 0;; ++it) {
-    if (it > 0 && psd_verdict<NT>(ca.partial, NCOL + 1, ctl, it, b == 0, nullptr)) break;
+    if (it > 0 && psd_verdict<NT, NCOL + 1>(ca.partial, NCOL + 1, ctl, it, b == 0, nullptr)) break;
     if (it >= limit) break;  // not reached: the test stops at the limit
     for (int v = b; v < NROW; v += G) {
       psd_row_task<N, R, ER, RTWL>(ra, v);
@@ -1008,26 +1115,6 @@ __global__ __launch_bounds__(N / EC, WPE) void k_psd_solve(RowArgs ra, ColArgs c
 }
 
 // ---- batched ensemble entry points (member = blockIdx.y) --------------------
-// Member fields that no kernel changes while it runs (the model constants, the
-// buffer pointers, the slot indices and flags, which only the controller
-// kernel rotates) are read through the constant address space: scalar loads,
-// issued together at the start of every workgroup.  Control blocks and the
-// stage flags, which workgroup 0 of some stages writes, are read directly.
-template <class T>
-__device__ __forceinline__ T ldc(const T& x) {
-  if constexpr (std::is_scalar<T>::value) {
-    return *(const __attribute__((address_space(4))) T*)(&x);
-  } else {  // a struct of 8-byte words (the model constants)
-    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "struct of 8-byte words");
-    using W = unsigned long long;
-    const __attribute__((address_space(4))) W* p = (const __attribute__((address_space(4))) W*)(&x);
-    T r;
-    W* q = reinterpret_cast<W*>(&r);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) q[i] = p[i];
-    return r;
-  }
-}
 
 __device__ __forceinline__ void ens_col_args(const EnsMember* m, ColArgs& a) {
   a.c = ldc(m->c);
@@ -1085,7 +1172,7 @@ __global__ __launch_bounds__(R*(N / E)) void k_row_ens(EnsMember* mem, int first
     // stopping test of the previous iteration (none before the first)
     a.ctl = &m->sctl;
     const int it = m->sctl.iters;
-    a.psd_part = (it > 0) ? ldc(m->cpart) : nullptr;
+    a.psd_part = ldc(m->cpart);  // no test before the first iteration (it == 0)
     a.psd_ncol = ldc(m->H);
     a.psd_iter = it;
     a.psd_init_skip = &m->psd_init_skip;
