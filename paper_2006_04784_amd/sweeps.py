@@ -451,26 +451,28 @@ def cost_vs_error(name="super-critical", sigmas=DPD_SIGMAS, schemes=("imex", "sa
 
 
 def psd_iteration_readings(name="foot-1", sigma_tol=1e-5, factors=(1.0, 10.0, 100.0),
-                           device="cuda:0", log=None):
+                           lambdas=(), device="cuda:0", log=None):
     """Total PSD iterations of the adaptive run to the benchmark's final time
     (Table t:Comp-error) for stopping tolerances i_tol = f nu sigma_tol (nu and
     k_max of Table tolPSD): the quantity of Table tolPSD under readings of the
-    tolerance."""
+    tolerance.  Each lambda in `lambdas` adds a run at f = 1 with that fixed
+    step length of eq. recurrence in place of Table SearchSize's."""
     kw, u0 = inputs.paper_initial_data(name)
     q = kw["q"]
     nu, kmax = PSD_SETTINGS[q]
     plan = fch.Plan(**kw, device=device)
     uh0 = plan.forward(torch.from_numpy(np.ascontiguousarray(u0)).to(plan.device))
     out = []
-    for f in factors:
+    for f, lam in [(f, 0.0) for f in factors] + [(1.0, lam) for lam in lambdas]:
         a, b = uh0.clone(), torch.empty_like(uh0)
         plan.reset_stats()
         t1 = time.perf_counter()
-        row = {"benchmark": name, "sigma_tol": sigma_tol, "i_tol": f * nu * sigma_tol}
+        row = {"benchmark": name, "sigma_tol": sigma_tol, "i_tol": f * nu * sigma_tol,
+               "lambda": lam if lam > 0 else "Table SearchSize"}
         try:
             info = plan.run(a, b, scheme="psd", adaptive=True, startup=True, t_end=COMP_T[name],
                             k_first=1e-9, nsteps=5000000, psd_tol=f * nu * sigma_tol,
-                            psd_max_iter=20000,
+                            psd_max_iter=20000, psd_lambda=lam,
                             adapt=fch.AdaptOpts(sigma_tol=sigma_tol, k_max=kmax))
             row.update(psd_iters=int(info["psd_iters"]), accepted=int(info["accepted"]),
                        rejected=int(info["rejected"]))
@@ -528,9 +530,13 @@ if __name__ == "__main__":
     ap.add_argument("--psd-readings", default="",
                     help="PSD iterations to the final time of the named benchmark for i_tol = "
                          "f nu sigma_tol, f = 1, 10, 100, instead")
+    ap.add_argument("--psd-lambdas", default="",
+                    help="fixed PSD step lengths to add to --psd-readings (comma-separated)")
     args = ap.parse_args()
     if args.psd_readings:
+        lams = tuple(float(x) for x in args.psd_lambdas.split(",")) if args.psd_lambdas else ()
         print(json.dumps(psd_iteration_readings(args.psd_readings, sigma_tol=args.sigma,
+                                                lambdas=lams,
                                                 log=lambda m: print(m, file=sys.stderr,
                                                                     flush=True))))
         sys.exit(0)
