@@ -37,6 +37,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def spec_bytes(N):
     return 16 * N * (N // 2 + 1)
 
@@ -49,10 +53,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_class):
-    """HBM bytes per launch from the committed counter summary, if it was
+def read_traffic(kernel_class, summary="pmc_traffic_m1_imex.txt"):
+    """HBM bytes per launch from a committed counter summary, if it was
     taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_m1_imex.txt")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -94,6 +98,73 @@ def prof_kernels(prof, row_bytes, col_bytes, col_name):
             col_name: (col_bytes, cms * 1e-3 / max(cn, 1), cn)}
 
 
+def c3_leg(dev):
+    """c3: 2048^2 adaptive BDF2-PSD, its extra entry and the streaming roofline."""
+    import torch
+
+    from paper_2006_04784_amd import fch, inputs
+    # c3: 2048^2 adaptive BDF2-PSD (i_tol 1e-10, LTE target 1e-6, k_max 0.05), the
+    # first 100 accepted steps after the startup step
+    log("c3: 2048^2 adaptive BDF2-PSD, 100 accepted steps")
+    kw3, u3 = inputs.workload("c3")
+    plan3 = fch.Plan(**kw3, device=dev)
+    a3 = plan3.forward(torch.from_numpy(u3).to(dev))
+    b3 = torch.empty_like(a3)
+    u3d = a3.clone()
+    plan3.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info3 = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
+                      nsteps=101, k_first=1e-6,
+                      adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
+    torch.cuda.synchronize()
+    el3 = time.perf_counter() - t0
+    S3 = spec_bytes(kw3["N"])
+    acc3 = info3["accepted"]
+    launches3 = plan3.stats()["launches"]
+    # the same run with kernel timing on (each row and column pass records
+    # its start on the device clock; attempts then run from the host loop,
+    # one host wait per chunk of PSD iterations and per error estimate)
+    a3.copy_(u3d)
+    plan3.profile(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info3h = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
+                       nsteps=101, k_first=1e-6,
+                       adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
+    torch.cuda.synchronize()
+    el3h = time.perf_counter() - t0
+    prof3 = plan3.profile_read()
+    plan3.profile(False)
+    c3 = {
+        "accepted_steps": acc3, "rejected": info3["rejected"], "t": round(info3["t"], 6),
+        "psd_iters_per_step": round(info3["psd_iters"] / acc3, 2),
+        "psd_fft_calls_per_step": round(4.0 * info3["psd_iters"] / acc3, 2),
+        "total_fft_calls_per_step": round(info3["fft_calls"] / acc3, 2),
+        "ms_per_step": round(1e3 * el3 / acc3, 3),
+        "launches_per_step": round(launches3 / acc3, 2),
+        "control": "device (queued rounds, one host wait per 8 rounds)",
+        "ms_per_step_host_loop_timed": round(1e3 * el3h / info3h["accepted"], 3),
+        "psd_iteration_GBps": round(11 * S3 * info3["psd_iters"] / el3 / 1e9, 1),
+        "bytes_per_psd_iteration": 11 * S3}
+    # streaming roofline: the kernels of the timed rerun (working set: u^n, u^{n-1},
+    # the iterate, b u^n + c u^{n-1}, the pair buffer and three F caches,
+    # 9S = 302 MB, beyond the 256 MB Infinity Cache); row passes of the PSD
+    # iterations and of the error estimate, PSD column passes
+    kern3 = prof_kernels(prof3, 4 * S3, 7 * S3, "col_psd_fused")
+    roofline_streaming = hbm_roofline(
+        kern3, "c3 2048^2 adaptive BDF2-PSD, first 100 accepted steps (40 loops + random "
+               "field, working set 9S = %.0f MB)" % (9 * S3 / 1e6),
+        {"iteration_bytes": 11 * S3,
+         "iteration_frac": round(11 * S3 / (kern3["row_mu"][1] + kern3["col_psd_fused"][1])
+                                 / 1e9 / PEAK_HBM_GBS, 4)},
+        where="the run's rerun with kernel timing on")
+    roofline_streaming["traffic"] = read_traffic(roofline_streaming["kernel"],
+                                                 "pmc_traffic_c3_psd.txt")
+    del plan3, a3, b3
+    return c3, roofline_streaming
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +172,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip SAV/PSD/adaptive/FFT extras")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="of the extras run only the 2048^2 PSD leg (for counter runs)")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="of the extras, run only the two batched ensembles (for profiling)")
     ap.add_argument("--config", type=str, default="",
@@ -110,6 +183,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB copy (counter calibration)")
     args = ap.parse_args()
+    if args.streaming_only:
+        args.no_extra = True  # the 2048^2 PSD leg runs alone
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -126,9 +201,6 @@ def main():
     k = 1e-3
     plan = fch.Plan(**kw, device=dev)
     S = spec_bytes(N)
-
-    def log(msg):
-        print("[bench] " + msg, file=sys.stderr, flush=True)
 
     log("m1 1024^2: forward transform and startup step")
     uh0 = plan.forward(torch.from_numpy(u0).to(dev))
@@ -177,7 +249,10 @@ def main():
 
     extra = {}
     roofline_streaming = None
-    if not args.no_extra and not args.ensemble_only:
+    if args.streaming_only:
+        c3, roofline_streaming = c3_leg(dev)
+        extra["c3_psd_adaptive_2048"] = c3
+    elif not args.no_extra and not args.ensemble_only:
         # SAV, fixed step
         log("SAV fixed step")
         rs = [plan.sav_r(a), 0.0]
@@ -272,63 +347,8 @@ def main():
         extra["psd_iterations_per_s"] = round(info["psd_iters"] / el, 1)
         extra["psd_fft_calls_per_step"] = round(4.0 * info["psd_iters"] / npsd, 2)
         extra["psd_steps_per_s"] = round(npsd / el, 1)
-        # c3: 2048^2 adaptive BDF2-PSD (i_tol 1e-10, LTE target 1e-6, k_max 0.05), the
-        # first 100 accepted steps after the startup step
-        log("c3: 2048^2 adaptive BDF2-PSD, 100 accepted steps")
-        kw3, u3 = inputs.workload("c3")
-        plan3 = fch.Plan(**kw3, device=dev)
-        a3 = plan3.forward(torch.from_numpy(u3).to(dev))
-        b3 = torch.empty_like(a3)
-        u3d = a3.clone()
-        plan3.reset_stats()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info3 = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
-                          nsteps=101, k_first=1e-6,
-                          adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
-        torch.cuda.synchronize()
-        el3 = time.perf_counter() - t0
-        S3 = spec_bytes(kw3["N"])
-        acc3 = info3["accepted"]
-        launches3 = plan3.stats()["launches"]
-        # the same run with kernel timing on (each row and column pass records
-        # its start on the device clock; attempts then run from the host loop,
-        # one host wait per chunk of PSD iterations and per error estimate)
-        a3.copy_(u3d)
-        plan3.profile(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info3h = plan3.run(a3, b3, scheme="psd", adaptive=True, startup=True, t_end=100.0,
-                           nsteps=101, k_first=1e-6,
-                           adapt=fch.AdaptOpts(sigma_tol=1e-6, k_max=0.05), psd_tol=1e-10)
-        torch.cuda.synchronize()
-        el3h = time.perf_counter() - t0
-        prof3 = plan3.profile_read()
-        plan3.profile(False)
-        extra["c3_psd_adaptive_2048"] = {
-            "accepted_steps": acc3, "rejected": info3["rejected"], "t": round(info3["t"], 6),
-            "psd_iters_per_step": round(info3["psd_iters"] / acc3, 2),
-            "psd_fft_calls_per_step": round(4.0 * info3["psd_iters"] / acc3, 2),
-            "total_fft_calls_per_step": round(info3["fft_calls"] / acc3, 2),
-            "ms_per_step": round(1e3 * el3 / acc3, 3),
-            "launches_per_step": round(launches3 / acc3, 2),
-            "control": "device (queued rounds, one host wait per 8 rounds)",
-            "ms_per_step_host_loop_timed": round(1e3 * el3h / info3h["accepted"], 3),
-            "psd_iteration_GBps": round(11 * S3 * info3["psd_iters"] / el3 / 1e9, 1),
-            "bytes_per_psd_iteration": 11 * S3}
-        # streaming roofline: the kernels of the timed rerun (working set: u^n, u^{n-1},
-        # the iterate, b u^n + c u^{n-1}, the pair buffer and three F caches,
-        # 9S = 302 MB, beyond the 256 MB Infinity Cache); row passes of the PSD
-        # iterations and of the error estimate, PSD column passes
-        kern3 = prof_kernels(prof3, 4 * S3, 7 * S3, "col_psd_fused")
-        roofline_streaming = hbm_roofline(
-            kern3, "c3 2048^2 adaptive BDF2-PSD, first 100 accepted steps (40 loops + random "
-                   "field, working set 9S = %.0f MB)" % (9 * S3 / 1e6),
-            {"iteration_bytes": 11 * S3,
-             "iteration_frac": round(11 * S3 / (kern3["row_mu"][1] + kern3["col_psd_fused"][1])
-                                     / 1e9 / PEAK_HBM_GBS, 4)},
-            where="the run's rerun with kernel timing on")
-        del plan3, a3, b3
+        c3, roofline_streaming = c3_leg(dev)
+        extra["c3_psd_adaptive_2048"] = c3
         # 2D FFT bandwidth, streaming regime: R2C then C2R over a 32-field batch
         # (269 MB physical + 269 MB spectral + 269 MB staging, beyond the 256 MB
         # Infinity Cache), batched launches; and one field (cache-resident)
