@@ -888,3 +888,34 @@ def test_largest_grid_4096(F, orc):
     assert rel(host(a), ref) < 1e-10
     e = plan.step_etd(dev(uh0), 1e-3)
     assert rel(host(e), orc.etd_step(m, uh0, 1e-3)) < 1e-10
+
+
+def test_largest_grid_4096_sav_psd(F, orc):
+    """N = 4096: the sums folded into the next kernel span the most partials
+    here (N / R = 4096 row partials, N/2 + 1 = 2049 column partials), so each
+    lane takes them in several rounds of preloaded loads.  A single SAV step,
+    the fused SAV chain (r^{n+1} solved in every workgroup of the column pass)
+    and two PSD iterations (the stopping test's ratio) against the oracle."""
+    log("4096^2: SAV step, SAV chain, PSD iterations")
+    N, L = 4096, 64 * np.pi
+    kw = model_kw(N, L)
+    plan, m = pair(F, orc, **kw)
+    uh0 = orc.r2c(inputs.circle_bilayer(N, L, 0.1, seed=5))
+    k = 1e-3
+    r0 = float(np.sqrt(orc.E1(m, uh0) + m.D0))
+    assert abs(plan.sav_r(dev(uh0)) - r0) < 1e-12 * r0
+    u1, r1 = orc.sav_step(m, uh0, None, r0, r0, k, -1.0)
+    u2, r2 = orc.sav_step(m, u1, uh0, r1, r0, 1.3 * k, k)
+    g2, q2 = plan.step_sav(dev(u1), dev(uh0), r1, r0, 1.3 * k, k)
+    assert rel(host(g2), u2) < 1e-10 and abs(q2 - r2) < 1e-12 * abs(r2)
+    u3, r3 = orc.sav_step(m, u1, uh0, r1, r0, k, k)
+    a, b = dev(uh0), torch.zeros_like(dev(uh0))
+    info = plan.run(a, b, scheme="sav", nsteps=3, k=k)
+    ref3, _ = orc.sav_step(m, u3, u1, r3, r1, k, k)
+    assert rel(host(a), ref3) < 1e-10 and rel(host(b), u3) < 1e-10
+    ref, it, ratio, _ = orc.psd_step(m, u1, uh0, k, k, fixed_iters=2)
+    out, st = plan.step_psd(dev(u1), dev(uh0), k, k, fixed_iters=2)
+    log("  SAV step %.1e, chain %.1e, PSD %.1e, ratio %.3e / %.3e"
+        % (rel(host(g2), u2), rel(host(a), ref3), rel(host(out), ref), st["last_ratio"], ratio))
+    assert st["iters"] == 2 and rel(host(out), ref) < 1e-10
+    assert abs(st["last_ratio"] - ratio) < 1e-6 * ratio
