@@ -711,8 +711,13 @@ __device__ __forceinline__ cd herm(cd x, cd xr) {
 // non-Hermitian component of these columns would be amplified by the
 // explicit terms of the schemes); the inverse transforms pack the same way.
 // vcol >= 0: the column task of a persistent workgroup instead of the
-// launch's own block index (task 0 is the self-conjugate pair)
-template <int N, int E, int EPI, int PRO, int TWL>
+// launch's own block index (task 0 is the self-conjugate pair).
+// PART: 0 every column (N/2 workgroups); 1 the columns kx = 1 .. N/2-1 only
+// (N/2 - 1 workgroups, kx = block index + 1), 2 the self-conjugate pair only
+// (one workgroup).  A launch split into parts 1 and 2 compiles each path
+// alone, so neither holds the other's registers (the pair's path carries both
+// of its columns' state values).
+template <int N, int E, int EPI, int PRO, int TWL, int PART = 0>
 __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int vcol = -1) {
   constexpr int T = N / E;
   constexpr int M = N / 2;
@@ -737,8 +742,9 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
 
   const Consts& c = a.c;
   const int t = threadIdx.x;
-  const int kx = (vcol < 0) ? (int)blockIdx.x : vcol;
-  const bool sc = (kx == 0);  // the self-conjugate pair kx = 0, N/2
+  const int kx = (vcol >= 0) ? vcol : (PART == 1) ? (int)blockIdx.x + 1 : (PART == 2) ? 0
+                                                                                : (int)blockIdx.x;
+  const bool sc = (PART == 2) || (PART == 0 && kx == 0);  // the self-conjugate pair kx = 0, N/2
   const size_t col = (size_t)kx * N;
   constexpr size_t colM = (size_t)M * N;
   const double wgt = sc ? 1.0 : 2.0;  // Parseval weight of the half spectrum
@@ -1020,10 +1026,10 @@ __global__ __launch_bounds__(R*(N / E)) void k_row(RowArgs a, const int* done) {
   row_body<N, R, E, MODE, TWL>(a, done);
 }
 
-template <int N, int E, int EPI, int PRO, int TWL>
+template <int N, int E, int EPI, int PRO, int TWL, int PART = 0>
 __global__ __launch_bounds__(N / E) void k_col(ColArgs a, const int* done) {
-  stamp_start(a.tstart);
-  col_body<N, E, EPI, PRO, TWL>(a, done);
+  if constexpr (PART != 2) stamp_start(a.tstart);
+  col_body<N, E, EPI, PRO, TWL, PART>(a, done);
 }
 
 // ---- one-launch PSD solve (Sec. 3.3) ------------------------------------------
