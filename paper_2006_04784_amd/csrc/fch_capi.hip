@@ -188,7 +188,7 @@ fch_status col(fch_plan_s* p, int epi, int pro, const ColArgs& a) {
   const int r = prof_begin(p, kind);
   ColArgs b = a;
   b.tstart = prof_slot(p, r);
-  HIPCHK(p->cv->col(epi, pro, b, p->stream, nullptr, nullptr));
+  HIPCHK(p->cv->col(epi, pro, b, p->stream, nullptr, nullptr, &p->lane));
   prof_end(p, r);
   p->stats.launches += 1;
   return FCH_OK;
@@ -496,6 +496,13 @@ fch_status fch_plan_create(const fch_params* prm, fch_plan_t* out) {
     fch_plan_destroy(p);
     return FCH_E_HIP;
   }
+  if (p->N >= 4096 &&
+      (hipStreamCreateWithFlags(&p->lane.stream, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&p->lane.fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&p->lane.join, hipEventDisableTiming) != hipSuccess)) {
+    fch_plan_destroy(p);
+    return FCH_E_HIP;
+  }
   psd1_setup(p);
   *out = p;
   return FCH_OK;
@@ -588,6 +595,12 @@ fch_status fch_plan_destroy(fch_plan_t p) {
   }
   if (p->gfork) (void)hipEventDestroy(p->gfork);
   if (p->gjoin) (void)hipEventDestroy(p->gjoin);
+  if (p->lane.stream) {
+    (void)hipStreamSynchronize(p->lane.stream);
+    (void)hipStreamDestroy(p->lane.stream);
+  }
+  if (p->lane.fork) (void)hipEventDestroy(p->lane.fork);
+  if (p->lane.join) (void)hipEventDestroy(p->lane.join);
   if (p->prof_ev) {
     for (int i = 0; i < 2 * kProfCap; ++i) (void)hipEventDestroy(p->prof_ev[i]);
     delete[] p->prof_ev;
@@ -749,7 +762,7 @@ fch_status fch_autotune(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
       a.s0 = cur;
       a.s1 = prev;
       a.tstart = slots;
-      if (p->cv->col(fch::EPI_NONE, fch::PRO_EXTRAP, a, p->stream, nullptr, nullptr) !=
+      if (p->cv->col(fch::EPI_NONE, fch::PRO_EXTRAP, a, p->stream, nullptr, nullptr, &p->lane) !=
               hipSuccess ||
           hipEventRecord(ev[0], p->stream) != hipSuccess) {
         st = FCH_E_HIP;
@@ -764,7 +777,7 @@ fch_status fch_autotune(fch_plan_t p, const fch_c128* uh_n, const fch_c128* uh_n
         a.tstart = slots + 2 + 2 * s;
         if (p->rv->row(fch::ROW_MU, r, p->stream, nullptr, nullptr) != hipSuccess ||
             p->cv->col(fch::EPI_IMEX, s + 1 < K ? fch::PRO_NEXT_EXTRAP : fch::PRO_NONE, a,
-                       p->stream, nullptr, nullptr) != hipSuccess)
+                       p->stream, nullptr, nullptr, &p->lane) != hipSuccess)
           st = FCH_E_HIP;
         std::swap(cur, prev);
       }

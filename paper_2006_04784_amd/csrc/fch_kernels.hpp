@@ -191,10 +191,21 @@ struct RowVT {
   hipError_t (*row_batch)(int mode, const RowArgs& a, int batch, size_t pstride, size_t sstride,
                           hipStream_t s);
 };
+// A plan's second stream and two events.  A fused column pass split into its
+// columns kx >= 1 and the self-conjugate pair launches the pair on this stream,
+// beside the other launch: forked after the work before it, joined before the
+// work after it (both are captured into a graph when the plan's stream is).
+struct SideLane {
+  hipStream_t stream;
+  hipEvent_t fork, join;
+};
+
 struct ColVT {
   int N, E, twl, threads;
+  // side (nullable): the plan's side lane for the split passes (without it
+  // their two launches run one after the other)
   hipError_t (*col)(int epi, int pro, const ColArgs& a, hipStream_t s, hipEvent_t e0,
-                    hipEvent_t e1);
+                    hipEvent_t e1, const SideLane* side);
   hipError_t (*col_fwd1)(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   hipError_t (*col_inv1)(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   hipError_t (*col_ens)(int stage, EnsMember* m, int first, int count, hipStream_t s);

@@ -12,6 +12,7 @@ struct fch_plan_s {
   const fch::RowVT* rv;
   const fch::ColVT* cv;
   hipStream_t stream;
+  fch::SideLane lane;  // the split column passes' side stream (N >= 4096; else null)
   int device;
   fch::cd* tw;
   fch::StepCtl* ctl;

@@ -83,23 +83,40 @@ template <int N, int E, int TWL>
 struct ColImpl {
   static constexpr int CT = N / E;
   static constexpr int H = N / 2 + 1;
-  // At N = 4096 the fused IMEX, ETDRK2 and PSD passes run as two launches,
-  // the columns kx >= 1 and then the self-conjugate pair, so that neither
-  // path holds the other's registers: one kernel with both spilled up to
-  // 1.1 KB per lane to scratch.  The pair's launch runs alone after the
-  // others; measured, the split gains 10% per IMEX and ETDRK2 step and 6% per
-  // PSD iteration, and costs the SAV step 7%, whose passes stay whole.
+  // At N = 4096 the fused passes (those with an epilogue) run as two
+  // launches, the columns kx >= 1 and the self-conjugate pair, so that neither
+  // path holds the other's registers: compiled as one kernel, the pair's path
+  // (both of its columns' state values) sets the register count of every
+  // workgroup and spilled up to 1.1 KB per lane to scratch.  The pair's single
+  // workgroup runs on the plan's side stream beside the others.  (At 2048 the
+  // split measured slower: the others fill every CU first, and the pair's
+  // workgroup, started late, outlasts them.)
   template <int EPI>
-  static constexpr bool SPLIT =
-      (N >= 4096 && (EPI == EPI_IMEX || EPI == EPI_PSD || EPI == EPI_ETD1 || EPI == EPI_ETD2));
+  static constexpr bool SPLIT = (N >= 4096 && EPI != EPI_NONE);
+  static constexpr int EP = E;  // elements per thread of the pair's launch
 
   template <int EPI, int PRO>
-  static hipError_t lc(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  static hipError_t lc(const ColArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                       const SideLane* side) {
     const int* done = a.check_done ? &a.ctl->done : nullptr;
     if constexpr (SPLIT<EPI>) {
+      hipError_t err;
+      if (side && side->stream) {
+        if ((err = hipEventRecord(side->fork, s)) != hipSuccess) return err;
+        if ((err = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess) return err;
+        hipLaunchKernelGGL((k_col<N, EP, EPI, PRO, TWL, 2>), dim3(1), dim3(N / EP), 0,
+                           side->stream, a, done);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if ((err = hipEventRecord(side->join, side->stream)) != hipSuccess) return err;
+        FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL, 1>), dim3(N / 2 - 1), dim3(CT), s, e0, e1, a,
+                   done);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        return hipStreamWaitEvent(s, side->join, 0);
+      }
       FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL, 1>), dim3(N / 2 - 1), dim3(CT), s, e0, nullptr, a,
                  done);
-      FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL, 2>), dim3(1), dim3(CT), s, nullptr, e1, a, done);
+      FCH_LAUNCH((k_col<N, EP, EPI, PRO, TWL, 2>), dim3(1), dim3(N / EP), s, nullptr, e1, a,
+                 done);
     } else {
       FCH_LAUNCH((k_col<N, E, EPI, PRO, TWL>), dim3(N / 2), dim3(CT), s, e0, e1, a, done);
     }
@@ -107,9 +124,9 @@ struct ColImpl {
   }
 
   static hipError_t col(int epi, int pro, const ColArgs& a, hipStream_t s, hipEvent_t e0,
-                        hipEvent_t e1) {
+                        hipEvent_t e1, const SideLane* side) {
 #define FCH_COL(E_, P_) \
-  if (epi == E_ && pro == P_) return lc<E_, P_>(a, s, e0, e1);
+  if (epi == E_ && pro == P_) return lc<E_, P_>(a, s, e0, e1, side);
     FCH_COL(EPI_NONE, PRO_FIELD)
     FCH_COL(EPI_NONE, PRO_EXTRAP)
     FCH_COL(EPI_NONE, PRO_PSD_INIT)

@@ -620,6 +620,47 @@ def test_dev_steps_in_a_captured_graph(F, orc):
         assert int(st.item()) == 0
 
 
+def test_split_column_passes_captured_and_aliased(F, orc):
+    """At 4096^2 the fused column passes run as two launches, the pair of
+    self-conjugate columns on the plan's side stream (forked from and joined
+    back to the plan's stream).  Captured into a graph with torch's capture of
+    that stream, two device-scalar IMEX steps replay bit for bit like the eager
+    steps; an aliased output (u^{n+1} over u^{n-1}) equals the plain call."""
+    log("4096^2: split column passes under graph capture, aliasing")
+    N, L = 4096, 64 * np.pi
+    plan = F.Plan(**model_kw(N, L))
+    k = 1e-3
+    a0 = plan.forward(torch.from_numpy(inputs.circle_bilayer(N, L, 0.1, seed=5)).cuda())
+    u1 = plan.step_imex(a0, None, k, -1.0)
+    ref = plan.step_imex(u1, a0, 1.3 * k, k)
+    b = a0.clone()
+    plan.step_imex(u1, b, 1.3 * k, k, out=b)
+    assert torch.equal(b, ref)
+    x_nm1, x_n = a0.clone(), u1.clone()
+    y1, y2 = plan.spec(), plan.spec()
+    kd1 = torch.tensor([k, k], dtype=torch.float64, device="cuda")
+    kd2 = torch.tensor([k, k], dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.step_imex_dev(x_n, x_nm1, kd1, y1, st)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.step_imex_dev(x_n, x_nm1, kd1, y1, st)
+        plan.step_imex_dev(y1, x_n, kd2, y2, st)
+    for rep, (um, un, k1, k0, k2) in enumerate([(a0, u1, 1.3 * k, k, 0.8 * k),
+                                                (u1, ref, k, 1.3 * k, 2.0 * k)]):
+        x_nm1.copy_(um)
+        x_n.copy_(un)
+        kd1.copy_(torch.tensor([k1, k0], dtype=torch.float64))
+        kd2.copy_(torch.tensor([k2, k1], dtype=torch.float64))
+        g.replay()
+        torch.cuda.synchronize()
+        e1 = plan.step_imex(un, um, k1, k0)
+        e2 = plan.step_imex(e1, un, k2, k1)
+        assert torch.equal(y1, e1) and torch.equal(y2, e2), rep
+        assert int(st.item()) == 0
+
+
 def test_output_aliasing_u_nm1_is_exact(F, orc):
     """IMEX, SAV and PSD with uh_np1 == uh_nm1 equal the non-aliased call bit
     for bit: every value a column workgroup reads (including the mirrored
