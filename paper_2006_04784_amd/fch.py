@@ -9,6 +9,8 @@ CPU implementation: a missing library raises.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
 import os
 from dataclasses import dataclass
 
@@ -214,6 +216,33 @@ def sav_constants(prm: fch_params):
     return z.value, d.value
 
 
+_LIB_DIGEST = None
+
+
+def tune_key(N, device="cuda:0"):
+    """Key of a tuned launch choice: the GPU's architecture, the grid size and
+    a digest of the library (a rebuilt library tunes again)."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        h = hashlib.sha256()
+        with open(LIB_PATH, "rb") as fh:
+            for chunk in iter(lambda: fh.read(1 << 20), b""):
+                h.update(chunk)
+        _LIB_DIGEST = h.hexdigest()[:16]
+    props = torch.cuda.get_device_properties(torch.device(device))
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return "%s|N=%d|lib=%s" % (arch, int(N), _LIB_DIGEST)
+
+
+def _tune_cache_read(path):
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
 def config_list(N: int):
     """Compiled (row variants, column variants) of a grid size: row variants
     as (R, E, twl), column variants as (E, twl)."""
@@ -321,16 +350,34 @@ class Plan:
         _check(lib().fch_plan_get_config(self.h, C.byref(c)))
         return (c.row_R, c.row_E, c.row_twl, c.col_E, c.col_twl)
 
-    def autotune(self, uh_n, uh_nm1, k=1e-3, reps=20):
+    def autotune(self, uh_n, uh_nm1, k=1e-3, reps=20, cache=None):
         """Pick the fastest compiled row/column variants on the fused IMEX step;
-        returns (config, (row_us, col_us))."""
+        returns (config, (row_us, col_us)).  cache: path of a JSON file of
+        earlier choices keyed by GPU architecture, N and the library's
+        contents; a hit sets that choice without timing, a miss tunes and adds
+        it (the file is replaced whole, so a reader never sees half of it)."""
         self._chk_spec(uh_n, uh_nm1)
+        key = tune_key(self.N, self.device) if cache else None
+        if key:
+            hit = _tune_cache_read(cache).get(key)
+            if hit:
+                cfg = tuple(int(x) for x in hit["config"])
+                self.set_config(cfg)
+                return cfg, tuple(hit["us"])
         c = fch_launch_cfg()
         us = (C.c_double * 2)()
         self._sync_stream()
         _check(lib().fch_autotune(self.h, _p(uh_n), _p(uh_nm1), k, reps, C.byref(c),
                                   C.cast(us, _PD)))
-        return (c.row_R, c.row_E, c.row_twl, c.col_E, c.col_twl), (us[0], us[1])
+        cfg = (c.row_R, c.row_E, c.row_twl, c.col_E, c.col_twl)
+        if key:
+            d = _tune_cache_read(cache)
+            d[key] = {"config": list(cfg), "us": [us[0], us[1]]}
+            tmp = "%s.tmp%d" % (cache, os.getpid())
+            with open(tmp, "w") as fh:
+                json.dump(d, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return cfg, (us[0], us[1])
 
     def stats(self):
         s = fch_stats()

@@ -140,3 +140,16 @@ def test_every_entry_point_rejects_null_arguments(fch):
             assert r == fch.FCH_E_INVALID, (name, r)
         checked += 1
     assert checked > 50
+
+
+def test_tune_cache_reader_tolerates_bad_files(fch, tmp_path):
+    """The launch-choice cache reads as empty when missing, unparsable or not
+    a mapping, and returns the stored entries otherwise."""
+    p = tmp_path / "tune.json"
+    assert fch._tune_cache_read(str(p)) == {}
+    p.write_text("{broken")
+    assert fch._tune_cache_read(str(p)) == {}
+    p.write_text("[1, 2]")
+    assert fch._tune_cache_read(str(p)) == {}
+    p.write_text('{"gfx950|N=256|lib=x": {"config": [4, 8, 0, 4, 0], "us": [1.0, 2.0]}}')
+    assert fch._tune_cache_read(str(p))["gfx950|N=256|lib=x"]["config"] == [4, 8, 0, 4, 0]

@@ -3,6 +3,7 @@ inputs.  Tolerances (relative L2 unless stated): transforms 1e-13, chemical
 potential 1e-12, one step 1e-10, fixed-step trajectories 1e-8, SAV scalar
 1e-12.  Spectra cross the boundary in the library's kx-major layout; the
 tests transpose to the oracle's numpy layout."""
+import json
 import os
 import sys
 
@@ -522,6 +523,37 @@ def test_autotune_picks_a_compiled_variant(F, orc):
     assert torch.equal(a, a0) and torch.equal(b, b0)     # inputs untouched
     out = plan.step_imex(a, b, 1e-3, 1e-3)
     assert rel(host(out), orc.imex_step(m, u1, uh0, 1e-3, 1e-3)) < 1e-10
+
+
+def test_autotune_cache(F, orc, tmp_path):
+    """A tuned choice is kept in a JSON cache keyed by architecture, N and the
+    library: a second plan takes it from the file without timing (the plan's
+    configuration is set, the file unchanged); another N adds an entry; an
+    unreadable file counts as empty."""
+    log("autotune cache")
+    cache = str(tmp_path / "tune.json")
+    N, L = 256, 4 * np.pi
+    plan = F.Plan(**model_kw(N, L))
+    a = plan.forward(torch.from_numpy(inputs.circle_bilayer(N, L, 0.1, seed=0)).cuda())
+    b = a.clone()
+    cfg, us = plan.autotune(a, b, reps=2, cache=cache)
+    key = F.tune_key(N)
+    d = json.load(open(cache))
+    assert d[key]["config"] == list(cfg)
+    mtime = os.path.getmtime(cache)
+    plan2 = F.Plan(**model_kw(N, L))
+    plan2.set_config(None)
+    cfg2, us2 = plan2.autotune(a, b, reps=2, cache=cache)
+    assert cfg2 == cfg and tuple(us2) == tuple(us) and plan2.get_config() == cfg
+    assert os.path.getmtime(cache) == mtime
+    plan3 = F.Plan(**model_kw(128, 2 * np.pi))
+    a3 = plan3.forward(torch.from_numpy(inputs.circle_bilayer(128, 2 * np.pi, 0.1, seed=0)).cuda())
+    plan3.autotune(a3, a3.clone(), reps=2, cache=cache)
+    assert set(json.load(open(cache))) == {key, F.tune_key(128)}
+    with open(cache, "w") as fh:
+        fh.write("{not json")
+    cfg4, _ = plan2.autotune(a, b, reps=2, cache=cache)
+    assert list(json.load(open(cache))) == [key]
 
 
 # ---- device-scalar (graph-capturable) steps ---------------------------------
