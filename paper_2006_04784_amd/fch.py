@@ -14,6 +14,7 @@ import json
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -606,6 +607,15 @@ class Plan:
                                       _p(status_dev)))
         return out
 
+    def resume(self, uh_n, uh_nm1, meta, **kw):
+        """Continues a run saved by save_checkpoint (load_checkpoint's meta):
+        fch_run without the startup step, from its next trial step, its last
+        accepted step and (SAV) its r values; kw as for run (adaptive,
+        nsteps, t_end, adapt, ...).  The info's t counts from the resume."""
+        args = dict(k=meta["k_next"], k_prev=meta["k_last"], rs=tuple(meta["rs"]))
+        args.update(kw)
+        return self.run(uh_n, uh_nm1, scheme=meta["scheme"], startup=False, **args)
+
     def run(self, uh_n, uh_nm1, scheme="imex", adaptive=False, startup=True, nsteps=0, k=1e-3,
             k_prev=0.0, k_first=0.0, t_end=0.0, adapt: AdaptOpts = None, psd_tol=1e-10,
             psd_max_iter=1000, psd_lambda=0.0, rs=None, kappa0=ETD_KAPPA0, kappa2=ETD_KAPPA2,
@@ -625,6 +635,26 @@ class Plan:
         d = {k_: getattr(info, k_) for k_, _ in fch_run_info._fields_}
         d["rs"] = (r[0], r[1])
         return d
+
+
+def save_checkpoint(path, uh_n, uh_nm1, info, scheme, t=0.0):
+    """Writes what a run of `scheme` needs to continue where fch_run left it
+    (info: its returned dict): u^n and u^{n-1} (half spectra), the last
+    accepted and the next trial step, SAV's r^n and r^{n-1}, and the elapsed
+    time t, as one .npz holding only arrays (readable without unpickling)."""
+    meta = {"scheme": scheme, "k_last": float(info["k_last"]), "k_next": float(info["k_next"]),
+            "rs": [float(x) for x in info.get("rs", (0.0, 0.0))], "t": float(t)}
+    np.savez(path, uh_n=uh_n.detach().cpu().numpy(), uh_nm1=uh_nm1.detach().cpu().numpy(),
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load_checkpoint(path, device="cuda:0"):
+    """(u^n, u^{n-1}, meta) of save_checkpoint, the spectra on `device`."""
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(bytes(z["meta"]).decode())
+        dev = torch.device(device)
+        return (torch.from_numpy(z["uh_n"]).to(dev), torch.from_numpy(z["uh_nm1"]).to(dev),
+                meta)
 
 
 class Ensemble:
