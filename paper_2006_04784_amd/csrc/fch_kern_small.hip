@@ -117,29 +117,9 @@ __device__ __forceinline__ void ens_finish(EnsMember* m) {
   m->sctl.done = 4;
 }
 
-__global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) {
-  __shared__ double red[256];
-  EnsMember* m = mem + first + blockIdx.x;
-  if (m->ctl.done) return;
-  if (m->psd && m->psd_eval_skip) return;  // the PSD solve of the attempt still runs
-  const double c0 = sum_strided(m->cpart, m->H, 2, 0, red);
-  const double c1 = sum_strided(m->cpart, m->H, 2, 1, red);
-  // largest u of the trial state: one value per workgroup of the trial
-  // evaluation's row pass (the other slots hold -inf); the slots are reset
-  double um = -INFINITY;
-  for (int i = threadIdx.x; i < m->c.N; i += 256) {
-    um = fmax(um, m->umaxpart[i]);
-    m->umaxpart[i] = -INFINITY;
-  }
-  __syncthreads();
-  red[threadIdx.x] = um;
-  __syncthreads();
-  for (int off = 128; off >= 1; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  um = red[0];
+// The controller's decisions, on the workgroup's copy of the member block m
+// (thread 0): from the AM3 sums c0, c1 and the trial's largest u.
+__device__ void ens_decide(EnsMember* m, double c0, double c1, double um) {
   StepCtl& ctl = m->ctl;
   if (m->psd) {
     // the solve stopped: converged (1), at max_iter (2) or non-finite (3)
@@ -192,6 +172,53 @@ __global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) 
     ctl.invalid = 1;
     ens_finish(m);
   }
+}
+
+// The member block is copied into LDS with one round of coalesced loads, the
+// decisions run on that copy (each field read then costs LDS latency, not a
+// dependent global load), and the block is written back whole: no other
+// launch touches the member while its controller runs (a member's stages run
+// in order on its class's stream).
+__global__ __launch_bounds__(256) void k_ens_control(EnsMember* mem, int first) {
+  __shared__ double red[2 * 4];
+  constexpr int NWORD = sizeof(EnsMember) / 8;
+  static_assert(sizeof(EnsMember) % 8 == 0 && alignof(EnsMember) >= 8, "8-byte words");
+  __shared__ unsigned long long words[NWORD];
+  EnsMember* gm = mem + first + blockIdx.x;
+  unsigned long long* gw = reinterpret_cast<unsigned long long*>(gm);
+  for (int i = threadIdx.x; i < NWORD; i += 256) words[i] = gw[i];
+  __syncthreads();
+  EnsMember* m = reinterpret_cast<EnsMember*>(words);
+  if (m->ctl.done) return;
+  if (m->psd && m->psd_eval_skip) return;  // the PSD solve of the attempt still runs
+  // the AM3 sums: both columns of the partials in one pass, each in the
+  // order of the single-column sum (per thread i = tid, tid + 256, ...,
+  // then the fixed block reduction)
+  double acc[2] = {0.0, 0.0};
+  const double* cp = m->cpart;
+  for (int i = threadIdx.x; i < m->H; i += 256) {
+    acc[0] += cp[2 * (size_t)i];
+    acc[1] += cp[2 * (size_t)i + 1];
+  }
+  __shared__ double sums[2];
+  block_reduce<256, 2>(acc, red, sums);
+  // largest u of the trial state: one value per workgroup of the trial
+  // evaluation's row pass (the other slots hold -inf); the slots are reset
+  double um = -INFINITY;
+  for (int i = threadIdx.x; i < m->c.N; i += 256) {
+    um = fmax(um, m->umaxpart[i]);
+    m->umaxpart[i] = -INFINITY;
+  }
+  __shared__ double umx[256];
+  umx[threadIdx.x] = um;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (threadIdx.x < off) umx[threadIdx.x] = fmax(umx[threadIdx.x], umx[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ens_decide(m, sums[0], sums[1], umx[0]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < NWORD; i += 256) gw[i] = words[i];
 }
 
 hipError_t launch_ens_control(EnsMember* m, int first, int count, hipStream_t s) {
