@@ -211,6 +211,14 @@ fch_status fch_inverse_batch(fch_plan_t plan, int32_t batch, const fch_c128* uh,
  * - (eps^2 eta1/2) ||grad u||^2 with the gradient term by Parseval. */
 fch_status fch_chem_potential(fch_plan_t plan, const fch_c128* uh, fch_c128* muh,
                               double* energy);
+/* The same evaluation with every output in device memory and nothing read
+ * back (graph-capturable): muh as above; mu_phys (nullable, device, N x N
+ * doubles, row-major, overlapping neither uh nor muh): mu on the grid, the
+ * inverse transform of muh; energy_dev (nullable, device double): the energy
+ * above; status_dev (nullable, device int32): 0, or -6 when a non-finite
+ * value appeared.  FCH_E_INVALID for null or overlapping arrays. */
+fch_status fch_chem_potential_dev(fch_plan_t plan, const fch_c128* uh, fch_c128* muh,
+                                  double* mu_phys, double* energy_dev, int32_t* status_dev);
 
 /* ---- BDF2 steps (eqs. BDF2Coef, BDF2-general) ---------------------------- */
 /* Every step solves a u^{n+1} + b u^n + c u^{n-1} = (scheme's Lap mu) with

@@ -949,6 +949,31 @@ fch_status fch_chem_potential(fch_plan_t p, const fch_c128* uh, fch_c128* muh, d
   return FCH_OK;
 }
 
+fch_status fch_chem_potential_dev(fch_plan_t p, const fch_c128* uh, fch_c128* muh,
+                                  double* mu_phys, double* energy_dev, int32_t* status_dev) {
+  if (!p || !uh || !muh || (const void*)uh == (const void*)muh) return FCH_E_INVALID;
+  const void* mp = mu_phys;
+  if (mp && (mp == (const void*)uh || mp == (const void*)muh)) return FCH_E_INVALID;
+  CHK(need_ws(p));
+  CHK(ctl_set(p, ctl_zero()));
+  ColArgs a = col_args(p);
+  a.s0 = (const cd*)uh;
+  CHK(col(p, fch::EPI_NONE, fch::PRO_FIELD, a));
+  CHK(row_mu(p, p->rpart));
+  a.out = (cd*)muh;
+  a.partial = p->cpart;
+  CHK(col(p, fch::EPI_MU, fch::PRO_NONE, a));
+  p->stats.fft_calls += 4;
+  if (energy_dev || status_dev) {
+    CHK(finalize(p, fch::FIN_ENERGY, true, true));
+    HIPCHK(fch::launch_ctl_out(p->ctl, fch::OUT_ENERGY, energy_dev, nullptr, status_dev,
+                               p->stream));
+    p->stats.launches += 1;
+  }
+  if (mu_phys) CHK(fch_inverse(p, muh, (double*)mu_phys));
+  return FCH_OK;
+}
+
 fch_status fch_rhs(fch_plan_t p, const fch_c128* uh, fch_c128* Fh) {
   if (!p || !uh || !Fh || (const void*)uh == (const void*)Fh) return FCH_E_INVALID;
   CHK(need_ws(p));

@@ -255,7 +255,8 @@ __global__ void k_ctl_dev(StepCtl* ctl, StepCtl v, const double* k_dev, const do
 }
 
 // Scalar results and status of the last step, written to caller memory:
-// SAV r^{n+1}; PSD iterations; adaptivity (accept, k_next, err).  status:
+// SAV r^{n+1}; PSD iterations; adaptivity (accept, k_next, err); the
+// finalized energy of a chemical-potential evaluation.  status:
 // 0 ok, -1 invalid scalars, -3 the one-launch PSD solve gave up at a grid
 // barrier, -5 PSD not converged, -6 non-finite values.
 __global__ void k_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_out, int* status) {
@@ -270,6 +271,7 @@ __global__ void k_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_ou
   else if (what == OUT_PSD && c.done == 5)
     st = -3;  // the one-launch solve's grid barrier gave up
   if (what == OUT_SAV && d_out) d_out[0] = c.r_np1;
+  if (what == OUT_ENERGY && d_out) d_out[0] = c.energy;
   if (what == OUT_PSD && i_out) i_out[0] = c.iters;
   if (what == OUT_ADAPT && d_out) {
     d_out[0] = c.accept ? 1.0 : 0.0;

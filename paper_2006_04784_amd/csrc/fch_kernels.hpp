@@ -232,7 +232,7 @@ const ColVT* col_variant(int N, int i);
 hipError_t launch_ctl_set(StepCtl* ctl, const StepCtl& v, hipStream_t s);
 // device-scalar steps: flags of k_ctl_dev, result kinds of k_ctl_out
 enum CtlFlags { CTL_AM3 = 1, CTL_SAV = 2, CTL_LAMBDA = 4, CTL_K1_ONLY = 8 };
-enum CtlOut { OUT_STATUS = 0, OUT_SAV = 1, OUT_PSD = 2, OUT_ADAPT = 3 };
+enum CtlOut { OUT_STATUS = 0, OUT_SAV = 1, OUT_PSD = 2, OUT_ADAPT = 3, OUT_ENERGY = 4 };
 hipError_t launch_ctl_dev(StepCtl* ctl, const StepCtl& v, const double* k_dev,
                           const double* r_dev, double q, int flags, hipStream_t s);
 hipError_t launch_ctl_out(const StepCtl* ctl, int what, double* d_out, int* i_out, int* status,

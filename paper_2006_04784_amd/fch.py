@@ -146,6 +146,7 @@ _SIGS = {
     "fch_forward": (_I, [_V, _V, _V]),
     "fch_inverse": (_I, [_V, _V, _V]),
     "fch_chem_potential": (_I, [_V, _V, _V, _PD]),
+    "fch_chem_potential_dev": (_I, [_V, _V, _V, _V, _V, _V]),
     "fch_step_imex": (_I, [_V, _V, _V, _D, _D, _V]),
     "fch_step_imex_static": (_I, [_V, _V, _V, _D, _D, _V]),
     "fch_step_etd": (_I, [_V, _V, _V, _D, C.POINTER(fch_etd_opts), _V]),
@@ -465,6 +466,25 @@ class Plan:
         self._sync_stream()
         _check(lib().fch_chem_potential(self.h, _p(uh), _p(out), C.byref(e) if energy else None))
         return (out, e.value) if energy else out
+
+    def chem_potential_dev(self, uh, out=None, mu_phys=None, energy_dev=None, status_dev=None):
+        """fch_chem_potential_dev: mu's half spectrum, and optionally mu on the
+        grid (float64 (N, N)), the energy (float64 (1,)) and a status (int32
+        (1,)), all in device memory."""
+        self._chk_spec(uh)
+        out = self.spec() if out is None else out
+        if mu_phys is not None and (mu_phys.dtype != torch.float64 or
+                                    tuple(mu_phys.shape) != (self.N, self.N) or
+                                    not mu_phys.is_contiguous() or mu_phys.device != self.device):
+            raise ValueError("mu_phys: contiguous float64 (N, N)")
+        if energy_dev is not None:
+            self._chk_dev(energy_dev, 1, torch.float64)
+        if status_dev is not None:
+            self._chk_dev(status_dev, 1, torch.int32)
+        self._sync_stream()
+        _check(lib().fch_chem_potential_dev(self.h, _p(uh), _p(out), _p(mu_phys),
+                                            _p(energy_dev), _p(status_dev)))
+        return out
 
     def rhs(self, uh, out=None):
         self._chk_spec(uh)

@@ -116,6 +116,42 @@ def test_chem_potential_and_energy(F, orc, N, q):
     assert rel(host(Fh), orc.F(m, uh)) < 1e-11
 
 
+def test_chem_potential_dev(F, orc):
+    """fch_chem_potential_dev gives fch_chem_potential's spectrum and energy bit
+    for bit, mu on the grid equal to the inverse transform of that spectrum
+    (and to the oracle's mu to 1e-12), and the same again when captured into a
+    graph and replayed on a new state."""
+    log("chem potential, device outputs")
+    N = 128
+    kw = model_kw(N, N * 4 * np.pi / 256, q=0.2)
+    plan, m = pair(F, orc, **kw)
+    uh = orc.r2c(inputs.circle_bilayer(N, kw["L"], kw["eps"], seed=1))
+    uh2 = orc.r2c(inputs.circle_bilayer(N, kw["L"], kw["eps"], seed=2))
+    x = dev(uh)
+    mu_ref, E_ref = plan.chem_potential(x, energy=True)
+    mud, mphys = plan.spec(), torch.empty((N, N), dtype=torch.float64, device="cuda")
+    e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    plan.chem_potential_dev(x, mud, mphys, e, st)
+    torch.cuda.synchronize()
+    assert torch.equal(mud, mu_ref) and float(e.item()) == E_ref and int(st.item()) == 0
+    assert torch.equal(mphys, plan.inverse(mud))
+    ref_phys = orc.c2r(orc.mu(m, uh))
+    assert rel(mphys.cpu().numpy(), ref_phys) < 1e-12
+    with pytest.raises(F.FchError):
+        plan.chem_potential_dev(x, x)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.chem_potential_dev(x, mud, mphys, e, st)
+    x.copy_(dev(uh2))
+    e.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    mu2, E2 = plan.chem_potential(dev(uh2), energy=True)
+    assert torch.equal(mud, mu2) and float(e.item()) == E2
+    assert torch.equal(mphys, plan.inverse(mu2))
+
+
 # ---- IMEX -------------------------------------------------------------------
 def _c1(orc, F):
     kw, u0 = inputs.workload("c1")
