@@ -16,10 +16,12 @@ The same JSON line carries:
                   WRITE_SIZE summary when it was taken on the current kernel
                   source;
   roofline_streaming -- the same for the 2048^2 adaptive PSD run (working set
-                  beyond the 256 MB Infinity Cache);
+                  beyond the 256 MB Infinity Cache), traffic from its own
+                  counter summary (--streaming-only runs that leg alone);
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
-  extra        -- SAV steps/s, adaptive IMEX accepted steps/s, PSD iterations/s
-                  and FFT calls per PSD step, 2D FFT GB/s on a 32-field batch.
+  extra        -- SAV, ETDRK2 and adaptive steps/s, PSD iterations/s and FFT
+                  calls per PSD step, 2D FFT GB/s on a 32-field batch, the
+                  critical-d sweep, the ensembles and the learned warm start.
 """
 from __future__ import annotations
 
