@@ -664,8 +664,9 @@ def save_checkpoint(path, uh_n, uh_nm1, info, scheme, t=0.0):
     time t, as one .npz holding only arrays (readable without unpickling)."""
     meta = {"scheme": scheme, "k_last": float(info["k_last"]), "k_next": float(info["k_next"]),
             "rs": [float(x) for x in info.get("rs", (0.0, 0.0))], "t": float(t)}
-    np.savez(path, uh_n=uh_n.detach().cpu().numpy(), uh_nm1=uh_nm1.detach().cpu().numpy(),
-             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+    with open(path, "wb") as fh:  # (a path given to savez would gain a .npz suffix)
+        np.savez(fh, uh_n=uh_n.detach().cpu().numpy(), uh_nm1=uh_nm1.detach().cpu().numpy(),
+                 meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
 
 
 def load_checkpoint(path, device="cuda:0"):

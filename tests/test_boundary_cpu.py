@@ -153,3 +153,19 @@ def test_tune_cache_reader_tolerates_bad_files(fch, tmp_path):
     assert fch._tune_cache_read(str(p)) == {}
     p.write_text('{"gfx950|N=256|lib=x": {"config": [4, 8, 0, 4, 0], "us": [1.0, 2.0]}}')
     assert fch._tune_cache_read(str(p))["gfx950|N=256|lib=x"]["config"] == [4, 8, 0, 4, 0]
+
+
+def test_checkpoint_file_round_trip(fch, tmp_path):
+    """save_checkpoint writes exactly the path it is given (no suffix added) and
+    load_checkpoint returns the spectra and scalars unchanged."""
+    import torch
+    a = torch.randn(5, 8, dtype=torch.complex128)
+    b = torch.randn(5, 8, dtype=torch.complex128)
+    info = {"k_last": 1e-3, "k_next": 1.25e-3, "rs": (3.5, 3.25)}
+    path = str(tmp_path / "ckpt")
+    fch.save_checkpoint(path, a, b, info, "sav", t=0.125)
+    assert os.path.exists(path) and not os.path.exists(path + ".npz")
+    x, y, meta = fch.load_checkpoint(path, device="cpu")
+    assert torch.equal(x, a) and torch.equal(y, b)
+    assert meta == {"scheme": "sav", "k_last": 1e-3, "k_next": 1.25e-3, "rs": [3.5, 3.25],
+                    "t": 0.125}
