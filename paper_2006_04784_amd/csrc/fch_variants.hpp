@@ -90,7 +90,9 @@ struct ColImpl {
   // workgroup and spilled up to 1.1 KB per lane to scratch.  The pair's single
   // workgroup runs on the plan's side stream beside the others.  (At 2048 the
   // split measured slower: the others fill every CU first, and the pair's
-  // workgroup, started late, outlasts them.)
+  // workgroup, started late, outlasts them.  Holding both launches to two
+  // waves per SIMD, so that the pair shares a CU, made the pair spill and
+  // was slower still.)
   template <int EPI>
   static constexpr bool SPLIT = (N >= 4096 && EPI != EPI_NONE);
   static constexpr int EP = E;  // elements per thread of the pair's launch
