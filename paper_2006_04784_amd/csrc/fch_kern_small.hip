@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   if (a.cpart) {
     if (a.mode == FIN_PSD) {
       // the same summation as the stopping test folded into the row pass
-      fixed_sum2<256, 4096 / 2 + 1>(a.cpart, a.ncol, c0, c1);
+      fixed_sum2<256, 4096 / 2 + 1, 32>(a.cpart, a.ncol, c0, c1);
     } else {
       c0 = sum_strided(a.cpart, a.ncol, 2, 0, red);
       c1 = sum_strided(a.cpart, a.ncol, 2, 1, red);
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_sav_combine(cd* out, const cd* q, StepC
                                                      const double* cpart, int ncol, double pars) {
   __shared__ double rs;
   double c0 = 0.0, c1 = 0.0;
-  fixed_sum2<256, 4096 / 2 + 1>(cpart, ncol, c0, c1);
+  fixed_sum2<256, 4096 / 2 + 1, 32>(cpart, ncol, c0, c1);
   if (threadIdx.x == 0) {
     const double r = sav_r_solve(*ctl, pars * c0, pars * c1);
     rs = r;

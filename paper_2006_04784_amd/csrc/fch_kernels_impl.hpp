@@ -132,14 +132,14 @@ __device__ __forceinline__ void block_reduce(const double (&v)[K], double* red, 
 // 0..NT-1 of a workgroup; with NT >= 64 the first wavefront computes it,
 // with fewer threads thread 0 reproduces the same additions.  Valid in
 // thread 0.  NMAX > 0 (a bound on n known at compile time): each lane
-// issues up to 16 of its loads before the first addition, so the sum costs
-// one memory latency per 1024 partials instead of one per 64; the additions
-// and their order are unchanged.
-template <int NT, int NMAX = 0>
+// issues up to CHMAX of its loads before the first addition, so the sum
+// costs one memory latency per 64 CHMAX partials instead of one per 64; the
+// additions and their order are unchanged.
+template <int NT, int NMAX = 0, int CHMAX = 16>
 __device__ __forceinline__ void fixed_sum2(const double* p, int n, double& s0, double& s1) {
   if constexpr (NT >= 64 && NMAX > 0) {
     constexpr int PER = (NMAX + 63) / 64;
-    constexpr int CH = PER < 16 ? PER : 16;
+    constexpr int CH = PER < CHMAX ? PER : CHMAX;
     if (threadIdx.x < 64) {
       const int l = threadIdx.x;
       double a = 0.0, b = 0.0;
@@ -239,7 +239,10 @@ __device__ __forceinline__ int psd_verdict(const double* part, int ncol, StepCtl
     tol = ctl->tol;
     maxit = ctl->max_iter;
   }
-  fixed_sum2<NT, NMAX>(part, ncol, c0, c1);
+  // (up to 32 loads per lane in flight: the 2049 column partials of 4096^2
+  // in two rounds, those of 2048^2 in one; this sits at the head of the row
+  // pass, where few other values are live)
+  fixed_sum2<NT, NMAX, 32>(part, ncol, c0, c1);
   if (threadIdx.x == 0) {
     const double ratio = sqrt(c0 / c1);
     const int code =
@@ -763,7 +766,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
     __shared__ double sh_s;
     if (a.sav_rpart) {
       double r0 = 0.0, r1 = 0.0;
-      fixed_sum2<T, N>(a.sav_rpart, a.sav_nrow, r0, r1);  // N / R rows
+      fixed_sum2<T, N, 32>(a.sav_rpart, a.sav_nrow, r0, r1);  // N / R rows
       if (t == 0) {
         const double E1 = c.h2 * r0;
         double sst;
@@ -789,7 +792,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, const int* done, int 
   if constexpr (PRO == PRO_SAV_NEXT || PRO == PRO_SAV_FIELD) {
     __shared__ double sh_r;
     double c0 = 0.0, c1 = 0.0;
-    fixed_sum2<T, N / 2 + 1>(a.sav_cpart, a.sav_ncol, c0, c1);
+    fixed_sum2<T, N / 2 + 1, 32>(a.sav_cpart, a.sav_ncol, c0, c1);
     if (t == 0) {
       const int sl = a.rslot;
       const double r = sav_r_solve(*a.ctl, a.ctl->rring[sl], a.ctl->rring[(sl + 2) % 3],
