@@ -14,7 +14,7 @@ The same JSON line carries:
                   the next launch's start in the back-to-back chain), against
                   8 TB/s; traffic from the committed rocprofv3 FETCH_SIZE /
                   WRITE_SIZE summary when it was taken on the current kernel
-                  source;
+                  source and on the variant the run timed;
   roofline_streaming -- the same for the 2048^2 adaptive PSD run (working set
                   beyond the 256 MB Infinity Cache), traffic from its own
                   counter summary (--streaming-only runs that leg alone);
@@ -55,18 +55,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_class, summary="pmc_traffic_m1_imex.txt"):
+def row_kernel_name(N, cfg):
+    """Name of the row pass (chemical-potential mode) of launch config cfg =
+    (row R, row E, row twl, col E, col twl), as rocprofv3 reports it."""
+    return "fch::k_row<%d, %d, %d, 0, %d>" % (N, cfg[0], cfg[1], cfg[2])
+
+
+def read_traffic(kernel_class, summary="pmc_traffic_m1_imex.txt", kernel=None):
     """HBM bytes per launch from a committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source and, when `kernel` is given, on that
+    kernel (else None)."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
-        m = re.match(r"\s*([a-z_0-9]+)\s*:\s*(\S+)", line)
+        m = re.match(r"\s*([a-z_0-9]+)\s*:\s*(.+?)\s*$", line)
         if m:
             kv[m.group(1)] = m.group(2)
     if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if kernel is not None and kv.get("%s_kernel" % kernel_class) != kernel:
         return None
     key = "%s_bytes_per_launch" % kernel_class
     return float(kv[key]) if key in kv else None
@@ -161,8 +170,10 @@ def c3_leg(dev):
          "iteration_frac": round(11 * S3 / (kern3["row_mu"][1] + kern3["col_psd_fused"][1])
                                  / 1e9 / PEAK_HBM_GBS, 4)},
         where="the run's rerun with kernel timing on")
-    roofline_streaming["traffic"] = read_traffic(roofline_streaming["kernel"],
-                                                 "pmc_traffic_c3_psd.txt")
+    roofline_streaming["traffic"] = read_traffic(
+        roofline_streaming["kernel"], "pmc_traffic_c3_psd.txt",
+        row_kernel_name(kw3["N"], plan3.get_config())
+        if roofline_streaming["kernel"] == "row_mu" else None)
     del plan3, a3, b3
     return c3, roofline_streaming
 
@@ -247,7 +258,9 @@ def main():
         "step_us_events": round(ev0.elapsed_time(ev1) * 1e3 / args.steps, 3),
         "step_GBps": round(11 * S * steps_per_s / 1e9, 1),
         "step_frac": round(11 * S * steps_per_s / 1e9 / PEAK_HBM_GBS, 4)})
-    roofline["traffic"] = read_traffic(roofline["kernel"])
+    roofline["traffic"] = read_traffic(
+        roofline["kernel"], kernel=row_kernel_name(N, plan.get_config())
+        if roofline["kernel"] == "row_mu" else None)
 
     extra = {}
     roofline_streaming = None

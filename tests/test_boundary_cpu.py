@@ -169,3 +169,36 @@ def test_checkpoint_file_round_trip(fch, tmp_path):
     assert torch.equal(x, a) and torch.equal(y, b)
     assert meta == {"scheme": "sav", "k_last": 1e-3, "k_next": 1.25e-3, "rs": [3.5, 3.25],
                     "t": 0.125}
+
+
+def test_bench_traffic_summaries_name_their_kernels():
+    """The committed counter summaries record the kernel each figure was
+    taken on, and the bench takes a figure only for that kernel and only on
+    the kernel source the counters saw."""
+    import importlib.util
+    import sys
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    argv, sys.argv = sys.argv, ["bench.py"]
+    try:
+        spec.loader.exec_module(bench)
+    finally:
+        sys.argv = argv
+    for summary, N in (("pmc_traffic_m1_imex.txt", 1024), ("pmc_traffic_c3_psd.txt", 2048)):
+        kv = {}
+        for line in open(os.path.join(ROOT, "profiles", summary)):
+            m = re.match(r"\s*([a-z_0-9]+)\s*:\s*(.+?)\s*$", line)
+            if m:
+                kv[m.group(1)] = m.group(2)
+        name = kv["row_mu_kernel"]
+        m = re.fullmatch(r"fch::k_row<(\d+), (\d+), (\d+), 0, (\d)>", name)
+        assert m and int(m.group(1)) == N, name
+        cfg = (int(m.group(2)), int(m.group(3)), int(m.group(4)), 4, 0)
+        assert bench.row_kernel_name(N, cfg) == name
+        other = (cfg[0], cfg[1], 1 - cfg[2], 4, 0)
+        assert bench.read_traffic("row_mu", summary, bench.row_kernel_name(N, other)) is None
+        got = bench.read_traffic("row_mu", summary, name)
+        if kv["kernel_source_sha256"] == bench.kernel_source_hash():
+            assert got == float(kv["row_mu_bytes_per_launch"])
+        else:
+            assert got is None
