@@ -21,7 +21,9 @@ The same JSON line carries:
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload;
   extra        -- SAV, ETDRK2 and adaptive steps/s, PSD iterations/s and FFT
                   calls per PSD step, 2D FFT GB/s on a 32-field batch, the
-                  critical-d sweep, the ensembles and the learned warm start.
+                  critical-d sweep, the ensembles and the learned warm start
+                  (trained in the run at reduced scale, and from stored
+                  full-scale parameters on full-length held-out runs).
 """
 from __future__ import annotations
 
@@ -490,6 +492,18 @@ def main():
             "configuration trains on 40 seeds x 500 steps (about 20k pairs)")
         extra["learned_warm_start"]["fft_calls_note"] = (
             "learned: 4 per PSD iteration plus the forward transform of the guess")
+        # the same comparison at the workload's full scale: stored parameters
+        # trained on about 20k pairs, held-out trajectories of 500 accepted steps
+        log("learned PSD warm start, full scale (stored parameters, held-out 500-step runs)")
+        evf = learned.evaluate_pretrained(learned.WEIGHTS_C5, [900, 901], nsteps=500,
+                                          device=dev)
+        evf.pop("per_step")
+        extra["learned_warm_start_full_scale"] = {
+            k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in evf.items()}
+        extra["learned_warm_start_full_scale"]["scale"] = (
+            "full: parameters trained on 40 seeds x 500 accepted steps (19960 pairs, 10 "
+            "epochs; python -m paper_2006_04784_amd.learned --train-full), evaluated on "
+            "held-out seeds 900 and 901, 500 accepted steps each")
     if args.copy_probe:
         # a plain elementwise copy of known size: 256 MiB read, 256 MiB written
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

@@ -7,6 +7,7 @@ run in the library's kernels.
 """
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -177,3 +178,55 @@ def run_experiment(train_seeds, test_seeds, nsteps=60, epochs=20, batch=16, lr=1
     ev.update({"train_pairs": len(make_pairs(tr)), "epochs": epochs, "loss_first": losses[0],
                "loss_last": losses[-1], "gen_s": round(t_gen, 2), "train_s": round(t_train, 2)})
     return ev, net, plan
+
+
+# parameters trained at the full scale of the warm-start workload (40 seeds x
+# 500 accepted steps, 10 epochs), written by `python -m
+# paper_2006_04784_amd.learned --train-full <path>`
+WEIGHTS_C5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                          "warm_start_c5_full.npz")
+
+
+def evaluate_pretrained(weights, test_seeds, nsteps=500, tol=1e-10, log=None, device="cuda:0"):
+    """Held-out comparison with stored parameters: generates the test
+    trajectories (full length), then replays every step plainly and from the
+    learned guess (evaluate)."""
+    kw = c5_model()
+    plan = fch.Plan(**kw, device=device)
+    net = WarmStartNet(kw["N"], kw["N"], 1, seed=0, device=device)
+    net.load_params(weights)
+    t0 = time.perf_counter()
+    te = []
+    for s in test_seeds:
+        te.append(psd_trajectory(plan, c5_initial(s), nsteps, tol=tol))
+        if log:
+            log("trajectory seed %d: %d steps to t = %.3f" % (s, te[-1][0].shape[0] - 1,
+                                                              float(te[-1][1].sum())))
+    t_gen = time.perf_counter() - t0
+    ev = evaluate(plan, net, te, tol=tol)
+    ev.update({"gen_s": round(t_gen, 2), "weights": os.path.basename(weights)})
+    return ev
+
+
+def _main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="learned PSD warm start at 256^2")
+    ap.add_argument("--train-full", metavar="PATH",
+                    help="generate 40 x 500-step training trajectories, train 10 epochs and "
+                         "write the parameters to PATH")
+    ap.add_argument("--seeds", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=10)
+    args = ap.parse_args(argv)
+    if args.train_full:
+        def log(m):
+            print(m, flush=True)
+        ev, net, _ = run_experiment(range(args.seeds), [900, 901], nsteps=args.steps,
+                                    epochs=args.epochs, log=log)
+        net.save_params(args.train_full)
+        ev.pop("per_step")
+        print({k: v for k, v in ev.items()}, flush=True)
+
+
+if __name__ == "__main__":
+    _main()

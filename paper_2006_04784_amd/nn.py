@@ -96,6 +96,25 @@ class WarmStartNet:
             out.append((a[:9 * cout * CH].reshape(9, cout, CH), a[9 * cout * CH:].copy()))
         return out
 
+    def save_params(self, path):
+        """Writes the FP32 master parameters and the layer widths to an .npz
+        file (plain arrays, no pickles) at exactly `path`."""
+        with open(path, "wb") as fh:
+            np.savez(fh, params=self.P.cpu().numpy(), layers=np.array(LAYERS, dtype=np.int64),
+                     ch=np.int64(CH), in_ch=np.int64(IN_CH))
+
+    def load_params(self, path):
+        """Reads parameters written by save_params (same architecture)."""
+        with np.load(path, allow_pickle=False) as z:
+            if (tuple(int(c) for c in z["layers"]) != tuple(LAYERS) or int(z["ch"]) != CH
+                    or int(z["in_ch"]) != IN_CH):
+                raise ValueError("%s: parameters of another architecture" % path)
+            p = np.asarray(z["params"])
+        if p.dtype != np.float32 or p.shape != (self.nparam,) or not np.isfinite(p).all():
+            raise ValueError("%s: expected %d finite float32 parameters" % (path, self.nparam))
+        self.P.copy_(torch.from_numpy(p))
+        _chk(fch.lib().fch_nn_to_bf16(self.nparam, _p(self.P), _p(self.PB), None))
+
     def get_grads(self):
         flat = self.G.cpu().numpy().astype(np.float64)
         out = []

@@ -202,3 +202,19 @@ def test_bench_traffic_summaries_name_their_kernels():
             assert got == float(kv["row_mu_bytes_per_launch"])
         else:
             assert got is None
+
+
+def test_stored_warm_start_parameters():
+    """The stored full-scale parameters of the learned warm start match the
+    network's architecture and load without unpickling anything."""
+    from paper_2006_04784_amd import nn
+    path = os.path.join(ROOT, "paper_2006_04784_amd", "data", "warm_start_c5_full.npz")
+    with np.load(path, allow_pickle=False) as z:
+        assert tuple(int(c) for c in z["layers"]) == tuple(nn.LAYERS)
+        assert int(z["ch"]) == nn.CH and int(z["in_ch"]) == nn.IN_CH
+        p = np.asarray(z["params"])
+    n = sum(9 * c * nn.CH + c for c in nn.LAYERS)
+    assert p.dtype == np.float32 and p.shape == (n,) and np.isfinite(p).all()
+    # unused input channels of the first layer stay zero through training
+    w0 = p[:9 * nn.LAYERS[0] * nn.CH].reshape(9, nn.LAYERS[0], nn.CH)
+    assert not w0[:, :, nn.IN_CH:].any() and w0[:, :, :nn.IN_CH].any()

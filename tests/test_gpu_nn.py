@@ -201,3 +201,36 @@ def test_learned_warm_start_gain(F):
     # and fewer FFT calls, counting the transform of the guess
     assert ev["fft_calls_per_step_learned"] < ev["fft_calls_per_step_plain"]
     assert ev["max_rel_diff_solutions"] < 1e-8
+
+
+def test_stored_parameters_round_trip_and_evaluate(F, tmp_path):
+    """save_params / load_params reproduce a trained network's parameters and
+    guess bit for bit; the stored full-scale parameters drive the held-out
+    comparison to the same solutions as the plain solver."""
+    from paper_2006_04784_amd import learned, nn
+    plan = F.Plan(**learned.c5_model())
+    S, ks = learned.psd_trajectory(plan, learned.c5_initial(202), 6)
+    net = nn.WarmStartNet(256, 256, 1, seed=0)
+    net.load_params(learned.WEIGHTS_C5)
+    path = str(tmp_path / "w")   # no suffix: written at exactly this path
+    net.save_params(path)
+    net2 = nn.WarmStartNet(256, 256, 1, seed=3)
+    net2.load_params(path)
+    assert torch.equal(net.P, net2.P) and torch.equal(net.PB, net2.PB)
+    k = torch.tensor([[ks[3], ks[2]]], dtype=torch.float64, device="cuda")
+    g1 = net.guess(S[2:3].contiguous(), S[1:2].contiguous(), k).clone()
+    g2 = net2.guess(S[2:3].contiguous(), S[1:2].contiguous(), k)
+    assert torch.equal(g1, g2)
+    ev = learned.evaluate(plan, net, [(S, ks)])
+    print({k_: v for k_, v in ev.items() if k_ != "per_step"}, flush=True)
+    assert ev["steps"] == 5 and ev["max_rel_diff_solutions"] < 1e-8
+    with pytest.raises(ValueError):   # another architecture's file
+        nn.WarmStartNet(256, 256, 1).load_params(_bad_params(tmp_path))
+
+
+def _bad_params(tmp_path):
+    p = str(tmp_path / "bad.npz")
+    with open(p, "wb") as fh:
+        np.savez(fh, params=np.zeros(7, np.float32), layers=np.array([32]), ch=np.int64(32),
+                 in_ch=np.int64(3))
+    return p
