@@ -211,13 +211,10 @@ __device__ __forceinline__ void fixed_sum2(const double* p, int n, double& s0, d
   }
 }
 
-// Stopping test of a PSD iteration (Sec. 3.3) from its column partial sums
-// (sum |d|^2, sum |u_{s+1}|^2): every workgroup of the next row pass computes
-// the same verdict; workgroup 0 records it.  Returns the done code in all
-// threads.
-// The stopping test of Sec. 3.3 after `iter` iterations, from the column
-// partial sums (|d|^2, |u|^2 per column): every workgroup forms the same sums
-// in the same order and returns the same code; the recording workgroup
+// The stopping test of a PSD solve (Sec. 3.3) after `iter` iterations, from
+// the column partial sums (sum |d|^2, sum |u_{s+1}|^2 per column): every
+// workgroup of the next pass forms the same sums in the same order and gets
+// the same done code (returned in all threads); the recording workgroup
 // (rec) writes the ratio, the count and the code into the control block.
 // NMAX bounds ncol at compile time (0: none).  done (nullable): the solve's
 // stop flag; when it is already set the test is not taken, nothing is
